@@ -1,0 +1,384 @@
+"""Pins of the CPU oracle against what the paper prints and what the
+mathematics fixes.  No expected value here comes from the HIP path.
+
+Each pin is written as a function returning the list of failures, so that
+``test_pins_catch_planted_mistakes`` can plant plausible mistakes in a copy
+of the oracle (on the CPU) and show that some pin fails for each of them.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import codec, metrics
+from oracle import transform as tf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ----------------------------------------------------------------------------
+# Pins written as functions of an oracle-like namespace.
+
+def pin_orthogonality(T):
+    """Section 2: T T^T is diagonal and its diagonal is the printed 1/S^2."""
+    bad = []
+    g = T @ T.T
+    if np.count_nonzero(g - np.diag(np.diag(g))):
+        bad.append("T T^T not diagonal")
+    want = np.array(_golden("s_diag.json")["inv_sqrt_of"])
+    if not np.array_equal(np.diag(g), want):
+        bad.append("diag(T T^T) != printed S^-2")
+    return bad
+
+
+def pin_table2(T, C):
+    """Table 2: d2, epsilon, MSE, Cg, eta of S T and of the exact DCT at the
+    printed number of decimals."""
+    bad = []
+    n = np.diag(T @ T.T).astype(np.float64)
+    ch = (1.0 / np.sqrt(n))[:, None] * T.astype(np.float64)
+    rows = _golden("table2.json")["rows"]
+    for name, mat in (("Proposed", ch), ("DCT", C)):
+        got = metrics.table2_row(C, mat)
+        for k, txt in rows[name].items():
+            dec = len(txt.split(".")[1]) if "." in txt else 0
+            if abs(got[k] - float(txt)) > 0.5 * 10.0 ** (-dec) + 1e-12:
+                bad.append(f"{name}.{k}: {got[k]} vs printed {txt}")
+    return bad
+
+
+def pin_forward_bruteforce(forward, seed=3, nblk=4):
+    """Z[u,v] = sum_a sum_b T[u,a] A[a,b] T[v,b], with T taken from the
+    factorisation's product (independent of the literal) and the sums
+    written out as Python loops."""
+    P = np.eye(16, dtype=np.int64)
+    for f in tf.factors():
+        P = f @ P
+    rng = np.random.default_rng(seed)
+    blocks = rng.integers(-300, 300, size=(nblk, 16, 16))
+    got = forward(blocks)
+    bad = []
+    for k in range(nblk):
+        A = blocks[k].tolist()
+        for u in range(16):
+            for v in range(16):
+                s = 0
+                for a in range(16):
+                    for b in range(16):
+                        s += int(P[u, a]) * A[a][b] * int(P[v, b])
+                if s != int(got[k, u, v]):
+                    bad.append((k, u, v))
+    return bad
+
+
+def pin_inverse_identity(inverse_num, forward):
+    """Orthogonality of C_hat: with nothing discarded the round trip
+    reconstructs the block exactly (numerator = 2304 * A)."""
+    rng = np.random.default_rng(11)
+    a = rng.integers(0, 256, size=(32, 16, 16))
+    num = inverse_num(forward(a))
+    return [] if np.array_equal(num, 2304 * a) else ["round trip numerator != 2304 A"]
+
+
+# ----------------------------------------------------------------------------
+# Matrix facts.
+
+def test_T_orthogonality_and_S():
+    assert pin_orthogonality(tf.T) == []
+    ch = tf.c_hat()
+    assert np.max(np.abs(ch @ ch.T - np.eye(16))) < 1e-15
+    assert np.max(np.abs(ch.T @ ch - np.eye(16))) < 1e-15
+    # T^T T itself is not diagonal: only the scaled matrix is orthogonal.
+    g = tf.T.T @ tf.T
+    assert np.count_nonzero(g - np.diag(np.diag(g))) > 0
+
+
+def test_T_entries_and_symmetry():
+    assert set(np.unique(tf.T).tolist()) == {-1, 0, 1}
+    # Only row 0 has a non-zero sum: a flat block has only a DC coefficient.
+    assert tf.T.sum(axis=1).tolist() == [16] + [0] * 15
+    # Even rows are symmetric, odd rows antisymmetric, like the DCT's.
+    for i in range(16):
+        r = tf.T[i]
+        assert np.array_equal(r[::-1], r if i % 2 == 0 else -r)
+
+
+def test_factorisation_product_is_T():
+    P = np.eye(16, dtype=np.int64)
+    for f in tf.factors():
+        P = f @ P
+    assert np.array_equal(P, tf.T)
+
+
+def test_p2_reading():
+    # The printed cycles repeat their first element; the chosen reading
+    # maps a -> b within each cycle.  The opposite direction fails.
+    sig = tf.p2_sigma()
+    assert sig.tolist() == [0, 8, 4, 11, 3, 9, 5, 12, 1, 13, 7, 10, 2, 14, 6, 15]
+    rev = [list(reversed(c)) for c in tf.P2_CYCLES]
+    fs = tf.factors()
+    fs[-1] = tf.factor_P2(rev)
+    P = np.eye(16, dtype=np.int64)
+    for f in fs:
+        P = f @ P
+    assert not np.array_equal(P, tf.T)
+
+
+def test_addition_count_table1():
+    want = _golden("table1.json")["proposed"]
+    per = [tf.additions(f) for f in tf.factors()]
+    assert per == [16, 0, 16, 24, 4, 0]
+    assert sum(per) == want["additions"] == 60
+    # No factor multiplies: all entries are in {0, +1, -1}.
+    for f in tf.factors():
+        assert set(np.unique(f).tolist()) <= {-1, 0, 1}
+    # Every row of every factor has a +1 (no negation-only output).
+    for f in tf.factors():
+        assert np.all((f == 1).any(axis=1))
+    # The transposed factorisation (inverse transform) also costs 60.
+    assert sum(tf.additions(f.T) for f in tf.factors()) == 60
+
+
+def test_table2_reproduces():
+    assert pin_table2(tf.T, tf.dct_matrix()) == []
+
+
+def test_table2_wht_row():
+    # Third, independent matrix for the measures: the Walsh-Hadamard
+    # transform in natural (Sylvester) order, scaled to be orthonormal.
+    from scipy.linalg import hadamard
+    h = hadamard(16) / 4.0
+    got = metrics.table2_row(tf.dct_matrix(), h)
+    for k, txt in _golden("table2.json")["rows"]["WHT"].items():
+        dec = len(txt.split(".")[1])
+        assert abs(got[k] - float(txt)) <= 0.5 * 10.0 ** (-dec) + 1e-12, k
+
+
+def test_dct_matrix_against_library():
+    from scipy.fft import dct
+    c = tf.dct_matrix()
+    lib = dct(np.eye(16), type=2, norm="ortho", axis=0)
+    assert np.max(np.abs(c - lib)) < 1e-14
+    assert np.max(np.abs(c @ c.T - np.eye(16))) < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# Blockwise transform.
+
+def test_forward_bruteforce():
+    assert pin_forward_bruteforce(tf.forward_int) == []
+
+
+def test_forward_unit_blocks_and_constant():
+    # A block with a single 1 at (a, b) gives the outer product T[:, a] T[:, b]^T.
+    for a, b in [(0, 0), (3, 11), (15, 7)]:
+        e = np.zeros((1, 16, 16), dtype=np.int64)
+        e[0, a, b] = 1
+        assert np.array_equal(tf.forward_int(e)[0], np.outer(tf.T[:, a], tf.T[:, b]))
+    for c in (0, 1, 128, 255):
+        z = tf.forward_int(np.full((1, 16, 16), c))[0]
+        want = np.zeros((16, 16), dtype=np.int64)
+        want[0, 0] = 256 * c
+        assert np.array_equal(z, want)
+
+
+def test_forward_extreme_ranges():
+    # uint8 blocks reach DC 65280 and AC +-32640; centred int8 fits int16.
+    t = tf.T
+    hi = np.where(np.outer(t[1], t[1]) > 0, 255, 0)
+    lo = np.where(np.outer(t[1], t[1]) > 0, 0, 255)
+    z = tf.forward_int(np.stack([np.full((16, 16), 255), hi, lo]))
+    assert z[0, 0, 0] == 65280
+    assert z[1, 1, 1] == 32640 and z[2, 1, 1] == -32640
+    zc = tf.forward_int(np.stack([hi - 128, lo - 128]))
+    assert zc.max() <= 32767 and zc.min() >= -32768
+    # Uncentred minus centred is 32768 at DC only.
+    d = tf.forward_int(hi[None]) - tf.forward_int((hi - 128)[None])
+    want = np.zeros((16, 16), dtype=np.int64)
+    want[0, 0] = 32768
+    assert np.array_equal(d[0], want)
+
+
+def test_scaled_coefficients_are_orthonormal():
+    rng = np.random.default_rng(5)
+    a = rng.integers(0, 256, size=(16, 16, 16))
+    b = tf.scale(tf.forward_int(a))
+    assert np.max(np.abs(b - tf.forward_real(a))) < 1e-9
+    # Parseval: an orthogonal transform keeps the energy of every block.
+    assert np.allclose(np.sum(b * b, axis=(1, 2)), np.sum(a.astype(float) ** 2, axis=(1, 2)), rtol=1e-13)
+
+
+def test_inverse_integer_form_equals_paper_form():
+    assert pin_inverse_identity(tf.inverse_int_numerator, tf.forward_int) == []
+    rng = np.random.default_rng(7)
+    a = rng.integers(0, 256, size=(64, 16, 16))
+    z = tf.forward_int(a)
+    for keep in (codec.mask_zonal(2), codec.mask_zonal(8), codec.mask_zigzag(16), codec.mask_zigzag(100)):
+        zk = np.where(keep[None], z, 0)
+        exact = tf.inverse_int_numerator(zk) / 2304.0
+        paper = tf.inverse_real(tf.scale(zk))
+        assert np.max(np.abs(exact - paper)) < 1e-9
+
+
+def test_inverse_numerator_range_int32():
+    # Worst case over the +-1 sign patterns of T rows for the zonal masks:
+    # the exact numerator stays far inside int32.
+    w = tf.inverse_weights()
+    for r in (1, 2, 4, 6, 8, 16):
+        keep = codec.mask_zonal(r)
+        # |N_ij| <= sum_uv |T[u,i] w_u w_v T[v,j]| * max|Z_uv| with |Z| <= 65280
+        bound = np.abs(tf.T.T) @ (np.outer(w, w) * keep) @ np.abs(tf.T) * 65280
+        assert bound.max() < 2**31
+
+
+def test_rounding_matches_exact_rationals():
+    nums = np.arange(-20000, 700000, 97, dtype=np.int64)
+    got = codec.int_recon_u8(nums)
+    for n, g in zip(nums.tolist(), got.tolist()):
+        v = math.floor(Fraction(n, 2304) + Fraction(1, 2))
+        assert g == min(255, max(0, v))
+
+
+# ----------------------------------------------------------------------------
+# Retention masks and the zig-zag scan.
+
+def test_zigzag_scan():
+    order = codec.zigzag_order()
+    assert len(order) == 256 and len(set(order)) == 256
+    assert order[:10] == [(0, 0), (0, 1), (1, 0), (2, 0), (1, 1), (0, 2), (0, 3), (1, 2), (2, 1), (3, 0)]
+    assert order[-1] == (15, 15)
+    for (u0, v0), (u1, v1) in zip(order, order[1:]):
+        d0, d1 = u0 + v0, u1 + v1
+        assert d1 in (d0, d0 + 1)
+        if d1 == d0:  # within a diagonal, one step along it
+            assert abs(u1 - u0) == 1 and abs(v1 - v0) == 1
+    for r in (1, 16, 50, 256):
+        assert codec.mask_zigzag(r).sum() == r
+    # The 16th coefficient opens diagonal 5 at (0, 5).
+    assert codec.mask_zigzag(16)[0, 5] and not codec.mask_zigzag(16)[5, 0]
+    assert codec.mask_zonal(4).sum() == 16 and codec.mask_zonal(16).all()
+
+
+# ----------------------------------------------------------------------------
+# Uniform quantiser.
+
+def test_uniform_multipliers_closed_forms():
+    m = codec.uniform_multipliers(1)
+    n = tf.row_norms()
+    for u in range(16):
+        for v in range(16):
+            nn = int(n[u] * n[v])
+            if nn == 256:
+                assert m[u, v] == np.float32(1 / 16)
+            elif nn == 64:
+                assert m[u, v] == np.float32(1 / 8)
+            elif nn == 144:
+                assert m[u, v] == np.float32(1 / 12)
+    for q, k in ((8, 3), (16, 4), (32, 5)):
+        assert np.array_equal(codec.uniform_multipliers(q), m / np.float32(2 ** k))
+
+
+def test_uniform_levels_against_ideal():
+    rng = np.random.default_rng(9)
+    a = rng.integers(-255, 256, size=(500, 16, 16))
+    z = tf.forward_int(a)
+    for q in (1, 8, 16, 32):
+        lv = codec.quantise_uniform(z, q)
+        ideal = codec.quantise_uniform_ideal(z, q)
+        diff = lv != ideal
+        # The float32 decision may differ from the float64 ideal only at an
+        # exact rounding tie of the real value (Z / (sqrt(n_u n_v) q) with a
+        # rational scale), where the two float evaluations break the tie
+        # differently.
+        y = tf.scale(z) / q
+        frac = np.abs(np.abs(y - np.floor(y)) - 0.5)
+        assert np.all(frac[diff] < 1e-9)
+        # Where s_u s_v is a power of two the decision is an exact division.
+        n = tf.row_norms()
+        exact = np.isin(np.outer(n, n), (64, 256))
+        want = np.rint(z[:, exact] / (np.sqrt(np.outer(n, n))[exact] * q))
+        assert np.array_equal(lv[:, exact], want)
+
+
+# ----------------------------------------------------------------------------
+# Quality measures.
+
+def test_psnr_closed_forms():
+    a = np.full((48, 32), 100, dtype=np.uint8)
+    assert codec.psnr(a, a) == math.inf
+    b = a + 1
+    assert abs(codec.psnr(a, b) - 20 * math.log10(255)) < 1e-12
+    c = a.astype(np.int16) - 10
+    assert abs(codec.psnr(a, c) - (20 * math.log10(255) - 20)) < 1e-12
+    assert codec.sse(a, c) == 100 * a.size
+
+
+def test_ssim_closed_forms():
+    rng = np.random.default_rng(1)
+    x = rng.integers(0, 256, size=(40, 40)).astype(np.uint8)
+    assert abs(codec.ssim(x, x) - 1.0) < 1e-12
+    a, b = 100.0, 140.0
+    c1 = (0.01 * 255) ** 2
+    s = codec.ssim(np.full((20, 20), a), np.full((20, 20), b))
+    assert abs(s - (2 * a * b + c1) / (a * a + b * b + c1)) < 1e-12
+
+
+def test_blocking_round_trip_and_edge_extension():
+    rng = np.random.default_rng(2)
+    img = rng.integers(0, 256, size=(37, 50)).astype(np.uint8)
+    blk = codec.image_to_blocks(img)
+    assert blk.shape == (3 * 4, 16, 16)
+    assert np.array_equal(codec.blocks_to_image(blk, 37, 50), img)
+    # Padding repeats the last row/column.
+    full = codec.blocks_to_image(blk, 48, 64)
+    assert np.array_equal(full[37:, :50], np.repeat(img[-1:, :], 11, axis=0))
+    assert np.array_equal(full[:37, 50:], np.repeat(img[:, -1:], 14, axis=1))
+
+
+def test_lossless_and_zonal_experiment():
+    from synth import ar1_image
+    img = ar1_image(0x16060556 + 1, 128, 96)
+    rec, s, p = codec.compress_kept(img, codec.mask_zonal(16))
+    assert s == 0 and p == math.inf and np.array_equal(rec, img)
+    ps = [codec.compress_kept(img, codec.mask_zonal(r))[2] for r in (2, 4, 8)]
+    assert ps[0] < ps[1] < ps[2]
+    # Energy compaction: keeping more coefficients never hurts on this image,
+    # and the exact DCT compacts better than the approximation at r = 4.
+    _, pd = codec.compress_dct_kept(img, codec.mask_zonal(4))
+    assert pd > ps[1]
+
+
+# ----------------------------------------------------------------------------
+# Planted mistakes: each plausible error in the oracle trips some pin.
+
+def _mutants():
+    t_sign = tf.T.copy()
+    t_sign[6, 3] *= -1
+    t_swap = tf.T.copy()
+    t_swap[[4, 5]] = t_swap[[5, 4]]
+    yield "sign flip in T", t_sign, tf.forward_int, tf.inverse_int_numerator
+    yield "two rows of T swapped", t_swap, tf.forward_int, tf.inverse_int_numerator
+    yield "transposed operand in forward", tf.T, (lambda a: tf.T @ np.swapaxes(np.asarray(a, np.int64), 1, 2) @ tf.T.T), tf.inverse_int_numerator
+    yield "dropped T^T in forward", tf.T, (lambda a: tf.T @ np.asarray(a, np.int64)), tf.inverse_int_numerator
+    w = tf.inverse_weights()
+    yield "weights applied once", tf.T, tf.forward_int, (lambda z: tf.T.T @ (w[:, None] * np.asarray(z, np.int64)) @ tf.T * 48)
+
+
+@pytest.mark.parametrize("name,T,fwd,inv", list(_mutants()), ids=[m[0] for m in _mutants()])
+def test_pins_catch_planted_mistakes(name, T, fwd, inv):
+    failures = (pin_orthogonality(T) + pin_table2(T, tf.dct_matrix())
+                + pin_forward_bruteforce(fwd, nblk=1) + pin_inverse_identity(inv, fwd))
+    assert failures, f"planted mistake '{name}' went undetected"
+
+
+def test_oracle_header_declares_test_infrastructure():
+    assert "TEST INFRASTRUCTURE ONLY" in oracle.__doc__
