@@ -1,0 +1,214 @@
+/*
+ * adct16.h - C ABI of the MI355X (gfx950) library for the orthogonal 16-point
+ * approximate DCT of da Silveira, Cintra, Bayer, Coelho, Kulasekera,
+ * Madanayake and Rajapaksha ("An Orthogonal 16-point Approximate DCT for
+ * Image and Video Compression").
+ *
+ * The method (Section 2): T is a 16x16 matrix with entries in {0, +1, -1};
+ * T T^T = diag(n) is diagonal, S = diag(1/sqrt(n)) and C_hat = S T is
+ * orthogonal.  Eq. (1) factors T into sparse stages costing 60 additions per
+ * 16-point transform (Table 1).  Images are cut into disjoint 16x16 blocks
+ * and each block A is transformed as B = C_hat A C_hat^T; coefficients are
+ * retained or quantised and the block is rebuilt as A' = C_hat^T B' C_hat;
+ * quality is measured by PSNR (Section 4).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All functions have C linkage, never throw and return an adct16_status.
+ *   adct16_last_error_string() gives a thread-local description of the last
+ *   failure of the calling thread.
+ * - Device pointers are plain HIP device addresses owned by the caller.  The
+ *   library never frees or retains them beyond the call (a graph keeps the
+ *   pointers it was created with, see adct16_graph_create).
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *   is enqueued asynchronously; errors the host can detect are returned
+ *   before anything is enqueued, and a failed launch returns
+ *   ADCT16_E_LAUNCH.  No compute call allocates memory.
+ * - Images of a batch live in one packed device buffer.  Image k has
+ *   height[k] x width[k] pixels; its row y starts at element
+ *   offset[k] + y * pitch[k].  Requirements: pitch >= width rounded up to
+ *   a multiple of 16; offset*esize and pitch*esize multiples of 16 bytes;
+ *   the buffer base 16-byte aligned.  Reconstructions use the same
+ *   offsets and pitches as the input (in elements of their own type).
+ * - Blocks are numbered in raster order per image; images follow each other.
+ *   Coefficient buffers are block-major: block b occupies 256 consecutive
+ *   elements, element u*16+v holding coefficient (u, v), u the vertical and
+ *   v the horizontal frequency: Z[u][v] = sum_ab T[u][a] A[a][b] T[v][b].
+ *   Image k's first block is the sum of the block counts of images < k.
+ * - Sizes that are not multiples of 16 are extended by repeating the last
+ *   row / column before the transform; reconstructions are written and PSNR
+ *   is measured on the true pixels only.
+ */
+#ifndef ADCT16_H
+#define ADCT16_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum adct16_status {
+  ADCT16_OK = 0,
+  ADCT16_E_NULL = 1,     /* a required pointer argument is NULL */
+  ADCT16_E_SHAPE = 2,    /* non-positive size, pitch too small, batch too large */
+  ADCT16_E_DTYPE = 3,    /* unsupported dtype or dtype combination */
+  ADCT16_E_MODE = 4,     /* r, q, qmode, backend or precision out of range */
+  ADCT16_E_ALIGN = 5,    /* pointer, offset or pitch not 16-byte aligned */
+  ADCT16_E_NOMEM = 6,    /* plan-time device or host allocation failed */
+  ADCT16_E_DEVICE = 7,   /* no device, or the current device is not gfx950 */
+  ADCT16_E_LAUNCH = 8,   /* a kernel launch or graph operation failed */
+  ADCT16_E_STATE = 9     /* the call does not apply to this plan */
+} adct16_status;
+
+typedef enum adct16_dtype {
+  ADCT16_U8 = 1,    /* uint8 pixels 0..255 */
+  ADCT16_I16 = 2,   /* int16 (residual samples, centred coefficients, levels) */
+  ADCT16_I32 = 3,   /* int32 coefficients or levels */
+  ADCT16_F32 = 4,   /* float32 scaled coefficients / unrounded reconstruction */
+  ADCT16_BF16 = 5,  /* operand precision of the exact DCT-II comparison */
+  ADCT16_F16 = 6
+} adct16_dtype;
+
+typedef enum adct16_qmode {
+  ADCT16_Q_NONE = 0,     /* keep every coefficient (lossless round trip) */
+  ADCT16_Q_ZONAL = 1,    /* keep the top-left r x r coefficients, 1 <= r <= 16 */
+  ADCT16_Q_ZIGZAG = 2,   /* keep the first r coefficients of the zig-zag scan, 1 <= r <= 256 (Section 4) */
+  ADCT16_Q_UNIFORM = 3   /* uniform step q >= 1 with S folded into one float32 multiplier */
+} adct16_qmode;
+
+typedef enum adct16_backend {
+  ADCT16_BACKEND_AUTO = 0,  /* autotuned (flag ADCT16_FLAG_AUTOTUNE) or the built-in default */
+  ADCT16_BACKEND_VALU = 1,  /* 60-addition butterflies of Eq. (1) on the vector ALUs */
+  ADCT16_BACKEND_MFMA = 2   /* T as a dense {0,+1,-1} int8 contraction on the matrix cores */
+} adct16_backend;
+
+enum {
+  ADCT16_FLAG_AUTOTUNE = 1  /* time the candidate kernels at plan creation */
+};
+
+/*
+ * Batch descriptor, read by adct16_plan_create (arrays are copied).
+ *
+ * in_dtype    ADCT16_U8 (8-bit images, Section 4) or ADCT16_I16 (prediction
+ *             residuals, Section 5.3).  The MFMA backend needs U8 or, for
+ *             I16, samples in [-255, 255]; the VALU backend takes any int16.
+ * coef_dtype  output of adct16_forward:
+ *               ADCT16_I32  Z = T A T^T exactly;
+ *               ADCT16_I16  (U8 input only) Z of the centred block A - 128,
+ *                           i.e. Z with 32768 subtracted at (0,0); fits int16;
+ *               ADCT16_F32  B = S Z S, the orthonormal coefficients, as
+ *                           fl32(Z) * fl32(1/sqrt(n_u n_v)).
+ * qmode, r, q retention / quantiser used by adct16_quantise, adct16_inverse
+ *             (uniform only) and the fused calls.
+ * qcoef_dtype output of adct16_quantise (input of adct16_inverse):
+ *               mask modes: same as coef_dtype (I32 or I16), kept values
+ *                           unchanged, the rest zero;
+ *               uniform:    levels L_uv = round_half_even(fl32(fl32(Z_uv) *
+ *                           M_uv)), M_uv = fl32(1/(sqrt(n_u n_v) q)), stored
+ *                           as ADCT16_I16 (saturated) or ADCT16_I32.
+ * out_dtype   reconstruction: ADCT16_U8 (rounded half up, clamped 0..255),
+ *             ADCT16_I16 (rounded half up, saturated) or ADCT16_F32 (the
+ *             unrounded A').  U8 needs U8 input.
+ */
+typedef struct adct16_desc {
+  int32_t n_images;
+  const int32_t *height;
+  const int32_t *width;
+  const int32_t *pitch;
+  const int64_t *offset;
+  int32_t in_dtype;
+  int32_t coef_dtype;
+  int32_t qcoef_dtype;
+  int32_t out_dtype;
+  int32_t qmode;
+  int32_t r;
+  int32_t q;
+  int32_t backend;
+  int32_t flags;
+} adct16_desc;
+
+typedef struct adct16_plan_s *adct16_plan;
+typedef struct adct16_graph_s *adct16_graph;
+
+/* Validate `desc`, upload the image table and constant tables to the
+ * current device and choose kernels.  Allocates device memory (the only
+ * call besides adct16_graph_create that does).  On error *out is NULL. */
+adct16_status adct16_plan_create(const adct16_desc *desc, adct16_plan *out);
+adct16_status adct16_plan_destroy(adct16_plan plan);
+
+/* Number of 16x16 blocks of the batch; coefficient buffers hold 256 times
+ * this many elements. */
+adct16_status adct16_plan_num_blocks(adct16_plan plan, int64_t *num_blocks);
+
+/* NUL-terminated JSON describing the chosen kernels (backend, launch shape). */
+adct16_status adct16_plan_info(adct16_plan plan, char *buf, int32_t buf_len);
+
+/* Section 4, forward: d_in (in_dtype) -> d_coef (coef_dtype, block-major).
+ * Evaluates T by the 60-addition factorisation of Eq. (1) (VALU backend)
+ * or as an exact int8 contraction (MFMA backend); results are identical. */
+adct16_status adct16_forward(adct16_plan plan, const void *d_in, void *d_coef, void *stream);
+
+/* Section 4, retention (mask modes) or the uniform quantiser (Section 2: S
+ * absorbed into the quantisation step).  d_coef must be I32 or I16
+ * coefficients as written by adct16_forward; d_qcoef is qcoef_dtype.
+ * d_qcoef may equal d_coef when the dtypes are equal. */
+adct16_status adct16_quantise(adct16_plan plan, const void *d_coef, void *d_qcoef, void *stream);
+
+/* Section 4, inverse A' = C_hat^T B' C_hat of every block, reassembled into
+ * d_out (out_dtype, same layout as the input batch).
+ * Mask modes: d_qcoef holds integer coefficients Z' (coef dtype I32 or
+ * I16-centred); A' = T^T (w w^T .* Z') T / 2304 with w = 48/n, evaluated
+ * exactly in int32.  Uniform: d_qcoef holds levels L; B' = q L and A' is
+ * evaluated in float64. */
+adct16_status adct16_inverse(adct16_plan plan, const void *d_qcoef, void *d_out, void *stream);
+
+/* Section 4, quality: per-image SSE over the true pixels and
+ * PSNR = 10 log10(255^2 h w / SSE) (+inf when SSE = 0).  d_a is in_dtype,
+ * d_b is out_dtype (U8 or I16).  d_sse: n_images int64 (overwritten);
+ * d_psnr: n_images doubles, may be NULL. */
+adct16_status adct16_measure(adct16_plan plan, const void *d_a, const void *d_b,
+                             int64_t *d_sse, double *d_psnr, void *stream);
+
+/* Forward -> retention/quantiser -> inverse -> SSE/PSNR fused in one pass
+ * over the batch (one persistent kernel plus a finalisation kernel).
+ * d_out (out_dtype U8/I16) and d_qcoef (qcoef_dtype) are optional (NULL =
+ * not written); d_sse may be NULL (plan workspace), d_psnr may be NULL. */
+adct16_status adct16_compress_and_measure(adct16_plan plan, const void *d_in, void *d_out,
+                                          void *d_qcoef, int64_t *d_sse, double *d_psnr,
+                                          void *stream);
+
+/* Comparison transform (Section 3): exact orthonormal DCT-II of every block,
+ * Y = C X C^T, on the BF16 or F16 matrix cores with float32 accumulation.
+ * X is the block centred to [-128, 127] for U8 input, the raw samples for
+ * I16 input (|x| <= 255 is exact in both operand types); C is rounded to
+ * the operand type.  d_y: float32, block-major.  Its error against the
+ * float64 DCT is a property of the operand precision, not a bug. */
+adct16_status adct16_dct_forward(adct16_plan plan, const void *d_in, float *d_y,
+                                 int32_t precision, void *stream);
+
+/* Section 2/3: the 16-point 1-D transform y = T x of n vectors (Fig. 4's
+ * datapath).  d_x, d_y: n x 16 int32, row-major, 16-byte aligned.
+ * Plan-free.  n = 0 is a no-op (pointers may then be NULL); n < 0 is
+ * ADCT16_E_SHAPE. */
+adct16_status adct16_forward_1d(const int32_t *d_x, int32_t *d_y, int64_t n, void *stream);
+/* y = T^T x, the 1-D inverse up to the factor diag(n) (T^T T x / n-weights
+ * recover x: x = T^T diag(1/n) T x). */
+adct16_status adct16_inverse_1d(const int32_t *d_x, int32_t *d_y, int64_t n, void *stream);
+
+/* Capture adct16_compress_and_measure with fixed pointers into a HIP graph
+ * (created with a private capture stream; allocates).  Launching the graph
+ * repeats exactly that call on `stream`. */
+adct16_status adct16_graph_create(adct16_plan plan, const void *d_in, void *d_out, void *d_qcoef,
+                                  int64_t *d_sse, double *d_psnr, adct16_graph *out);
+adct16_status adct16_graph_launch(adct16_graph graph, void *stream);
+adct16_status adct16_graph_destroy(adct16_graph graph);
+
+const char *adct16_status_string(adct16_status status);
+const char *adct16_last_error_string(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADCT16_H */

@@ -1,0 +1,78 @@
+// Internal definitions shared by the host API and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adct16.h"
+
+namespace adct16 {
+
+// A strip is the unit of work of one wavefront: 16 image rows by 8 blocks
+// (128 columns) of one image.  Images are covered by whole strips; the last
+// strip of a block row may hold fewer than 8 blocks.
+constexpr int kStripBlocks = 8;
+constexpr int kWavesPerGroup = 4;
+constexpr int kGroupThreads = 64 * kWavesPerGroup;
+
+struct ImageDesc {
+  int64_t offset;       // element offset of row 0 in the packed image buffer
+  int64_t block_begin;  // index of the image's first block in coefficient buffers
+  int64_t strip_begin;  // index of the image's first strip
+  int32_t h, w, pitch;  // true size and row pitch (elements)
+  int32_t bx, by;       // blocks across / down
+  int32_t sx;           // strips across = ceil(bx / 8)
+  int32_t pad[2];
+};
+static_assert(sizeof(ImageDesc) == 56, "ImageDesc layout");
+
+// Per-plan constant tables, indexed u * 16 + v.
+struct Tables {
+  int32_t wkeep[256];  // w_u w_v keep(u, v): inverse weights with the retention mask
+  int32_t wall[256];   // w_u w_v: inverse weights (w = 48 / n)
+  float qmul[256];     // M_uv = fl32(1 / (sqrt(n_u n_v) q))
+  float yscale[256];   // K_uv = fl32(1 / sqrt(n_u n_v))
+  double deqc[16];     // q s_v, per horizontal frequency v
+};
+
+enum InKind { IN_U8 = 0, IN_I16 = 1 };
+enum CoefKind { CF_I32 = 0, CF_I16C = 1, CF_F32 = 2, CF_L16 = 3, CF_L32 = 4, CF_NONE = 5 };
+enum OutKind { OUT_NONE = 0, OUT_U8 = 1, OUT_I16 = 2, OUT_F32 = 3 };
+enum ModeKind { MODE_MASK = 0, MODE_UNIFORM = 1 };
+
+struct Params {
+  const ImageDesc* images;
+  int32_t n_images;
+  int32_t pad0;
+  int64_t n_strips;
+  int64_t n_blocks;
+  const Tables* tables;
+  const void* in;
+  const void* in2;      // second image batch (measure)
+  void* out;
+  void* coef;
+  void* qcoef;
+  unsigned long long* sse;
+  double* psnr;
+};
+
+// Launchers (return hipSuccess or the launch error).  `grid` is the number
+// of workgroups of kGroupThreads threads for the persistent strip kernels.
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+hipError_t launch_psnr_finalize(const Params& P, hipStream_t s);
+hipError_t launch_valu_forward(int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s);
+hipError_t launch_valu_fused(int in_kind, int mode, int qout_kind, int out_kind, const Params& P,
+                             int grid, hipStream_t s);
+hipError_t launch_valu_inverse(int coef_kind, int mode, int out_kind, const Params& P, int grid,
+                               hipStream_t s);
+hipError_t launch_quantise(int coef_kind, int mode, int qout_kind, const Params& P, hipStream_t s);
+hipError_t launch_measure(int in_kind, int out_kind, const Params& P, int grid, hipStream_t s);
+hipError_t launch_1d(bool inverse, const int32_t* x, int32_t* y, int64_t n, hipStream_t s);
+
+hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStream_t s);
+hipError_t launch_mfma_fused(int mode, int qout_kind, int out_kind, const Params& P, int grid,
+                             hipStream_t s);
+hipError_t launch_dct_mfma(int in_kind, int precision, const Params& P, float* y, int grid,
+                           hipStream_t s);
+
+}  // namespace adct16

@@ -1,0 +1,563 @@
+// C ABI: plan creation and validation, dispatch to the kernels, HIP graphs,
+// kernel-choice autotuning and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "adct16_internal.hpp"
+
+using namespace adct16;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+adct16_status fail(adct16_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+adct16_status hip_fail(hipError_t e, const char* what) {
+  return fail(ADCT16_E_LAUNCH, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Section 2: n_i = (T T^T)_ii, the squared row norms of T; S = diag(1/sqrt(n)).
+constexpr int kNorm[16] = {16, 16, 12, 8, 8, 16, 12, 12, 16, 12, 12, 8, 8, 12, 12, 12};
+
+// Section 4: 16x16 zig-zag scan, anti-diagonal by anti-diagonal starting
+// (0,0), (0,1), (1,0), ...; rank[u*16+v] = scan position.
+void zigzag_rank(int (&rank)[256]) {
+  int u = 0, v = 0;
+  for (int k = 0; k < 256; ++k) {
+    rank[u * 16 + v] = k;
+    if ((u + v) % 2 == 0) {  // moving up-right
+      if (v == 15) ++u;
+      else if (u == 0) ++v;
+      else { --u; ++v; }
+    } else {                 // moving down-left
+      if (u == 15) ++v;
+      else if (v == 0) ++u;
+      else { ++u; --v; }
+    }
+  }
+}
+
+bool is_int_dtype_for_in(int dt) { return dt == ADCT16_U8 || dt == ADCT16_I16; }
+
+int esize(int dt) {
+  switch (dt) {
+    case ADCT16_U8: return 1;
+    case ADCT16_I16: return 2;
+    default: return 4;
+  }
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+struct adct16_plan_s {
+  adct16_desc d{};
+  std::vector<ImageDesc> images;
+  int device = 0;
+  int cu_count = 0;
+  int in_kind = IN_U8, coef_kind = CF_I32, qcoef_kind = CF_I32, out_kind = OUT_U8, mode = MODE_MASK;
+  int64_t n_blocks = 0, n_strips = 0;
+  ImageDesc* d_images = nullptr;
+  Tables* d_tables = nullptr;
+  unsigned long long* d_sse_ws = nullptr;
+  int grid = 0;           // persistent workgroups for the strip kernels
+  int backend = ADCT16_BACKEND_VALU;   // resolved backend of the fused/forward calls
+  std::string tuned;      // how the choice was made
+};
+
+struct adct16_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+Params base_params(const adct16_plan_s* p) {
+  Params P{};
+  P.images = p->d_images;
+  P.n_images = (int32_t)p->images.size();
+  P.n_strips = p->n_strips;
+  P.n_blocks = p->n_blocks;
+  P.tables = p->d_tables;
+  return P;
+}
+
+adct16_status check_plan(adct16_plan p) {
+  if (!p) return fail(ADCT16_E_NULL, "plan is NULL");
+  return ADCT16_OK;
+}
+
+adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void* d_in, void* d_out,
+                            void* d_qcoef, int64_t* d_sse, double* d_psnr, hipStream_t s) {
+  Params P = base_params(p);
+  P.in = d_in;
+  P.out = d_out;
+  P.qcoef = d_qcoef;
+  P.sse = d_sse ? reinterpret_cast<unsigned long long*>(d_sse) : p->d_sse_ws;
+  P.psnr = d_psnr;
+  hipError_t e = launch_zero_u64(P.sse, P.n_images, s);
+  if (e != hipSuccess) return hip_fail(e, "zero SSE");
+  const int qk = d_qcoef ? p->qcoef_kind : CF_NONE;
+  const int ok = d_out ? p->out_kind : OUT_NONE;
+  if (backend == ADCT16_BACKEND_MFMA)
+    e = launch_mfma_fused(p->mode, qk, ok, P, grid, s);
+  else
+    e = launch_valu_fused(p->in_kind, p->mode, qk, ok, P, grid, s);
+  if (e != hipSuccess) return hip_fail(e, "fused kernel");
+  if (d_psnr) {
+    e = launch_psnr_finalize(P, s);
+    if (e != hipSuccess) return hip_fail(e, "PSNR kernel");
+  }
+  return ADCT16_OK;
+}
+
+bool mfma_supported(const adct16_plan_s* p) {
+  (void)p;
+  return false;
+}
+
+// Autotuning: time the fused call for each candidate (backend, workgroups
+// per CU) on a scratch batch of the plan's own geometry, keep the fastest.
+// Results are cached per process and, if ADCT16_TUNE_CACHE names a file,
+// across processes (key: device arch, CU count, call shape).
+std::mutex g_tune_mu;
+
+std::string tune_key(const adct16_plan_s* p, const char* arch) {
+  std::ostringstream k;
+  k << arch << "/cu" << p->cu_count << "/in" << p->in_kind << "/m" << p->mode << "/o" << p->out_kind
+    << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips);
+  return k.str();
+}
+
+bool tune_cache_get(const std::string& key, int& backend, int& wgpc) {
+  const char* path = getenv("ADCT16_TUNE_CACHE");
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string k;
+  int b, w;
+  bool found = false;
+  while (f >> k >> b >> w)
+    if (k == key) { backend = b; wgpc = w; found = true; }
+  return found;
+}
+
+void tune_cache_put(const std::string& key, int backend, int wgpc) {
+  const char* path = getenv("ADCT16_TUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << backend << " " << wgpc << "\n";
+}
+
+adct16_status autotune(adct16_plan_s* p, const char* arch) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const std::string key = tune_key(p, arch);
+  int best_b = ADCT16_BACKEND_VALU, best_w = 2;
+  if (tune_cache_get(key, best_b, best_w)) {
+    p->backend = best_b;
+    p->grid = (int)std::min<int64_t>(p->cu_count * best_w, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup);
+    p->tuned = "cache";
+    return ADCT16_OK;
+  }
+  // Scratch input / output covering the packed batch extent.
+  int64_t in_elems = 0;
+  for (size_t i = 0; i < p->images.size(); ++i)
+    in_elems = std::max<int64_t>(in_elems, p->images[i].offset + (int64_t)p->images[i].h * p->images[i].pitch);
+  const int es = esize(p->d.in_dtype);
+  void *din = nullptr, *dout = nullptr;
+  if (hipMalloc(&din, in_elems * es + 64) != hipSuccess) return fail(ADCT16_E_NOMEM, "autotune scratch");
+  if (hipMalloc(&dout, in_elems * es + 64) != hipSuccess) { hipFree(din); return fail(ADCT16_E_NOMEM, "autotune scratch"); }
+  hipMemset(din, 0x5a, in_elems * es);
+  hipStream_t s;
+  hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  float best = 1e30f;
+  std::vector<int> backends = {ADCT16_BACKEND_VALU};
+  if (mfma_supported(p)) backends.push_back(ADCT16_BACKEND_MFMA);
+  const int cands[] = {1, 2, 3, 4, 6, 8};
+  adct16_status st = ADCT16_OK;
+  for (int b : backends) {
+    for (int w : cands) {
+      const int grid = (int)std::min<int64_t>(p->cu_count * w, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup);
+      st = compress_impl(p, b, grid, din, p->out_kind == OUT_F32 ? nullptr : dout, nullptr, nullptr, nullptr, s);
+      if (st != ADCT16_OK) break;
+      hipEventRecord(e0, s);
+      const int reps = 3;
+      for (int r = 0; r < reps; ++r) compress_impl(p, b, grid, din, p->out_kind == OUT_F32 ? nullptr : dout, nullptr, nullptr, nullptr, s);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; best_b = b; best_w = w; }
+    }
+    if (st != ADCT16_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamDestroy(s);
+  hipFree(din);
+  hipFree(dout);
+  if (st != ADCT16_OK) return st;
+  p->backend = best_b;
+  p->grid = (int)std::min<int64_t>(p->cu_count * best_w, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup);
+  std::ostringstream t;
+  t << "timed:" << best_w << "wg/cu";
+  p->tuned = t.str();
+  tune_cache_put(key, best_b, best_w);
+  return ADCT16_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* adct16_status_string(adct16_status st) {
+  switch (st) {
+    case ADCT16_OK: return "ok";
+    case ADCT16_E_NULL: return "null pointer";
+    case ADCT16_E_SHAPE: return "invalid shape";
+    case ADCT16_E_DTYPE: return "unsupported dtype";
+    case ADCT16_E_MODE: return "invalid mode or parameter";
+    case ADCT16_E_ALIGN: return "misaligned pointer, offset or pitch";
+    case ADCT16_E_NOMEM: return "out of memory";
+    case ADCT16_E_DEVICE: return "no usable gfx950 device";
+    case ADCT16_E_LAUNCH: return "kernel launch failed";
+    case ADCT16_E_STATE: return "call not valid for this plan";
+  }
+  return "unknown status";
+}
+
+const char* adct16_last_error_string(void) { return g_last_error.c_str(); }
+
+adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
+  if (!out) return fail(ADCT16_E_NULL, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(ADCT16_E_NULL, "desc is NULL");
+  if (d->n_images < 1 || d->n_images > (1 << 20))
+    return fail(ADCT16_E_SHAPE, "n_images = %d outside [1, 2^20]", d->n_images);
+  if (!d->height || !d->width || !d->pitch || !d->offset) return fail(ADCT16_E_NULL, "image arrays are NULL");
+  // dtypes
+  if (!is_int_dtype_for_in(d->in_dtype)) return fail(ADCT16_E_DTYPE, "in_dtype must be U8 or I16");
+  const bool in_u8 = d->in_dtype == ADCT16_U8;
+  if (!(d->coef_dtype == ADCT16_I32 || d->coef_dtype == ADCT16_F32 || (in_u8 && d->coef_dtype == ADCT16_I16)))
+    return fail(ADCT16_E_DTYPE, "coef_dtype must be I32, F32 or (U8 input) I16");
+  if (!(d->out_dtype == ADCT16_I16 || d->out_dtype == ADCT16_F32 || (in_u8 && d->out_dtype == ADCT16_U8)))
+    return fail(ADCT16_E_DTYPE, "out_dtype must be I16, F32 or (U8 input) U8");
+  if (d->qmode < ADCT16_Q_NONE || d->qmode > ADCT16_Q_UNIFORM) return fail(ADCT16_E_MODE, "qmode %d", d->qmode);
+  const bool uniform = d->qmode == ADCT16_Q_UNIFORM;
+  if (uniform) {
+    if (!(d->qcoef_dtype == ADCT16_I16 || d->qcoef_dtype == ADCT16_I32))
+      return fail(ADCT16_E_DTYPE, "uniform levels must be I16 or I32");
+    if (d->q < 1 || d->q > 65535) return fail(ADCT16_E_MODE, "q = %d outside [1, 65535]", d->q);
+  } else {
+    if (!(d->qcoef_dtype == ADCT16_I32 || (in_u8 && d->qcoef_dtype == ADCT16_I16)))
+      return fail(ADCT16_E_DTYPE, "retained coefficients must be I32 or (U8 input) I16");
+    if (d->qmode == ADCT16_Q_ZONAL && (d->r < 1 || d->r > 16)) return fail(ADCT16_E_MODE, "zonal r = %d outside [1, 16]", d->r);
+    if (d->qmode == ADCT16_Q_ZIGZAG && (d->r < 1 || d->r > 256)) return fail(ADCT16_E_MODE, "zig-zag r = %d outside [1, 256]", d->r);
+  }
+  if (d->backend < ADCT16_BACKEND_AUTO || d->backend > ADCT16_BACKEND_MFMA)
+    return fail(ADCT16_E_MODE, "backend %d", d->backend);
+  // geometry
+  const int es = esize(d->in_dtype);
+  std::vector<ImageDesc> images(d->n_images);
+  int64_t blocks = 0, strips = 0;
+  for (int i = 0; i < d->n_images; ++i) {
+    const int h = d->height[i], w = d->width[i], pt = d->pitch[i];
+    const int64_t off = d->offset[i];
+    if (h < 1 || w < 1 || h > 65536 || w > 65536) return fail(ADCT16_E_SHAPE, "image %d: size %dx%d", i, h, w);
+    const int w16 = (w + 15) / 16 * 16;
+    if (pt < w16) return fail(ADCT16_E_SHAPE, "image %d: pitch %d < width rounded up to 16 (%d)", i, pt, w16);
+    if (off < 0) return fail(ADCT16_E_SHAPE, "image %d: negative offset", i);
+    if (((int64_t)pt * es) % 16 || (off * es) % 16)
+      return fail(ADCT16_E_ALIGN, "image %d: pitch/offset not 16-byte aligned", i);
+    ImageDesc& g = images[i];
+    memset(&g, 0, sizeof g);
+    g.offset = off;
+    g.h = h; g.w = w; g.pitch = pt;
+    g.bx = (w + 15) / 16;
+    g.by = (h + 15) / 16;
+    g.sx = (g.bx + kStripBlocks - 1) / kStripBlocks;
+    g.block_begin = blocks;
+    g.strip_begin = strips;
+    blocks += (int64_t)g.bx * g.by;
+    strips += (int64_t)g.sx * g.by;
+  }
+  if (blocks > ((int64_t)1 << 36)) return fail(ADCT16_E_SHAPE, "batch too large");
+  // device
+  int dev = 0, ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(ADCT16_E_DEVICE, "no HIP device");
+  if (hipGetDevice(&dev) != hipSuccess) return fail(ADCT16_E_DEVICE, "hipGetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(ADCT16_E_DEVICE, "hipGetDeviceProperties failed");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(ADCT16_E_DEVICE, "device %d is %s, not gfx950", dev, prop.gcnArchName);
+
+  auto* p = new adct16_plan_s();
+  p->d = *d;
+  p->d.height = p->d.width = p->d.pitch = nullptr;
+  p->d.offset = nullptr;
+  p->images = images;
+  p->device = dev;
+  p->cu_count = prop.multiProcessorCount;
+  p->in_kind = in_u8 ? IN_U8 : IN_I16;
+  p->coef_kind = d->coef_dtype == ADCT16_I32 ? CF_I32 : d->coef_dtype == ADCT16_I16 ? CF_I16C : CF_F32;
+  if (uniform) p->qcoef_kind = d->qcoef_dtype == ADCT16_I16 ? CF_L16 : CF_L32;
+  else p->qcoef_kind = d->qcoef_dtype == ADCT16_I16 ? CF_I16C : CF_I32;
+  p->out_kind = d->out_dtype == ADCT16_U8 ? OUT_U8 : d->out_dtype == ADCT16_I16 ? OUT_I16 : OUT_F32;
+  p->mode = uniform ? MODE_UNIFORM : MODE_MASK;
+  p->n_blocks = blocks;
+  p->n_strips = strips;
+
+  // constant tables
+  Tables t;
+  memset(&t, 0, sizeof t);
+  int zz[256];
+  zigzag_rank(zz);
+  for (int u = 0; u < 16; ++u) {
+    for (int v = 0; v < 16; ++v) {
+      const int nn = kNorm[u] * kNorm[v];
+      const int wuv = (48 / kNorm[u]) * (48 / kNorm[v]);
+      bool keep = true;
+      if (d->qmode == ADCT16_Q_ZONAL) keep = u < d->r && v < d->r;
+      if (d->qmode == ADCT16_Q_ZIGZAG) keep = zz[u * 16 + v] < d->r;
+      t.wall[u * 16 + v] = wuv;
+      t.wkeep[u * 16 + v] = keep ? wuv : 0;
+      t.yscale[u * 16 + v] = (float)(1.0 / std::sqrt((double)nn));
+      t.qmul[u * 16 + v] = uniform ? (float)(1.0 / (std::sqrt((double)nn) * (double)d->q)) : 0.0f;
+    }
+    t.deqc[u] = uniform ? (double)d->q / std::sqrt((double)kNorm[u]) : 0.0;
+  }
+  bool ok = hipMalloc(&p->d_images, sizeof(ImageDesc) * images.size()) == hipSuccess &&
+            hipMalloc(&p->d_tables, sizeof(Tables)) == hipSuccess &&
+            hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size()) == hipSuccess;
+  ok = ok && hipMemcpy(p->d_images, images.data(), sizeof(ImageDesc) * images.size(), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p->d_tables, &t, sizeof t, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    adct16_plan_destroy(p);
+    return fail(ADCT16_E_NOMEM, "plan allocation failed");
+  }
+  // kernel choice
+  const int64_t max_groups = (strips + kWavesPerGroup - 1) / kWavesPerGroup;
+  p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(p->cu_count * 2, max_groups));
+  if (d->backend == ADCT16_BACKEND_MFMA) {
+    if (!mfma_supported(p)) {
+      adct16_plan_destroy(p);
+      return fail(ADCT16_E_MODE, "MFMA backend supports U8 input with retention modes");
+    }
+    p->backend = ADCT16_BACKEND_MFMA;
+    p->tuned = "requested";
+  } else if (d->backend == ADCT16_BACKEND_VALU) {
+    p->backend = ADCT16_BACKEND_VALU;
+    p->tuned = "requested";
+  } else if (d->flags & ADCT16_FLAG_AUTOTUNE) {
+    adct16_status st = autotune(p, prop.gcnArchName);
+    if (st != ADCT16_OK) {
+      adct16_plan_destroy(p);
+      return st;
+    }
+  } else {
+    p->backend = ADCT16_BACKEND_VALU;
+    p->tuned = "default";
+  }
+  *out = p;
+  return ADCT16_OK;
+}
+
+adct16_status adct16_plan_destroy(adct16_plan p) {
+  if (!p) return fail(ADCT16_E_NULL, "plan is NULL");
+  if (p->d_images) hipFree(p->d_images);
+  if (p->d_tables) hipFree(p->d_tables);
+  if (p->d_sse_ws) hipFree(p->d_sse_ws);
+  delete p;
+  return ADCT16_OK;
+}
+
+adct16_status adct16_plan_num_blocks(adct16_plan p, int64_t* n) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!n) return fail(ADCT16_E_NULL, "num_blocks is NULL");
+  *n = p->n_blocks;
+  return ADCT16_OK;
+}
+
+adct16_status adct16_plan_info(adct16_plan p, char* buf, int32_t len) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!buf || len < 1) return fail(ADCT16_E_NULL, "buffer is NULL");
+  std::ostringstream o;
+  o << "{\"backend\": \"" << (p->backend == ADCT16_BACKEND_MFMA ? "mfma" : "valu") << "\", \"grid\": " << p->grid
+    << ", \"threads\": " << kGroupThreads << ", \"strips\": " << p->n_strips << ", \"blocks\": " << p->n_blocks
+    << ", \"cus\": " << p->cu_count << ", \"choice\": \"" << p->tuned << "\"}";
+  const std::string s = o.str();
+  if ((int32_t)s.size() + 1 > len) return fail(ADCT16_E_SHAPE, "buffer too small (%d needed)", (int)s.size() + 1);
+  memcpy(buf, s.c_str(), s.size() + 1);
+  return ADCT16_OK;
+}
+
+adct16_status adct16_forward(adct16_plan p, const void* d_in, void* d_coef, void* stream) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!d_in || !d_coef) return fail(ADCT16_E_NULL, "d_in / d_coef is NULL");
+  if (!aligned16(d_in) || !aligned16(d_coef)) return fail(ADCT16_E_ALIGN, "d_in / d_coef not 16-byte aligned");
+  Params P = base_params(p);
+  P.in = d_in;
+  P.coef = d_coef;
+  hipError_t e;
+  if (p->backend == ADCT16_BACKEND_MFMA && p->coef_kind != CF_F32)
+    e = launch_mfma_forward(p->coef_kind, P, p->grid, (hipStream_t)stream);
+  else
+    e = launch_valu_forward(p->in_kind, p->coef_kind, P, p->grid, (hipStream_t)stream);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "forward kernel");
+}
+
+adct16_status adct16_quantise(adct16_plan p, const void* d_coef, void* d_qcoef, void* stream) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!d_coef || !d_qcoef) return fail(ADCT16_E_NULL, "d_coef / d_qcoef is NULL");
+  if (!aligned16(d_coef) || !aligned16(d_qcoef)) return fail(ADCT16_E_ALIGN, "d_coef / d_qcoef not 16-byte aligned");
+  if (p->coef_kind == CF_F32) return fail(ADCT16_E_STATE, "quantise needs integer coefficients (coef_dtype I32 or I16)");
+  if (p->mode == MODE_MASK && p->qcoef_kind != p->coef_kind)
+    return fail(ADCT16_E_STATE, "retention keeps the coefficient dtype: qcoef_dtype must equal coef_dtype");
+  Params P = base_params(p);
+  P.coef = const_cast<void*>(d_coef);
+  P.qcoef = d_qcoef;
+  hipError_t e = launch_quantise(p->coef_kind, p->mode, p->qcoef_kind, P, (hipStream_t)stream);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "quantise kernel");
+}
+
+adct16_status adct16_inverse(adct16_plan p, const void* d_qcoef, void* d_out, void* stream) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!d_qcoef || !d_out) return fail(ADCT16_E_NULL, "d_qcoef / d_out is NULL");
+  if (!aligned16(d_qcoef) || !aligned16(d_out)) return fail(ADCT16_E_ALIGN, "d_qcoef / d_out not 16-byte aligned");
+  Params P = base_params(p);
+  P.qcoef = const_cast<void*>(d_qcoef);
+  P.out = d_out;
+  hipError_t e = launch_valu_inverse(p->qcoef_kind, p->mode, p->out_kind, P, p->grid, (hipStream_t)stream);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "inverse kernel");
+}
+
+adct16_status adct16_measure(adct16_plan p, const void* d_a, const void* d_b, int64_t* d_sse, double* d_psnr,
+                             void* stream) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!d_a || !d_b || !d_sse) return fail(ADCT16_E_NULL, "d_a / d_b / d_sse is NULL");
+  if (!aligned16(d_a) || !aligned16(d_b)) return fail(ADCT16_E_ALIGN, "d_a / d_b not 16-byte aligned");
+  if (p->out_kind == OUT_F32) return fail(ADCT16_E_STATE, "measure compares integer images (out_dtype U8 or I16)");
+  if ((p->in_kind == IN_U8) != (p->out_kind == OUT_U8))
+    return fail(ADCT16_E_STATE, "measure needs in_dtype == out_dtype");
+  Params P = base_params(p);
+  P.in = d_a;
+  P.in2 = d_b;
+  P.sse = reinterpret_cast<unsigned long long*>(d_sse);
+  P.psnr = d_psnr;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_zero_u64(P.sse, P.n_images, s);
+  if (e == hipSuccess) e = launch_measure(p->in_kind, p->out_kind, P, p->grid, s);
+  if (e == hipSuccess && d_psnr) e = launch_psnr_finalize(P, s);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "measure kernels");
+}
+
+adct16_status adct16_compress_and_measure(adct16_plan p, const void* d_in, void* d_out, void* d_qcoef,
+                                          int64_t* d_sse, double* d_psnr, void* stream) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!d_in) return fail(ADCT16_E_NULL, "d_in is NULL");
+  if (!aligned16(d_in) || (d_out && !aligned16(d_out)) || (d_qcoef && !aligned16(d_qcoef)))
+    return fail(ADCT16_E_ALIGN, "buffers must be 16-byte aligned");
+  if (d_out && p->out_kind == OUT_F32)
+    return fail(ADCT16_E_STATE, "the fused call writes rounded reconstructions (out_dtype U8 or I16)");
+  return compress_impl(p, p->backend, p->grid, d_in, d_out, d_qcoef, d_sse, d_psnr, (hipStream_t)stream);
+}
+
+adct16_status adct16_dct_forward(adct16_plan p, const void* d_in, float* d_y, int32_t precision, void* stream) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!d_in || !d_y) return fail(ADCT16_E_NULL, "d_in / d_y is NULL");
+  if (!aligned16(d_in) || !aligned16(d_y)) return fail(ADCT16_E_ALIGN, "d_in / d_y not 16-byte aligned");
+  if (precision != ADCT16_BF16 && precision != ADCT16_F16) return fail(ADCT16_E_MODE, "precision must be BF16 or F16");
+  Params P = base_params(p);
+  P.in = d_in;
+  hipError_t e = launch_dct_mfma(p->in_kind, precision, P, d_y, p->grid, (hipStream_t)stream);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "DCT kernel");
+}
+
+adct16_status adct16_forward_1d(const int32_t* d_x, int32_t* d_y, int64_t n, void* stream) {
+  if (n < 0) return fail(ADCT16_E_SHAPE, "n < 0");
+  if (n == 0) return ADCT16_OK;
+  if (!d_x || !d_y) return fail(ADCT16_E_NULL, "d_x / d_y is NULL");
+  if (!aligned16(d_x) || !aligned16(d_y)) return fail(ADCT16_E_ALIGN, "d_x / d_y not 16-byte aligned");
+  hipError_t e = launch_1d(false, d_x, d_y, n, (hipStream_t)stream);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "1-D kernel");
+}
+
+adct16_status adct16_inverse_1d(const int32_t* d_x, int32_t* d_y, int64_t n, void* stream) {
+  if (n < 0) return fail(ADCT16_E_SHAPE, "n < 0");
+  if (n == 0) return ADCT16_OK;
+  if (!d_x || !d_y) return fail(ADCT16_E_NULL, "d_x / d_y is NULL");
+  if (!aligned16(d_x) || !aligned16(d_y)) return fail(ADCT16_E_ALIGN, "d_x / d_y not 16-byte aligned");
+  hipError_t e = launch_1d(true, d_x, d_y, n, (hipStream_t)stream);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "1-D kernel");
+}
+
+adct16_status adct16_graph_create(adct16_plan p, const void* d_in, void* d_out, void* d_qcoef, int64_t* d_sse,
+                                  double* d_psnr, adct16_graph* out) {
+  if (!out) return fail(ADCT16_E_NULL, "out is NULL");
+  *out = nullptr;
+  if (adct16_status st = check_plan(p)) return st;
+  if (!d_in) return fail(ADCT16_E_NULL, "d_in is NULL");
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(ADCT16_E_LAUNCH, "capture stream");
+  auto* g = new adct16_graph_s();
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  adct16_status st = ADCT16_OK;
+  if (e == hipSuccess) {
+    st = adct16_compress_and_measure(p, d_in, d_out, d_qcoef, d_sse, d_psnr, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+    if (st == ADCT16_OK && e2 != hipSuccess) st = hip_fail(e2, "end capture");
+  } else {
+    st = hip_fail(e, "begin capture");
+  }
+  if (st == ADCT16_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) st = hip_fail(e, "graph instantiate");
+  }
+  hipStreamDestroy(cs);
+  if (st != ADCT16_OK) {
+    adct16_graph_destroy(g);
+    return st;
+  }
+  *out = g;
+  return ADCT16_OK;
+}
+
+adct16_status adct16_graph_launch(adct16_graph g, void* stream) {
+  if (!g) return fail(ADCT16_E_NULL, "graph is NULL");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "graph launch");
+}
+
+adct16_status adct16_graph_destroy(adct16_graph g) {
+  if (!g) return fail(ADCT16_E_NULL, "graph is NULL");
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
+  return ADCT16_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,848 @@
+// Vector-ALU kernels: the 60-addition butterflies of Eq. (1) applied to the
+// rows of 16x16 blocks, an LDS transpose, and the columns (Section 5.1's
+// row / transpose / column structure), plus retention, the uniform
+// quantiser, the inverse and the PSNR reduction of Section 4.
+//
+// Work layout.  A wavefront processes one strip (16 rows x 8 blocks) at a
+// time.  Lane l = 16 p + x works on blocks p and p + 4 of the strip: in the
+// row layout it holds row x of both blocks, in the column layout column x.
+// 8-bit pixels are transformed as packed pairs of 16-bit lanes (block p in
+// the low half, block p + 4 in the high half): every forward output lies in
+// a known range narrower than 2^16 (AC in [-32640, 32640], DC in [0, 65280]),
+// so modular 16-bit arithmetic recovers it exactly and each v_pk_add/sub
+// does two of the paper's additions.  Inverses run in int32 (exact) or
+// float64 (uniform quantiser).
+#include <algorithm>
+
+#include "device_common.hpp"
+
+namespace adct16 {
+
+__device__ __forceinline__ us2 as_us2(unsigned v) { return __builtin_bit_cast(us2, v); }
+__device__ __forceinline__ unsigned as_u32(us2 v) { return __builtin_bit_cast(unsigned, v); }
+
+// s_u = 1/sqrt(n_u), n = (16,16,12,8,8,16,12,12,16,12,12,8,8,12,12,12).
+__device__ __forceinline__ double s_of(int u) {
+  constexpr double q4 = 0.25, r12 = 0.28867513459481287, r8 = 0.35355339059327373;
+  switch (u) {
+    case 0: case 1: case 5: case 8: return q4;
+    case 3: case 4: case 11: case 12: return r8;
+    default: return r12;
+  }
+}
+
+struct LaneGeom {
+  bool rowok;      // this lane's row (row layout) lies inside the image
+  int na, nb;      // valid columns of blocks a / b (0: block absent)
+  int64_t rowoff;  // element offset of the (clamped) row
+  int xa, xb;      // first column of blocks a / b
+  int64_t blka, blkb;  // block indices in coefficient buffers
+};
+
+__device__ __forceinline__ LaneGeom lane_geom(const StripCursor& c, int x, int p) {
+  LaneGeom g;
+  const int y0 = c.sy * 16;
+  g.rowok = (y0 + x) < c.d.h;
+  const int y = min(y0 + x, c.d.h - 1);
+  const int ba = c.sxi * kStripBlocks + p, bb = ba + 4;
+  g.xa = ba * 16;
+  g.xb = bb * 16;
+  g.na = ba < c.d.bx ? min(16, c.d.w - g.xa) : 0;
+  g.nb = bb < c.d.bx ? min(16, c.d.w - g.xb) : 0;
+  g.rowoff = c.d.offset + (int64_t)y * c.d.pitch;
+  const int64_t rowblk = c.d.block_begin + (int64_t)c.sy * c.d.bx;
+  g.blka = rowblk + ba;
+  g.blkb = rowblk + bb;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// Loads of one block row (16 samples), edge-extended past the image width.
+__device__ __forceinline__ uint4 load_row_u8(const uint8_t* img, int64_t off, int n) {
+  if (n <= 0) return make_uint4(0, 0, 0, 0);
+  uint4 q = *reinterpret_cast<const uint4*>(img + off);
+  if (n < 16) q = extend_bytes(q, n);
+  return q;
+}
+
+__device__ __forceinline__ void load_row_i16(const int16_t* img, int64_t off, int n, int (&v)[16]) {
+  if (n <= 0) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = 0;
+    return;
+  }
+  const uint4* q = reinterpret_cast<const uint4*>(img + off);
+  const uint4 q0 = q[0], q1 = q[1];
+  const unsigned w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v[2 * k] = (int)(short)(w[k] & 0xffffu);
+    v[2 * k + 1] = ((int)w[k]) >> 16;
+  }
+  if (n < 16) {
+    int last = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) last = (k == n - 1) ? v[k] : last;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = (k < n) ? v[k] : last;
+  }
+}
+
+// (a[k], b[k]) byte pairs -> packed 16-bit pairs.
+__device__ __forceinline__ void pair_bytes(const uint4& a, const uint4& b, us2 (&X)[16]) {
+  const unsigned aw[4] = {a.x, a.y, a.z, a.w};
+  const unsigned bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const unsigned j = k & 3;
+    const unsigned sel = j | (0x0cu << 8) | ((4u + j) << 16) | (0x0cu << 24);
+    X[k] = as_us2(__builtin_amdgcn_perm(bw[k >> 2], aw[k >> 2], sel));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward transform of the strip; results in the column layout.
+struct ColsU8 { us2 z[16]; };       // packed (block a, block b) modulo 2^16
+struct ColsI32 { int a[16], b[16]; };
+
+// Raw 16-byte row loads of blocks a and b (zero for absent blocks); the
+// edge extension is applied where the rows are consumed, so that loads for
+// the next strip can be in flight while the current one is computed.
+__device__ __forceinline__ void load_rows_u8(const uint8_t* img, const LaneGeom& g, uint4& ra, uint4& rb) {
+  ra = g.na > 0 ? *reinterpret_cast<const uint4*>(img + g.rowoff + g.xa) : make_uint4(0, 0, 0, 0);
+  rb = g.nb > 0 ? *reinterpret_cast<const uint4*>(img + g.rowoff + g.xb) : make_uint4(0, 0, 0, 0);
+}
+
+__device__ __forceinline__ void fix_edges_u8(const LaneGeom& g, uint4& ra, uint4& rb) {
+  if (g.na > 0 && g.na < 16) ra = extend_bytes(ra, g.na);
+  if (g.nb > 0 && g.nb < 16) rb = extend_bytes(rb, g.nb);
+}
+
+// Forward transform of rows already loaded (and edge-extended).
+__device__ __forceinline__ void forward_u8_rows(int* lds, int x, int p, const uint4& ra, const uint4& rb,
+                                                us2 (&Z)[16]) {
+  pair_bytes(ra, rb, Z);
+  t_fwd(Z);                                 // row pass
+  transpose_rows_to_cols(lds, p, x, Z);     // transposition buffer
+  t_fwd(Z);                                 // column pass: Z[u] = (Za[u][x], Zb[u][x])
+}
+
+__device__ __forceinline__ void forward_u8(const uint8_t* img, const LaneGeom& g, int* lds, int x,
+                                           int p, uint4& ra, uint4& rb, us2 (&Z)[16]) {
+  ra = load_row_u8(img, g.rowoff + g.xa, g.na);
+  rb = load_row_u8(img, g.rowoff + g.xb, g.nb);
+  pair_bytes(ra, rb, Z);
+  t_fwd(Z);                                 // row pass
+  transpose_rows_to_cols(lds, p, x, Z);     // transposition buffer
+  t_fwd(Z);                                 // column pass: Z[u] = (Za[u][x], Zb[u][x])
+}
+
+// Exact int32 coefficients from the packed 16-bit residues: AC values are
+// the signed residues, DC (u = v = 0, lane x = 0) the unsigned one.
+__device__ __forceinline__ void widen_u8(const us2 (&Z)[16], int x, int (&za)[16], int (&zb)[16]) {
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const unsigned w = as_u32(Z[u]);
+    za[u] = (int)(short)(w & 0xffffu);
+    zb[u] = ((int)w) >> 16;
+  }
+  const unsigned w0 = as_u32(Z[0]);
+  za[0] = (x == 0) ? (int)(w0 & 0xffffu) : za[0];
+  zb[0] = (x == 0) ? (int)(w0 >> 16) : zb[0];
+}
+
+__device__ __forceinline__ void forward_i16(const int16_t* img, const LaneGeom& g, int* lds, int x,
+                                            int p, int (&za)[16], int (&zb)[16]) {
+  load_row_i16(img, g.rowoff + g.xa, g.na, za);
+  load_row_i16(img, g.rowoff + g.xb, g.nb, zb);
+  t_fwd(za);
+  t_fwd(zb);
+  transpose_rows_to_cols(lds, p, x, za);
+  transpose_rows_to_cols(lds, p, x, zb);
+  t_fwd(za);
+  t_fwd(zb);
+}
+
+// ---------------------------------------------------------------------------
+// Inverses, column layout in, row layout out.
+
+// Mask modes: t = T^T (W .* Z) T + 1152 exactly in int32 (W = w w^T .* keep
+// already applied by the caller).  `rnd` adds 1152 at (0,0), which adds 1152
+// to every output because row 0 of T is all ones.
+__device__ __forceinline__ void inverse_int(int* lds, int x, int p, int (&a)[16], int (&b)[16], bool rnd) {
+  if (rnd && x == 0) { a[0] += 1152; b[0] += 1152; }
+  t_inv(a);
+  t_inv(b);
+  transpose_cols_to_rows(lds, p, x, a);
+  transpose_cols_to_rows(lds, p, x, b);
+  t_inv(a);
+  t_inv(b);
+}
+
+__device__ __forceinline__ void inverse_f64(int* lds, int x, int p, double (&a)[16], double (&b)[16]) {
+  t_inv(a);
+  t_inv(b);
+  transpose_cols_to_rows_f64(lds, p, x, a);
+  transpose_cols_to_rows_f64(lds, p, x, b);
+  t_inv(a);
+  t_inv(b);
+}
+
+// floor((N + 1152) / 2304) clamped to [0, 255], given t = N + 1152: for
+// 0 <= t <= 589823, floor(t / 2304) = (t * 1864136) >> 32 (24-bit multiply).
+__device__ __forceinline__ unsigned pix_u8_from_t(int t) {
+  const unsigned tc = (unsigned)min(max(t, 0), 589823);
+  return (unsigned)(((unsigned long long)tc * 1864136ull) >> 32);
+}
+
+__device__ __forceinline__ int floor_div_2304(int t) {
+  int q = t / 2304;
+  return (q * 2304 > t) ? q - 1 : q;
+}
+
+__device__ __forceinline__ int sat16(long long v) { return (int)min(max(v, -32768ll), 32767ll); }
+
+__device__ __forceinline__ uint4 pack_u8(const unsigned (&v)[16]) {
+  uint4 r;
+  r.x = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+  r.y = v[4] | (v[5] << 8) | (v[6] << 16) | (v[7] << 24);
+  r.z = v[8] | (v[9] << 8) | (v[10] << 16) | (v[11] << 24);
+  r.w = v[12] | (v[13] << 8) | (v[14] << 16) | (v[15] << 24);
+  return r;
+}
+
+// Sum of squared byte differences over the first n bytes of two rows.
+__device__ __forceinline__ unsigned sse_u8(uint4 o, uint4 r, int n) {
+  if (n < 16) { o = keep_bytes(o, n); r = keep_bytes(r, n); }
+  const unsigned ow[4] = {o.x, o.y, o.z, o.w}, rw[4] = {r.x, r.y, r.z, r.w};
+  unsigned oo = 0, rr = 0, orr = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    oo = __builtin_amdgcn_udot4(ow[m], ow[m], oo, false);
+    rr = __builtin_amdgcn_udot4(rw[m], rw[m], rr, false);
+    orr = __builtin_amdgcn_udot4(ow[m], rw[m], orr, false);
+  }
+  return oo + rr - 2u * orr;
+}
+
+__device__ __forceinline__ void store_row_u8(uint8_t* img, int64_t off, int n, uint4 v) {
+  if (n >= 16) {
+    *reinterpret_cast<uint4*>(img + off) = v;
+  } else {
+    for (int k = 0; k < n; ++k) img[off + k] = (uint8_t)byte_of(v, k);
+  }
+}
+
+__device__ __forceinline__ void store_row_i16(int16_t* img, int64_t off, int n, const int (&v)[16]) {
+  if (n >= 16) {
+    uint4* q = reinterpret_cast<uint4*>(img + off);
+    unsigned w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = ((unsigned)v[2 * k] & 0xffffu) | ((unsigned)v[2 * k + 1] << 16);
+    q[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    q[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  } else {
+    for (int k = 0; k < n; ++k) img[off + k] = (int16_t)v[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coefficient stores / loads in the column layout (block-major buffers).
+template <int CF>
+__device__ __forceinline__ void store_col(void* buf, int64_t blk, int x, const int (&z)[16]) {
+  if constexpr (CF == CF_I32 || CF == CF_L32) {
+    int* d = reinterpret_cast<int*>(buf) + blk * 256 + x;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) d[u * 16] = z[u];
+  } else if constexpr (CF == CF_I16C) {
+    int16_t* d = reinterpret_cast<int16_t*>(buf) + blk * 256 + x;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) d[u * 16] = (int16_t)((u == 0 && x == 0) ? z[u] - 32768 : z[u]);
+  } else if constexpr (CF == CF_L16) {
+    int16_t* d = reinterpret_cast<int16_t*>(buf) + blk * 256 + x;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) d[u * 16] = (int16_t)sat16(z[u]);
+  }
+}
+
+template <int CF>
+__device__ __forceinline__ void load_col(const void* buf, int64_t blk, int x, bool ok, int (&z)[16]) {
+  if (!ok) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) z[u] = 0;
+    return;
+  }
+  if constexpr (CF == CF_I32 || CF == CF_L32) {
+    const int* s = reinterpret_cast<const int*>(buf) + blk * 256 + x;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) z[u] = s[u * 16];
+  } else {
+    const int16_t* s = reinterpret_cast<const int16_t*>(buf) + blk * 256 + x;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) z[u] = s[u * 16];
+    if constexpr (CF == CF_I16C) z[0] += (x == 0) ? 32768 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SSE accumulation per wavefront, flushed with one 64-bit atomic per image.
+struct SseAcc {
+  unsigned long long lane = 0;
+  __device__ __forceinline__ void flush(unsigned long long* sse, int img) {
+    const unsigned long long t = wave_sum_u64(lane);
+    if ((threadIdx.x & 63) == 0 && t) atomicAdd(sse + img, t);
+    lane = 0;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Kernels.
+
+template <int IN, int CF>
+__global__ __launch_bounds__(kGroupThreads) void k_forward(Params P) {
+  __shared__ int lds_all[kWavesPerGroup * kWaveLds];
+  int* lds = lds_all + (threadIdx.x >> 6) * kWaveLds;
+  const int lane = threadIdx.x & 63, x = lane & 15, p = lane >> 4;
+  float ysc[16];
+  if constexpr (CF == CF_F32) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) ysc[u] = P.tables->yscale[u * 16 + x];
+  }
+  StripCursor c;
+  if (!cursor_init(c, P)) return;
+  do {
+    const LaneGeom g = lane_geom(c, x, p);
+    int za[16], zb[16];
+    if constexpr (IN == IN_U8) {
+      uint4 ra, rb;
+      us2 Z[16];
+      forward_u8(reinterpret_cast<const uint8_t*>(P.in), g, lds, x, p, ra, rb, Z);
+      if constexpr (CF == CF_I16C) {
+        // Residues are the int16 bit patterns of the centred coefficients,
+        // except DC: flipping bit 15 subtracts 32768 modulo 2^16.
+        int16_t* d = reinterpret_cast<int16_t*>(P.coef);
+        if (x == 0) Z[0] = as_us2(as_u32(Z[0]) ^ 0x80008000u);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const unsigned w = as_u32(Z[u]);
+          if (g.na > 0) d[g.blka * 256 + u * 16 + x] = (int16_t)(w & 0xffffu);
+          if (g.nb > 0) d[g.blkb * 256 + u * 16 + x] = (int16_t)(w >> 16);
+        }
+        continue;
+      }
+      widen_u8(Z, x, za, zb);
+    } else {
+      forward_i16(reinterpret_cast<const int16_t*>(P.in), g, lds, x, p, za, zb);
+    }
+    if constexpr (CF == CF_I32) {
+      if (g.na > 0) store_col<CF_I32>(P.coef, g.blka, x, za);
+      if (g.nb > 0) store_col<CF_I32>(P.coef, g.blkb, x, zb);
+    } else if constexpr (CF == CF_F32) {
+      float* d = reinterpret_cast<float*>(P.coef);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        if (g.na > 0) d[g.blka * 256 + u * 16 + x] = (float)za[u] * ysc[u];
+        if (g.nb > 0) d[g.blkb * 256 + u * 16 + x] = (float)zb[u] * ysc[u];
+      }
+    }
+  } while (cursor_next(c, P), c.s < c.s_end);
+}
+
+// Retention / quantiser of the column-layout coefficients of one lane.
+// Mask modes multiply by W = w_u w_v keep(u, v) (the inverse weights); the
+// masked coefficients themselves are kept for an optional qcoef output.
+template <int MODE, int QOUT, int OUT>
+__device__ __forceinline__ void quant_and_inverse(const Params& P, const LaneGeom& g, int* lds, int x,
+                                                  int p, const int (&W)[16], const float (&Mq)[16],
+                                                  double Dc, int (&za)[16], int (&zb)[16],
+                                                  int (&oa)[16], int (&ob)[16], double (&fa)[16],
+                                                  double (&fb)[16]) {
+  if constexpr (MODE == MODE_MASK) {
+    if constexpr (QOUT != CF_NONE) {
+      int ka[16], kb[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        ka[u] = W[u] ? za[u] : 0;
+        kb[u] = W[u] ? zb[u] : 0;
+      }
+      if (g.na > 0) store_col<QOUT>(P.qcoef, g.blka, x, ka);
+      if (g.nb > 0) store_col<QOUT>(P.qcoef, g.blkb, x, kb);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      za[u] = __mul24(za[u], W[u]);
+      zb[u] = __mul24(zb[u], W[u]);
+    }
+    inverse_int(lds, x, p, za, zb, OUT != OUT_F32);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) { oa[k] = za[k]; ob[k] = zb[k]; }
+  } else {
+    int la[16], lb[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      la[u] = (int)__builtin_rintf((float)za[u] * Mq[u]);
+      lb[u] = (int)__builtin_rintf((float)zb[u] * Mq[u]);
+    }
+    if constexpr (QOUT != CF_NONE) {
+      if (g.na > 0) store_col<QOUT>(P.qcoef, g.blka, x, la);
+      if (g.nb > 0) store_col<QOUT>(P.qcoef, g.blkb, x, lb);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      fa[u] = ((double)la[u] * Dc) * s_of(u);
+      fb[u] = ((double)lb[u] * Dc) * s_of(u);
+    }
+    inverse_f64(lds, x, p, fa, fb);
+  }
+}
+
+// Row-layout epilogue: reconstruction pixels of this lane's rows.
+template <int MODE, int OUT>
+__device__ __forceinline__ void recon_u8(const int (&t)[16], const double (&f)[16], unsigned (&pix)[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if constexpr (MODE == MODE_MASK) {
+      pix[k] = pix_u8_from_t(t[k]);
+    } else {
+      const double r = floor(f[k] + 0.5);
+      pix[k] = (unsigned)fmin(fmax(r, 0.0), 255.0);
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void recon_i16(const int (&t)[16], const double (&f)[16], int (&pix)[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if constexpr (MODE == MODE_MASK) {
+      pix[k] = sat16(floor_div_2304(t[k]));
+    } else {
+      const double r = floor(f[k] + 0.5);
+      pix[k] = (int)fmin(fmax(r, -32768.0), 32767.0);
+    }
+  }
+}
+
+template <int IN, int MODE, int QOUT, int OUT>
+__global__ __launch_bounds__(kGroupThreads) void k_fused(Params P) {
+  __shared__ int lds_all[kWavesPerGroup * kWaveLds];
+  int* lds = lds_all + (threadIdx.x >> 6) * kWaveLds;
+  const int lane = threadIdx.x & 63, x = lane & 15, p = lane >> 4;
+  int W[16];
+  float Mq[16];
+  double Dc = 0.0;
+  if constexpr (MODE == MODE_MASK) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) W[u] = P.tables->wkeep[u * 16 + x];
+  } else {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) Mq[u] = P.tables->qmul[u * 16 + x];
+    Dc = P.tables->deqc[x];
+  }
+  StripCursor c;
+  if (!cursor_init(c, P)) return;
+  SseAcc acc;
+  int since_flush = 0;
+  const uint8_t* in8 = reinterpret_cast<const uint8_t*>(P.in);
+  LaneGeom gn = lane_geom(c, x, p);
+  uint4 na = make_uint4(0, 0, 0, 0), nb = na;
+  if constexpr (IN == IN_U8) load_rows_u8(in8, gn, na, nb);
+  for (;;) {
+    const LaneGeom g = gn;
+    int za[16], zb[16];
+    uint4 ra = na, rb = nb;
+    int ia[16], ib[16];
+    const int img = c.img;
+    const bool changed = cursor_next(c, P);
+    const bool done = c.s >= c.s_end;
+    if (!done) {
+      gn = lane_geom(c, x, p);
+      if constexpr (IN == IN_U8) load_rows_u8(in8, gn, na, nb);  // prefetch the next strip
+    }
+    if constexpr (IN == IN_U8) {
+      us2 Z[16];
+      fix_edges_u8(g, ra, rb);
+      forward_u8_rows(lds, x, p, ra, rb, Z);
+      widen_u8(Z, x, za, zb);
+    } else {
+      forward_i16(reinterpret_cast<const int16_t*>(P.in), g, lds, x, p, za, zb);
+    }
+    int ta[16], tb[16];
+    double fa[16], fb[16];
+    quant_and_inverse<MODE, QOUT, OUT>(P, g, lds, x, p, W, Mq, Dc, za, zb, ta, tb, fa, fb);
+    if constexpr (IN == IN_U8) {
+      unsigned pa[16], pb[16];
+      recon_u8<MODE, OUT>(ta, fa, pa);
+      recon_u8<MODE, OUT>(tb, fb, pb);
+      const uint4 qa = pack_u8(pa), qb = pack_u8(pb);
+      if (g.rowok) {
+        if constexpr (OUT == OUT_U8) {
+          uint8_t* o = reinterpret_cast<uint8_t*>(P.out);
+          if (g.na > 0) store_row_u8(o, g.rowoff + g.xa, g.na, qa);
+          if (g.nb > 0) store_row_u8(o, g.rowoff + g.xb, g.nb, qb);
+        }
+        acc.lane += (g.na > 0 ? sse_u8(ra, qa, g.na) : 0u) + (g.nb > 0 ? sse_u8(rb, qb, g.nb) : 0u);
+      }
+    } else {
+      int pa[16], pb[16];
+      recon_i16<MODE>(ta, fa, pa);
+      recon_i16<MODE>(tb, fb, pb);
+      // Re-read the input rows (cache-resident) for the error.
+      const int16_t* in = reinterpret_cast<const int16_t*>(P.in);
+      load_row_i16(in, g.rowoff + g.xa, g.na, ia);
+      load_row_i16(in, g.rowoff + g.xb, g.nb, ib);
+      if (g.rowok) {
+        if constexpr (OUT == OUT_I16) {
+          int16_t* o = reinterpret_cast<int16_t*>(P.out);
+          if (g.na > 0) store_row_i16(o, g.rowoff + g.xa, g.na, pa);
+          if (g.nb > 0) store_row_i16(o, g.rowoff + g.xb, g.nb, pb);
+        }
+        unsigned long long s = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const long long da = (k < g.na) ? (long long)(ia[k] - pa[k]) : 0;
+          const long long db = (k < g.nb) ? (long long)(ib[k] - pb[k]) : 0;
+          s += (unsigned long long)(da * da) + (unsigned long long)(db * db);
+        }
+        acc.lane += s;
+      }
+    }
+    if (changed || done || ++since_flush == 1024) {
+      acc.flush(P.sse, img);
+      since_flush = 0;
+    }
+    if (done) break;
+  }
+}
+
+// Inverse of block-major coefficients or levels.
+template <int CFIN, int MODE, int OUT>
+__global__ __launch_bounds__(kGroupThreads) void k_inverse(Params P) {
+  __shared__ int lds_all[kWavesPerGroup * kWaveLds];
+  int* lds = lds_all + (threadIdx.x >> 6) * kWaveLds;
+  const int lane = threadIdx.x & 63, x = lane & 15, p = lane >> 4;
+  int W[16];
+  double Dc = 0.0;
+  if constexpr (MODE == MODE_MASK) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) W[u] = P.tables->wall[u * 16 + x];
+  } else {
+    Dc = P.tables->deqc[x];
+  }
+  StripCursor c;
+  if (!cursor_init(c, P)) return;
+  do {
+    const LaneGeom g = lane_geom(c, x, p);
+    int za[16], zb[16];
+    load_col<CFIN>(P.qcoef, g.blka, x, g.na > 0, za);
+    load_col<CFIN>(P.qcoef, g.blkb, x, g.nb > 0, zb);
+    int ta[16], tb[16];
+    double fa[16], fb[16];
+    if constexpr (MODE == MODE_MASK) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        za[u] = __mul24(za[u], W[u]);
+        zb[u] = __mul24(zb[u], W[u]);
+      }
+      inverse_int(lds, x, p, za, zb, OUT != OUT_F32);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) { ta[k] = za[k]; tb[k] = zb[k]; }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        fa[u] = ((double)za[u] * Dc) * s_of(u);
+        fb[u] = ((double)zb[u] * Dc) * s_of(u);
+      }
+      inverse_f64(lds, x, p, fa, fb);
+    }
+    if (!g.rowok) continue;
+    if constexpr (OUT == OUT_U8) {
+      unsigned pa[16], pb[16];
+      recon_u8<MODE, OUT>(ta, fa, pa);
+      recon_u8<MODE, OUT>(tb, fb, pb);
+      uint8_t* o = reinterpret_cast<uint8_t*>(P.out);
+      if (g.na > 0) store_row_u8(o, g.rowoff + g.xa, g.na, pack_u8(pa));
+      if (g.nb > 0) store_row_u8(o, g.rowoff + g.xb, g.nb, pack_u8(pb));
+    } else if constexpr (OUT == OUT_I16) {
+      int pa[16], pb[16];
+      recon_i16<MODE>(ta, fa, pa);
+      recon_i16<MODE>(tb, fb, pb);
+      int16_t* o = reinterpret_cast<int16_t*>(P.out);
+      if (g.na > 0) store_row_i16(o, g.rowoff + g.xa, g.na, pa);
+      if (g.nb > 0) store_row_i16(o, g.rowoff + g.xb, g.nb, pb);
+    } else {
+      float* o = reinterpret_cast<float*>(P.out);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        float va, vb;
+        if constexpr (MODE == MODE_MASK) {
+          va = (float)((double)ta[k] / 2304.0);
+          vb = (float)((double)tb[k] / 2304.0);
+        } else {
+          va = (float)fa[k];
+          vb = (float)fb[k];
+        }
+        if (k < g.na) o[g.rowoff + g.xa + k] = va;
+        if (k < g.nb) o[g.rowoff + g.xb + k] = vb;
+      }
+    }
+  } while (cursor_next(c, P), c.s < c.s_end);
+}
+
+// Retention or uniform quantisation of block-major coefficients: thread t
+// handles the 16 coefficients of row u = t mod 16 of block t / 16.
+template <int CFIN, int MODE, int QOUT>
+__global__ __launch_bounds__(256) void k_quantise(Params P) {
+  const int64_t nrows = P.n_blocks * 16;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nrows;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int u = (int)(t & 15);
+    int z[16];
+    if constexpr (CFIN == CF_I32) {
+      const int4* s = reinterpret_cast<const int4*>(reinterpret_cast<const int*>(P.coef) + t * 16);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int4 q = s[m];
+        z[4 * m] = q.x; z[4 * m + 1] = q.y; z[4 * m + 2] = q.z; z[4 * m + 3] = q.w;
+      }
+    } else {
+      const uint4* s = reinterpret_cast<const uint4*>(reinterpret_cast<const int16_t*>(P.coef) + t * 16);
+      const uint4 q0 = s[0], q1 = s[1];
+      const unsigned w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        z[2 * k] = (int)(short)(w[k] & 0xffffu);
+        z[2 * k + 1] = ((int)w[k]) >> 16;
+      }
+    }
+    int r[16];
+    if constexpr (MODE == MODE_MASK) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) r[v] = P.tables->wkeep[u * 16 + v] ? z[v] : 0;
+    } else {
+      if constexpr (CFIN == CF_I16C) z[0] += (u == 0) ? 32768 : 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) r[v] = (int)__builtin_rintf((float)z[v] * P.tables->qmul[u * 16 + v]);
+    }
+    if constexpr (QOUT == CF_I32 || QOUT == CF_L32) {
+      int4* d = reinterpret_cast<int4*>(reinterpret_cast<int*>(P.qcoef) + t * 16);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) d[m] = make_int4(r[4 * m], r[4 * m + 1], r[4 * m + 2], r[4 * m + 3]);
+    } else {
+      unsigned w[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int lo = (QOUT == CF_L16) ? sat16(r[2 * k]) : r[2 * k];
+        const int hi = (QOUT == CF_L16) ? sat16(r[2 * k + 1]) : r[2 * k + 1];
+        w[k] = ((unsigned)lo & 0xffffu) | ((unsigned)hi << 16);
+      }
+      uint4* d = reinterpret_cast<uint4*>(reinterpret_cast<int16_t*>(P.qcoef) + t * 16);
+      d[0] = make_uint4(w[0], w[1], w[2], w[3]);
+      d[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    }
+  }
+}
+
+// Per-image SSE between P.in (IN) and P.in2 (OUT type).
+template <int IN>
+__global__ __launch_bounds__(kGroupThreads) void k_measure(Params P) {
+  const int lane = threadIdx.x & 63, x = lane & 15, p = lane >> 4;
+  StripCursor c;
+  if (!cursor_init(c, P)) return;
+  SseAcc acc;
+  int since_flush = 0;
+  for (;;) {
+    const LaneGeom g = lane_geom(c, x, p);
+    if (g.rowok) {
+      if constexpr (IN == IN_U8) {
+        const uint8_t* a = reinterpret_cast<const uint8_t*>(P.in);
+        const uint8_t* b = reinterpret_cast<const uint8_t*>(P.in2);
+        if (g.na > 0) acc.lane += sse_u8(load_row_u8(a, g.rowoff + g.xa, 16), load_row_u8(b, g.rowoff + g.xa, 16), g.na);
+        if (g.nb > 0) acc.lane += sse_u8(load_row_u8(a, g.rowoff + g.xb, 16), load_row_u8(b, g.rowoff + g.xb, 16), g.nb);
+      } else {
+        const int16_t* a = reinterpret_cast<const int16_t*>(P.in);
+        const int16_t* b = reinterpret_cast<const int16_t*>(P.in2);
+        int va[16], vb[16];
+        unsigned long long s = 0;
+        if (g.na > 0) {
+          load_row_i16(a, g.rowoff + g.xa, 16, va);
+          load_row_i16(b, g.rowoff + g.xa, 16, vb);
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const long long d = (k < g.na) ? (long long)(va[k] - vb[k]) : 0;
+            s += (unsigned long long)(d * d);
+          }
+        }
+        if (g.nb > 0) {
+          load_row_i16(a, g.rowoff + g.xb, 16, va);
+          load_row_i16(b, g.rowoff + g.xb, 16, vb);
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const long long d = (k < g.nb) ? (long long)(va[k] - vb[k]) : 0;
+            s += (unsigned long long)(d * d);
+          }
+        }
+        acc.lane += s;
+      }
+    }
+    const int img = c.img;
+    const bool changed = cursor_next(c, P);
+    const bool done = c.s >= c.s_end;
+    if (changed || done || ++since_flush == 1024) {
+      acc.flush(P.sse, img);
+      since_flush = 0;
+    }
+    if (done) break;
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// PSNR = 10 log10(255^2 h w / SSE), +inf for SSE = 0 (Section 4).
+__global__ void k_psnr(Params P) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P.n_images; i += gridDim.x * blockDim.x) {
+    const unsigned long long s = P.sse[i];
+    const ImageDesc d = P.images[i];
+    P.psnr[i] = s == 0 ? __builtin_huge_val()
+                       : 10.0 * log10(65025.0 * (double)d.h * (double)d.w / (double)s);
+  }
+}
+
+template <bool INV>
+__global__ void k_1d(const int32_t* x, int32_t* y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int v[16];
+    const int4* s = reinterpret_cast<const int4*>(x + i * 16);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int4 q = s[m];
+      v[4 * m] = q.x; v[4 * m + 1] = q.y; v[4 * m + 2] = q.z; v[4 * m + 3] = q.w;
+    }
+    if constexpr (INV) t_inv(v); else t_fwd(v);
+    int4* d = reinterpret_cast<int4*>(y + i * 16);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) d[m] = make_int4(v[4 * m], v[4 * m + 1], v[4 * m + 2], v[4 * m + 3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+#define ADCT16_LAUNCH(kernel, grid, s, P)                                     \
+  do {                                                                        \
+    hipLaunchKernelGGL((kernel), dim3(grid), dim3(kGroupThreads), 0, (s), (P)); \
+    return hipGetLastError();                                                 \
+  } while (0)
+
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_psnr_finalize(const Params& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_psnr, dim3((P.n_images + 255) / 256), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_valu_forward(int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s) {
+  if (in_kind == IN_U8) {
+    switch (coef_kind) {
+      case CF_I32: ADCT16_LAUNCH((k_forward<IN_U8, CF_I32>), grid, s, P);
+      case CF_I16C: ADCT16_LAUNCH((k_forward<IN_U8, CF_I16C>), grid, s, P);
+      case CF_F32: ADCT16_LAUNCH((k_forward<IN_U8, CF_F32>), grid, s, P);
+    }
+  } else {
+    switch (coef_kind) {
+      case CF_I32: ADCT16_LAUNCH((k_forward<IN_I16, CF_I32>), grid, s, P);
+      case CF_F32: ADCT16_LAUNCH((k_forward<IN_I16, CF_F32>), grid, s, P);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int IN, int MODE, int QOUT>
+static hipError_t fused_out(int out_kind, const Params& P, int grid, hipStream_t s) {
+  constexpr int OUTK = IN == IN_U8 ? OUT_U8 : OUT_I16;
+  if (out_kind == OUT_NONE) ADCT16_LAUNCH((k_fused<IN, MODE, QOUT, OUT_NONE>), grid, s, P);
+  if (out_kind == OUTK) ADCT16_LAUNCH((k_fused<IN, MODE, QOUT, OUTK>), grid, s, P);
+  return hipErrorInvalidValue;
+}
+
+template <int IN>
+static hipError_t fused_in(int mode, int qout, int out_kind, const Params& P, int grid, hipStream_t s) {
+  if (mode == MODE_MASK) {
+    if (qout == CF_NONE) return fused_out<IN, MODE_MASK, CF_NONE>(out_kind, P, grid, s);
+    if (qout == CF_I32) return fused_out<IN, MODE_MASK, CF_I32>(out_kind, P, grid, s);
+    if (IN == IN_U8 && qout == CF_I16C) return fused_out<IN, MODE_MASK, CF_I16C>(out_kind, P, grid, s);
+  } else {
+    if (qout == CF_NONE) return fused_out<IN, MODE_UNIFORM, CF_NONE>(out_kind, P, grid, s);
+    if (qout == CF_L16) return fused_out<IN, MODE_UNIFORM, CF_L16>(out_kind, P, grid, s);
+    if (qout == CF_L32) return fused_out<IN, MODE_UNIFORM, CF_L32>(out_kind, P, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_valu_fused(int in_kind, int mode, int qout_kind, int out_kind, const Params& P,
+                             int grid, hipStream_t s) {
+  if (in_kind == IN_U8) return fused_in<IN_U8>(mode, qout_kind, out_kind, P, grid, s);
+  return fused_in<IN_I16>(mode, qout_kind, out_kind, P, grid, s);
+}
+
+template <int CFIN, int MODE>
+static hipError_t inverse_out(int out_kind, const Params& P, int grid, hipStream_t s) {
+  switch (out_kind) {
+    case OUT_U8: ADCT16_LAUNCH((k_inverse<CFIN, MODE, OUT_U8>), grid, s, P);
+    case OUT_I16: ADCT16_LAUNCH((k_inverse<CFIN, MODE, OUT_I16>), grid, s, P);
+    case OUT_F32: ADCT16_LAUNCH((k_inverse<CFIN, MODE, OUT_F32>), grid, s, P);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_valu_inverse(int coef_kind, int mode, int out_kind, const Params& P, int grid,
+                               hipStream_t s) {
+  if (mode == MODE_MASK) {
+    if (coef_kind == CF_I32) return inverse_out<CF_I32, MODE_MASK>(out_kind, P, grid, s);
+    if (coef_kind == CF_I16C) return inverse_out<CF_I16C, MODE_MASK>(out_kind, P, grid, s);
+  } else {
+    if (coef_kind == CF_L32) return inverse_out<CF_L32, MODE_UNIFORM>(out_kind, P, grid, s);
+    if (coef_kind == CF_L16) return inverse_out<CF_L16, MODE_UNIFORM>(out_kind, P, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_quantise(int coef_kind, int mode, int qout_kind, const Params& P, hipStream_t s) {
+  const int64_t rows = P.n_blocks * 16;
+  const int grid = (int)std::min<int64_t>((rows + 255) / 256, 1 << 16);
+#define ADCT16_QLAUNCH(K)                                                \
+  do {                                                                   \
+    hipLaunchKernelGGL((K), dim3(grid), dim3(256), 0, s, P);             \
+    return hipGetLastError();                                            \
+  } while (0)
+  if (mode == MODE_MASK) {
+    if (coef_kind == CF_I32 && qout_kind == CF_I32) ADCT16_QLAUNCH((k_quantise<CF_I32, MODE_MASK, CF_I32>));
+    if (coef_kind == CF_I16C && qout_kind == CF_I16C) ADCT16_QLAUNCH((k_quantise<CF_I16C, MODE_MASK, CF_I16C>));
+  } else {
+    if (coef_kind == CF_I32 && qout_kind == CF_L16) ADCT16_QLAUNCH((k_quantise<CF_I32, MODE_UNIFORM, CF_L16>));
+    if (coef_kind == CF_I32 && qout_kind == CF_L32) ADCT16_QLAUNCH((k_quantise<CF_I32, MODE_UNIFORM, CF_L32>));
+    if (coef_kind == CF_I16C && qout_kind == CF_L16) ADCT16_QLAUNCH((k_quantise<CF_I16C, MODE_UNIFORM, CF_L16>));
+    if (coef_kind == CF_I16C && qout_kind == CF_L32) ADCT16_QLAUNCH((k_quantise<CF_I16C, MODE_UNIFORM, CF_L32>));
+  }
+#undef ADCT16_QLAUNCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_measure(int in_kind, int out_kind, const Params& P, int grid, hipStream_t s) {
+  if (in_kind == IN_U8 && out_kind == OUT_U8) ADCT16_LAUNCH((k_measure<IN_U8>), grid, s, P);
+  if (in_kind == IN_I16 && out_kind == OUT_I16) ADCT16_LAUNCH((k_measure<IN_I16>), grid, s, P);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_1d(bool inverse, const int32_t* x, int32_t* y, int64_t n, hipStream_t s) {
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 1 << 16);
+  if (inverse) hipLaunchKernelGGL(k_1d<true>, dim3(grid), dim3(256), 0, s, x, y, n);
+  else hipLaunchKernelGGL(k_1d<false>, dim3(grid), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
+
+}  // namespace adct16

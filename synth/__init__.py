@@ -66,8 +66,8 @@ def ar1_image(seed: int, h: int = 512, w: int = 512, rho: float = 0.95,
 
 def _rect_params(seed: int, h: int, w: int, count: int = 8, side: int = 64):
     rng = np.random.default_rng([seed, 0x7EC7])
-    y0 = rng.integers(0, h - side, count)
-    x0 = rng.integers(0, w - side, count)
+    y0 = rng.integers(0, max(1, h - side), count)
+    x0 = rng.integers(0, max(1, w - side), count)
     vy = rng.integers(-6, 7, count)
     vx = rng.integers(-6, 7, count)
     level = rng.integers(0, 256, count)
@@ -84,8 +84,8 @@ def luma_frame(seed: int, t: int, h: int = 1088, w: int = 1920,
     f = mean + sigma * ar1_field(rng, h, w, rho)
     y0, x0, vy, vx, level = _rect_params(seed, h, w, n_rect, side)
     for k in range(n_rect):
-        yy = int(y0[k] + vy[k] * t) % (h - side)
-        xx = int(x0[k] + vx[k] * t) % (w - side)
+        yy = int(y0[k] + vy[k] * t) % max(1, h - side)
+        xx = int(x0[k] + vx[k] * t) % max(1, w - side)
         f[yy:yy + side, xx:xx + side] = level[k]
     return _to_u8(f)
 
