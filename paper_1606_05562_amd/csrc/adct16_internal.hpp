@@ -33,6 +33,8 @@ struct Tables {
   float qmul[256];     // M_uv = fl32(1 / (sqrt(n_u n_v) q))
   float yscale[256];   // K_uv = fl32(1 / sqrt(n_u n_v))
   double deqc[16];     // q s_v, per horizontal frequency v
+  int32_t rsep;        // retained r x r square for separable masks (16 = all; zig-zag masks use wkeep)
+  int32_t pad[3];
 };
 
 enum InKind { IN_U8 = 0, IN_I16 = 1 };
@@ -70,8 +72,7 @@ hipError_t launch_measure(int in_kind, int out_kind, const Params& P, int grid, 
 hipError_t launch_1d(bool inverse, const int32_t* x, int32_t* y, int64_t n, hipStream_t s);
 
 hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStream_t s);
-hipError_t launch_mfma_fused(int mode, int qout_kind, int out_kind, const Params& P, int grid,
-                             hipStream_t s);
+hipError_t launch_mfma_fused(bool zigzag, int out_kind, const Params& P, int grid, hipStream_t s);
 hipError_t launch_dct_mfma(int in_kind, int precision, const Params& P, float* y, int grid,
                            hipStream_t s);
 

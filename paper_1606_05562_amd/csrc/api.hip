@@ -121,8 +121,10 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void*
   if (e != hipSuccess) return hip_fail(e, "zero SSE");
   const int qk = d_qcoef ? p->qcoef_kind : CF_NONE;
   const int ok = d_out ? p->out_kind : OUT_NONE;
-  if (backend == ADCT16_BACKEND_MFMA)
-    e = launch_mfma_fused(p->mode, qk, ok, P, grid, s);
+  // The matrix-core fused kernel writes reconstructions and errors; a call
+  // that also asks for the retained coefficients runs the vector kernel.
+  if (backend == ADCT16_BACKEND_MFMA && qk == CF_NONE)
+    e = launch_mfma_fused(p->d.qmode == ADCT16_Q_ZIGZAG, ok, P, grid, s);
   else
     e = launch_valu_fused(p->in_kind, p->mode, qk, ok, P, grid, s);
   if (e != hipSuccess) return hip_fail(e, "fused kernel");
@@ -133,9 +135,10 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void*
   return ADCT16_OK;
 }
 
+// The matrix-core kernels cover 8-bit input with retention masks (the
+// uniform quantiser's inverse runs in float64 on the vector ALUs).
 bool mfma_supported(const adct16_plan_s* p) {
-  (void)p;
-  return false;
+  return p->in_kind == IN_U8 && p->mode == MODE_MASK && p->out_kind != OUT_I16;
 }
 
 // Autotuning: time the fused call for each candidate (backend, workgroups
@@ -350,6 +353,7 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
     }
     t.deqc[u] = uniform ? (double)d->q / std::sqrt((double)kNorm[u]) : 0.0;
   }
+  t.rsep = d->qmode == ADCT16_Q_ZONAL ? d->r : 16;
   bool ok = hipMalloc(&p->d_images, sizeof(ImageDesc) * images.size()) == hipSuccess &&
             hipMalloc(&p->d_tables, sizeof(Tables)) == hipSuccess &&
             hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size()) == hipSuccess;
@@ -360,12 +364,16 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
     return fail(ADCT16_E_NOMEM, "plan allocation failed");
   }
   // kernel choice
+  // Persistent grid: workgroups per CU (ADCT16_WG_PER_CU overrides the
+  // default; the autotuner may replace it).
   const int64_t max_groups = (strips + kWavesPerGroup - 1) / kWavesPerGroup;
-  p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(p->cu_count * 2, max_groups));
+  int wgpc = 4;
+  if (const char* env = getenv("ADCT16_WG_PER_CU")) wgpc = std::max(1, std::min(64, atoi(env)));
+  p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)p->cu_count * wgpc, max_groups));
   if (d->backend == ADCT16_BACKEND_MFMA) {
     if (!mfma_supported(p)) {
       adct16_plan_destroy(p);
-      return fail(ADCT16_E_MODE, "MFMA backend supports U8 input with retention modes");
+      return fail(ADCT16_E_MODE, "MFMA backend supports U8 input, retention modes and U8/F32 output");
     }
     p->backend = ADCT16_BACKEND_MFMA;
     p->tuned = "requested";

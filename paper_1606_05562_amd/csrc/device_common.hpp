@@ -309,4 +309,15 @@ __device__ __forceinline__ uint4 keep_bytes(uint4 q, int n) {
   return q;
 }
 
+// ---------------------------------------------------------------------------
+// SSE accumulation per wavefront, flushed with one 64-bit atomic per image.
+struct SseAcc {
+  unsigned long long lane = 0;
+  __device__ __forceinline__ void flush(unsigned long long* sse, int img) {
+    const unsigned long long t = wave_sum_u64(lane);
+    if ((threadIdx.x & 63) == 0 && t) atomicAdd(sse + img, t);
+    lane = 0;
+  }
+};
+
 }  // namespace adct16

@@ -1,10 +1,281 @@
-// Matrix-core kernels (int8 MFMA form of the transform; BF16/F16 exact DCT-II).
-#include "device_common.hpp"
+// Matrix-core kernels.
+//
+// 1. The approximate DCT as exact FP16 contractions with FP32 accumulation.
+//    T has entries in {0, +1, -1}, so every product below is exact; the
+//    argument for exactness of each sum is that every partial sum is an
+//    integer (or a multiple of 2^-11) of magnitude below 2^24, whatever the
+//    order in which the matrix core adds the terms.  For 8-bit input X
+//    (centred Xc = X - 128, |Xc| <= 128) and every retention mask the worst
+//    cases (linear programs over the pixel box) are |P| <= 2048 after the row
+//    pass, |Z| <= 32768 after the column pass, |U| <= 212544 after the first
+//    inverse pass and |N| <= 1648452 for the final numerator.
+//
+//    stage 1  P  = (X + 1024) T^T - 18432 e_0     (X + 1024 is one v_perm
+//             away from the bytes: fp16 bits 0x64xx; the accumulator starts
+//             at -18432 in column 0, removing the 1024 offset and centring)
+//    stage 2  Z  = T P                      (P is fp16-exact: |P| <= 2048)
+//    split    Z  = a + b, a = fp16_rtz(Z), b = Z - a, |b| <= 15
+//    stage 3  U' = 1536 + 2^-11 sum_u w_u T[u][i] Z'[u][f]   (both digits)
+//    split    U' = A + B, A = fp16_rtz(U') = floor(U') since U' lies in
+//             [1024, 2048) where fp16 steps by 1; B in [0, 1), a multiple
+//             of 2^-11
+//    stage 4  s  = sum_f w_f T[f][j] (A - 1536), then + sum_f w_f T[f][j] B
+//             = N 2^-11 with N = T^T (w w^T .* Z') T, the exact numerator of
+//             the inverse (the weights w = 48/n come from C_hat = S T)
+//    round    pixel = cvt_pk_u8(fma(s, fl32(8/9), 128 + 2^-12)) which equals
+//             clamp(floor(N / 2304 + 1/2) + 128, 0, 255) exactly (the bias
+//             exceeds the fp32 error and stays below 1/2304 minus it).
+//
+//    Zonal masks are separable, so they are applied for free by zeroing rows
+//    of the constant operands; zig-zag masks are applied to Z.
+//
+// 2. The exact DCT-II comparison transform on BF16 / F16 matrix cores.
+//
+// Operand layout (16x16xK, checked on the hardware): lane l = 16 g + q
+// holds row q of A and column q of B restricted to the g-th quarter of K;
+// the accumulator holds rows 4g..4g+3 of column q.
+#include "mfma_stages.hpp"
 
 namespace adct16 {
 
-hipError_t launch_mfma_forward(int, const Params&, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_mfma_fused(int, int, int, const Params&, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_dct_mfma(int, int, const Params&, float*, int, hipStream_t) { return hipErrorNotSupported; }
+// One dword of block row q (columns 4g..4g+3), edge-extended.
+__device__ __forceinline__ unsigned load_dword_u8(const uint8_t* img, const ImageDesc& d, int y, int x0) {
+  const int64_t off = d.offset + (int64_t)y * d.pitch;
+  if (x0 + 3 < d.w) return *reinterpret_cast<const unsigned*>(img + off + x0);
+  unsigned r = 0;
+  for (int k = 0; k < 4; ++k) r |= (unsigned)img[off + min(x0 + k, d.w - 1)] << (8 * k);
+  return r;
+}
+
+// Reconstruct the 8 blocks of a strip from their dwords (all lanes busy).
+template <bool ZIGZAG>
+__device__ __forceinline__ void roundtrip8(const unsigned (&x)[kStripBlocks], unsigned (&out)[kStripBlocks],
+                                           const MfmaConsts& k, const bool (&keepz)[4]) {
+  f4 z[kStripBlocks];
+#pragma unroll
+  for (int b = 0; b < kStripBlocks; ++b) {
+    z[b] = fwd_block(x[b], k);
+    if constexpr (ZIGZAG) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) z[b][v] = keepz[v] ? z[b][v] : 0.0f;
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < kStripBlocks; ++b) out[b] = round_pack(inv_block(z[b], k));
+}
+
+__device__ __forceinline__ unsigned sse4(unsigned a, unsigned r) {
+  return __builtin_amdgcn_udot4(a, a, 0u, false) + __builtin_amdgcn_udot4(r, r, 0u, false) -
+         2u * __builtin_amdgcn_udot4(a, r, 0u, false);
+}
+
+template <bool ZIGZAG, int OUT>
+__global__ __launch_bounds__(kGroupThreads) void k_mfma_fused(Params P) {
+  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
+  const MfmaConsts k = make_consts(q, g, P.tables->rsep);
+  bool keepz[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) keepz[v] = P.tables->wkeep[(4 * g + v) * 16 + q] != 0;
+  const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
+  uint8_t* outp = reinterpret_cast<uint8_t*>(P.out);
+  StripCursor c;
+  if (!cursor_init(c, P)) return;
+  SseAcc acc;
+  int since_flush = 0;
+  for (;;) {
+    const int y0 = c.sy * 16;
+    const int y = min(y0 + q, c.d.h - 1);
+    const bool rowok = (y0 + q) < c.d.h;
+    const int b0 = c.sxi * kStripBlocks;
+    const int64_t off = c.d.offset + (int64_t)y * c.d.pitch;
+    unsigned x[kStripBlocks], out[kStripBlocks];
+    if ((b0 + kStripBlocks) * 16 <= c.d.w) {
+      // Interior strip: eight whole blocks, no per-block tests.
+      const uint8_t* src = in + off + b0 * 16 + 4 * g;
+#pragma unroll
+      for (int b = 0; b < kStripBlocks; ++b) x[b] = *reinterpret_cast<const unsigned*>(src + 16 * b);
+      roundtrip8<ZIGZAG>(x, out, k, keepz);
+      if (rowok) {
+        if constexpr (OUT == OUT_U8) {
+          uint8_t* dst = outp + off + b0 * 16 + 4 * g;
+#pragma unroll
+          for (int b = 0; b < kStripBlocks; ++b) *reinterpret_cast<unsigned*>(dst + 16 * b) = out[b];
+        }
+        unsigned s = 0;
+#pragma unroll
+        for (int b = 0; b < kStripBlocks; ++b) s += sse4(x[b], out[b]);
+        acc.lane += s;
+      }
+    } else {
+      // Right-edge strip: fewer blocks and / or a partial last block
+      // (columns past the width repeat the last one).
+      const int nb = min(kStripBlocks, c.d.bx - b0);
+#pragma unroll
+      for (int b = 0; b < kStripBlocks; ++b)
+        x[b] = b < nb ? load_dword_u8(in, c.d, y, (b0 + b) * 16 + 4 * g) : 0u;
+      roundtrip8<ZIGZAG>(x, out, k, keepz);
+      if (rowok) {
+#pragma unroll
+        for (int b = 0; b < kStripBlocks; ++b) {
+          const int x0 = (b0 + b) * 16 + 4 * g;
+          const int n = b < nb ? min(4, c.d.w - x0) : 0;
+          if (n > 0) {
+            if constexpr (OUT == OUT_U8) {
+              uint8_t* o = outp + off + x0;
+              if (n == 4) *reinterpret_cast<unsigned*>(o) = out[b];
+              else for (int j = 0; j < n; ++j) o[j] = (uint8_t)(out[b] >> (8 * j));
+            }
+            const unsigned m = n >= 4 ? 0xffffffffu : ((1u << (8 * n)) - 1u);
+            acc.lane += sse4(x[b] & m, out[b] & m);
+          }
+        }
+      }
+    }
+    const int img = c.img;
+    const bool changed = cursor_next(c, P);
+    const bool done = c.s >= c.s_end;
+    if (changed || done || ++since_flush == 1024) {
+      acc.flush(P.sse, img);
+      since_flush = 0;
+    }
+    if (done) break;
+  }
+}
+
+// Forward only: Z (int32) or the centred int16 form, block-major.  Stage 2
+// runs transposed (Z^T = P^T T^T) so that each lane ends with four
+// consecutive coefficients of one row: Z[q][4g..4g+3].
+template <int CF>
+__global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P) {
+  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
+  const MfmaConsts k = make_consts(q, g, 16);
+  const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
+  StripCursor c;
+  if (!cursor_init(c, P)) return;
+  do {
+    const int y = min(c.sy * 16 + q, c.d.h - 1);
+    const int b0 = c.sxi * kStripBlocks;
+    const int nb = min(kStripBlocks, c.d.bx - b0);
+    const int64_t rowblk = c.d.block_begin + (int64_t)c.sy * c.d.bx + b0;
+    unsigned x[kStripBlocks];
+#pragma unroll
+    for (int b = 0; b < kStripBlocks; ++b)
+      x[b] = b < nb ? load_dword_u8(in, c.d, y, (b0 + b) * 16 + 4 * g) : 0u;
+#pragma unroll
+    for (int b = 0; b < kStripBlocks; ++b) {
+      if (b < nb) {
+        const f4 c1 = {k.c1, k.c1, k.c1, k.c1};
+        const f4 p = mma16(bytes_to_h4(x[b]), k.tq, c1);
+        const uint2 ph = make_uint2(pack_h(p[0], p[1]), pack_h(p[2], p[3]));
+        const f4 zero = {0, 0, 0, 0};
+        const f4 zt = mma16(ph, k.tq, zero);  // Z_c[q][4g+v]
+        int z[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) z[v] = (int)zt[v];
+        const int64_t base = (rowblk + b) * 256 + q * 16 + 4 * g;
+        if constexpr (CF == CF_I32) {
+          if (q == 0 && g == 0) z[0] += 32768;  // undo the centring at (0, 0)
+          *reinterpret_cast<int4*>(reinterpret_cast<int*>(P.coef) + base) = make_int4(z[0], z[1], z[2], z[3]);
+        } else {
+          const unsigned lo = ((unsigned)z[0] & 0xffffu) | ((unsigned)z[1] << 16);
+          const unsigned hi = ((unsigned)z[2] & 0xffffu) | ((unsigned)z[3] << 16);
+          *reinterpret_cast<uint2*>(reinterpret_cast<int16_t*>(P.coef) + base) = make_uint2(lo, hi);
+        }
+      }
+    }
+  } while (cursor_next(c, P), c.s < c.s_end);
+}
+
+// ---------------------------------------------------------------------------
+// Exact DCT-II comparison transform, Y = C X C^T, operands rounded to BF16
+// or F16, FP32 accumulation.  Stage 2 runs transposed for row-wise stores.
+__device__ __forceinline__ float dct_c(int k, int m) {
+  const float a = k == 0 ? 0.25f : 0.35355339059327373f;
+  return a * cospif((float)((2 * m + 1) * k) / 32.0f);
+}
+
+template <int PREC>
+__device__ __forceinline__ unsigned pack2(float a, float b) {
+  if constexpr (PREC == ADCT16_F16) {
+    const _Float16 ha = (_Float16)a, hb = (_Float16)b;  // round to nearest
+    return (unsigned)__builtin_bit_cast(unsigned short, ha) | ((unsigned)__builtin_bit_cast(unsigned short, hb) << 16);
+  } else {
+    const __bf16 ha = (__bf16)a, hb = (__bf16)b;  // round to nearest
+    return (unsigned)__builtin_bit_cast(unsigned short, ha) | ((unsigned)__builtin_bit_cast(unsigned short, hb) << 16);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ f4 mma_p(uint2 a, uint2 b, f4 c) {
+  if constexpr (PREC == ADCT16_F16)
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a), __builtin_bit_cast(h4, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b), c, 0, 0, 0);
+}
+
+template <int IN, int PREC>
+__global__ __launch_bounds__(kGroupThreads) void k_dct(Params P, float* Y) {
+  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
+  // C[q][4g..4g+3] rounded to the operand type: stage-1 B (C^T) and stage-2 B.
+  const uint2 cq = make_uint2(pack2<PREC>(dct_c(q, 4 * g), dct_c(q, 4 * g + 1)),
+                              pack2<PREC>(dct_c(q, 4 * g + 2), dct_c(q, 4 * g + 3)));
+  StripCursor c;
+  if (!cursor_init(c, P)) return;
+  do {
+    const int y = min(c.sy * 16 + q, c.d.h - 1);
+    const int b0 = c.sxi * kStripBlocks;
+    const int nb = min(kStripBlocks, c.d.bx - b0);
+    const int64_t rowblk = c.d.block_begin + (int64_t)c.sy * c.d.bx + b0;
+    for (int b = 0; b < nb; ++b) {
+      const int x0 = (b0 + b) * 16 + 4 * g;
+      float xv[4];
+      if constexpr (IN == IN_U8) {
+        const unsigned xd = load_dword_u8(reinterpret_cast<const uint8_t*>(P.in), c.d, y, x0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) xv[m] = (float)((xd >> (8 * m)) & 0xffu) - 128.0f;
+      } else {
+        const int16_t* img = reinterpret_cast<const int16_t*>(P.in);
+        const int64_t off = c.d.offset + (int64_t)y * c.d.pitch;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) xv[m] = (float)img[off + min(x0 + m, c.d.w - 1)];
+      }
+      const uint2 a = make_uint2(pack2<PREC>(xv[0], xv[1]), pack2<PREC>(xv[2], xv[3]));
+      const f4 zero = {0, 0, 0, 0};
+      const f4 p = mma_p<PREC>(a, cq, zero);  // P[4g+v][q] = (X C^T)
+      const uint2 ph = make_uint2(pack2<PREC>(p[0], p[1]), pack2<PREC>(p[2], p[3]));
+      const f4 yt = mma_p<PREC>(ph, cq, zero);  // Y[q][4g+v]
+      *reinterpret_cast<float4*>(Y + (rowblk + b) * 256 + q * 16 + 4 * g) = make_float4(yt[0], yt[1], yt[2], yt[3]);
+    }
+  } while (cursor_next(c, P), c.s < c.s_end);
+}
+
+// ---------------------------------------------------------------------------
+#define ADCT16_MLAUNCH(kernel, grid, s, ...)                                           \
+  do {                                                                                 \
+    hipLaunchKernelGGL((kernel), dim3(grid), dim3(kGroupThreads), 0, (s), __VA_ARGS__); \
+    return hipGetLastError();                                                          \
+  } while (0)
+
+hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStream_t s) {
+  if (coef_kind == CF_I32) ADCT16_MLAUNCH((k_mfma_forward<CF_I32>), grid, s, P);
+  if (coef_kind == CF_I16C) ADCT16_MLAUNCH((k_mfma_forward<CF_I16C>), grid, s, P);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mfma_fused(bool zigzag, int out_kind, const Params& P, int grid, hipStream_t s) {
+  if (!zigzag && out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, OUT_U8>), grid, s, P);
+  if (!zigzag && out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, OUT_NONE>), grid, s, P);
+  if (zigzag && out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<true, OUT_U8>), grid, s, P);
+  if (zigzag && out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<true, OUT_NONE>), grid, s, P);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dct_mfma(int in_kind, int precision, const Params& P, float* y, int grid, hipStream_t s) {
+  if (in_kind == IN_U8 && precision == ADCT16_F16) ADCT16_MLAUNCH((k_dct<IN_U8, ADCT16_F16>), grid, s, P, y);
+  if (in_kind == IN_U8 && precision == ADCT16_BF16) ADCT16_MLAUNCH((k_dct<IN_U8, ADCT16_BF16>), grid, s, P, y);
+  if (in_kind == IN_I16 && precision == ADCT16_F16) ADCT16_MLAUNCH((k_dct<IN_I16, ADCT16_F16>), grid, s, P, y);
+  if (in_kind == IN_I16 && precision == ADCT16_BF16) ADCT16_MLAUNCH((k_dct<IN_I16, ADCT16_BF16>), grid, s, P, y);
+  return hipErrorInvalidValue;
+}
 
 }  // namespace adct16

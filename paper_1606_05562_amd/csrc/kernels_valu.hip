@@ -285,17 +285,6 @@ __device__ __forceinline__ void load_col(const void* buf, int64_t blk, int x, bo
 }
 
 // ---------------------------------------------------------------------------
-// SSE accumulation per wavefront, flushed with one 64-bit atomic per image.
-struct SseAcc {
-  unsigned long long lane = 0;
-  __device__ __forceinline__ void flush(unsigned long long* sse, int img) {
-    const unsigned long long t = wave_sum_u64(lane);
-    if ((threadIdx.x & 63) == 0 && t) atomicAdd(sse + img, t);
-    lane = 0;
-  }
-};
-
-// ---------------------------------------------------------------------------
 // Kernels.
 
 template <int IN, int CF>

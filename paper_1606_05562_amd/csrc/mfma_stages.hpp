@@ -1,0 +1,133 @@
+// Matrix-core stages of the 16x16 round trip (see kernels_mfma.hip for the
+// exactness argument).
+#pragma once
+
+#include "device_common.hpp"
+
+namespace adct16 {
+
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
+
+// Section 2: the matrix T.
+__constant__ signed char kT[16][16] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {1, 1, 1, 1, 1, 1, 1, 1, -1, -1, -1, -1, -1, -1, -1, -1},
+    {1, 1, 1, 0, 0, -1, -1, -1, -1, -1, -1, 0, 0, 1, 1, 1},
+    {1, 1, 0, 0, 0, 0, -1, -1, 1, 1, 0, 0, 0, 0, -1, -1},
+    {1, 0, 0, -1, -1, 0, 0, 1, 1, 0, 0, -1, -1, 0, 0, 1},
+    {1, 1, -1, -1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1},
+    {1, 0, -1, -1, 1, 1, 0, -1, -1, 0, 1, 1, -1, -1, 0, 1},
+    {0, 0, -1, 1, 1, -1, -1, 1, -1, 1, 1, -1, -1, 1, 0, 0},
+    {1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1},
+    {1, -1, -1, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 1, 1, -1},
+    {1, -1, 0, 1, -1, 0, 1, -1, -1, 1, 0, -1, 1, 0, -1, 1},
+    {0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 0, 0},
+    {0, -1, 1, 0, 0, 1, -1, 0, 0, -1, 1, 0, 0, 1, -1, 0},
+    {1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1},
+    {0, -1, 1, -1, 1, -1, 1, 0, 0, 1, -1, 1, -1, 1, -1, 0},
+    {1, -1, 0, 0, -1, 1, -1, 1, -1, 1, -1, 1, 0, 0, 1, -1},
+};
+// w_u = 48 / n_u with n = diag(T T^T).
+__constant__ signed char kW[16] = {3, 3, 4, 6, 6, 3, 4, 4, 3, 4, 4, 6, 6, 4, 4, 4};
+
+__device__ __forceinline__ unsigned h2bits(float lo, float hi) {
+  return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(lo, hi));
+}
+
+// Pack two fp16-exact values.
+__device__ __forceinline__ unsigned pack_h(float lo, float hi) { return h2bits(lo, hi); }
+
+// b = z - a for the two halves of the fp16 pair a (a = fp16_rtz(z)).  The
+// differences are exact in fp32 and fp16-representable (|b| below the fp16
+// step of a), so the repacking is exact too.
+__device__ __forceinline__ unsigned residual_pair(unsigned a, float z0, float z1) {
+  const fp16x2 ah = __builtin_bit_cast(fp16x2, a);
+  return h2bits(z0 - (float)ah[0], z1 - (float)ah[1]);
+}
+
+__device__ __forceinline__ f4 mma16(uint2 a, uint2 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a), __builtin_bit_cast(h4, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f4 mma32(uint4 a, uint4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+}
+
+// Per-lane constant operands of the round trip.
+struct MfmaConsts {
+  uint2 tq;      // T[q][4g..4g+3] with row q zeroed when q is not retained (stage-1 B, stage-2 A)
+  float c1;      // stage-1 accumulator start: -18432 in column 0
+  uint4 w3;      // stage-3 B: w_u T[u][q] 2^-11 for u = 4g..4g+3, twice (one per digit)
+  uint2 w4;      // stage-4 A: w_f T[f][q] for f = 4g..4g+3
+  f4 c4;         // stage-4 accumulator start: -1536 sum_f w_f T[f][j], j = 4g+v
+};
+
+__device__ __forceinline__ MfmaConsts make_consts(int q, int g, int r_sep) {
+  MfmaConsts k;
+  const bool keep_q = q < r_sep;
+  float t[4], w3[4], w4[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int kk = 4 * g + m;
+    t[m] = keep_q ? (float)kT[q][kk] : 0.0f;
+    w3[m] = (float)(kW[kk] * kT[kk][q]) * (1.0f / 2048.0f);
+    w4[m] = (float)(kW[kk] * kT[kk][q]);
+  }
+  k.tq = make_uint2(pack_h(t[0], t[1]), pack_h(t[2], t[3]));
+  k.c1 = (q == 0) ? -18432.0f : 0.0f;
+  const unsigned w30 = pack_h(w3[0], w3[1]), w31 = pack_h(w3[2], w3[3]);
+  k.w3 = make_uint4(w30, w31, w30, w31);
+  k.w4 = make_uint2(pack_h(w4[0], w4[1]), pack_h(w4[2], w4[3]));
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int j = 4 * g + v;
+    int s = 0;
+    for (int f = 0; f < 16; ++f) s += kW[f] * kT[f][j];
+    k.c4[v] = -1536.0f * (float)s;
+  }
+  return k;
+}
+
+// 4 pixels (one dword) -> (x + 1024) as 4 fp16 values.
+__device__ __forceinline__ uint2 bytes_to_h4(unsigned x) {
+  return make_uint2(__builtin_amdgcn_perm(0x64646464u, x, 0x04010400u),
+                    __builtin_amdgcn_perm(0x64646464u, x, 0x04030402u));
+}
+
+// Forward stages 1-2 for one block: returns Z_c[4g+v][q] (fp32, exact).
+__device__ __forceinline__ f4 fwd_block(unsigned xdw, const MfmaConsts& k) {
+  const f4 c1 = {k.c1, k.c1, k.c1, k.c1};
+  const f4 p = mma16(bytes_to_h4(xdw), k.tq, c1);                 // P_c[4g+v][q]
+  const uint2 ph = make_uint2(pack_h(p[0], p[1]), pack_h(p[2], p[3]));
+  const f4 zero = {0, 0, 0, 0};
+  return mma16(k.tq, ph, zero);                                    // Z_c[4g+v][q]
+}
+
+// Inverse stages 3-4 from Z_c (already masked); returns s[v] = N[q][4g+v] / 2048.
+__device__ __forceinline__ f4 inv_block(f4 z, const MfmaConsts& k) {
+  const unsigned a0 = h2bits(z[0], z[1]), a1 = h2bits(z[2], z[3]);
+  const unsigned b0 = residual_pair(a0, z[0], z[1]), b1 = residual_pair(a1, z[2], z[3]);
+  const f4 c3 = {1536.0f, 1536.0f, 1536.0f, 1536.0f};
+  const f4 u = mma32(make_uint4(a0, a1, b0, b1), k.w3, c3);       // 1536 + U[q][4g+v] 2^-11
+  const unsigned A0 = h2bits(u[0], u[1]), A1 = h2bits(u[2], u[3]);
+  const unsigned B0 = residual_pair(A0, u[0], u[1]), B1 = residual_pair(A1, u[2], u[3]);
+  const f4 sa = mma16(k.w4, make_uint2(A0, A1), k.c4);
+  return mma16(k.w4, make_uint2(B0, B1), sa);
+}
+
+__device__ __forceinline__ unsigned round_pack(f4 s) {
+  constexpr float c = 8.0f / 9.0f;           // fl32(2048 / 2304)
+  constexpr float off = 128.0f + 1.0f / 4096.0f;
+  unsigned r = 0;
+  r = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_fmaf(s[0], c, off), 0, r);
+  r = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_fmaf(s[1], c, off), 1, r);
+  r = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_fmaf(s[2], c, off), 2, r);
+  r = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_fmaf(s[3], c, off), 3, r);
+  return r;
+}
+
+}  // namespace adct16

@@ -1,0 +1,163 @@
+"""Matrix-core forms: the int-exact FP16 contractions must be bit-exact with
+the oracle (and therefore with the adder kernel); the exact DCT-II on BF16 /
+F16 operands is compared with the float64 DCT within an error bound derived
+from the operand rounding."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import codec
+from oracle import transform as tf
+from synth import BASE_SEED, luma_batch, mixed_image, random_blocks_u8
+
+from batch_util import Batch
+from test_gpu_parity import _images_u8
+
+pytestmark = pytest.mark.gpu
+
+
+def A():
+    import paper_1606_05562_amd as mod
+    return mod
+
+
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def batch_u8():
+    return Batch(_images_u8())
+
+
+@pytest.fixture(scope="module")
+def batch_worst():
+    # uniformly random blocks plus sign patterns of every pair of rows of T
+    # (the blocks that reach the extreme coefficients)
+    rnd = random_blocks_u8(BASE_SEED + 11, 1024)
+    t = tf.T
+    pats = [np.where(np.outer(t[u], t[v]) > 0, 255, 0).astype(np.uint8) for u in range(16) for v in range(16)]
+    pats += [255 - p for p in pats]
+    blocks = np.concatenate([rnd, np.stack(pats)])            # 1536 blocks
+    img = blocks.reshape(24, 64, 16, 16).transpose(0, 2, 1, 3).reshape(24 * 16, 64 * 16)
+    return Batch([img])
+
+
+@pytest.mark.parametrize("cd", ["i32", "i16"])
+def test_mfma_forward_bit_exact(batch_u8, cd):
+    T = torch()
+    plan = batch_u8.plan(coef_dtype=A().I32 if cd == "i32" else A().I16, backend=A().BACKEND_MFMA)
+    coef = batch_u8.coef_tensor(T.int32 if cd == "i32" else T.int16)
+    plan.forward(batch_u8.dev, coef)
+    T.cuda.synchronize()
+    for got, im in zip(batch_u8.split_coef(coef), batch_u8.images):
+        want = codec.forward_image(im)
+        if cd == "i16":
+            want = want.copy()
+            want[:, 0, 0] -= 32768
+        assert np.array_equal(got.astype(np.int64), want)
+
+
+def _fused(batch, backend, qmode, r):
+    T = torch()
+    plan = batch.plan(coef_dtype=A().I32, qmode=qmode, r=r, backend=backend)
+    out = batch.empty_like_images(np.uint8, 1)
+    sse = T.zeros(len(batch.images), dtype=T.int64, device="cuda")
+    psnr = T.zeros(len(batch.images), dtype=T.float64, device="cuda")
+    plan.compress_and_measure(batch.dev, out, None, sse, psnr)
+    T.cuda.synchronize()
+    return batch.unpack(out), sse.cpu().numpy(), psnr.cpu().numpy()
+
+
+CASES = [(1, r) for r in (1, 2, 3, 5, 8, 9, 12, 16)] + [(0, 16)] + [(2, r) for r in (1, 16, 100, 181, 256)]
+
+
+@pytest.mark.parametrize("qmode,r", CASES)
+def test_mfma_fused_bit_exact(batch_u8, qmode, r):
+    keep = {0: codec.mask_none(), 1: codec.mask_zonal(r), 2: codec.mask_zigzag(r)}[qmode]
+    recs, sse, psnr = _fused(batch_u8, A().BACKEND_MFMA, qmode, r)
+    for i, (got, im) in enumerate(zip(recs, batch_u8.images)):
+        want, s, p = codec.compress_kept(im, keep)
+        assert np.array_equal(got, want), f"image {i}"
+        assert sse[i] == s
+        assert (math.isinf(p) and math.isinf(psnr[i])) or abs(psnr[i] - p) <= 1e-3
+
+
+@pytest.mark.parametrize("qmode,r", [(1, 8), (1, 16), (2, 181), (1, 1)])
+def test_mfma_equals_adder_kernel_on_extremes(batch_worst, qmode, r):
+    a = _fused(batch_worst, A().BACKEND_MFMA, qmode, r)
+    b = _fused(batch_worst, A().BACKEND_VALU, qmode, r)
+    assert np.array_equal(a[0][0], b[0][0]) and np.array_equal(a[1], b[1])
+    keep = {1: codec.mask_zonal(r), 2: codec.mask_zigzag(r)}[qmode]
+    want, s, _ = codec.compress_kept(batch_worst.images[0], keep)
+    assert np.array_equal(a[0][0], want) and a[1][0] == s
+
+
+def test_mfma_ragged():
+    rng = np.random.default_rng(21)
+    sizes = [(int(x), int(y)) for x, y in rng.integers(16, 300, size=(7, 2))]
+    ims = [mixed_image(BASE_SEED + 4, k, h, w) for k, (h, w) in enumerate(sizes)]
+    b = Batch(ims)
+    recs, sse, _ = _fused(b, A().BACKEND_MFMA, A().Q_ZONAL, 8)
+    for i, (got, im) in enumerate(zip(recs, ims)):
+        want, s, _ = codec.compress_kept(im, codec.mask_zonal(8))
+        assert np.array_equal(got, want) and sse[i] == s
+
+
+def test_mfma_full_size_sampled():
+    T = torch()
+    mod = A()
+    n, h, w = 256, 1088, 1920
+    frames = luma_batch(BASE_SEED + 2, n, h, w)
+    dev = T.from_numpy(frames.reshape(-1)).cuda()
+    plan = mod.Plan([h] * n, [w] * n, [w] * n, [i * h * w for i in range(n)], in_dtype=mod.U8,
+                    coef_dtype=mod.I32, qmode=mod.Q_ZONAL, r=8, backend=mod.BACKEND_MFMA)
+    out = T.empty_like(dev)
+    sse = T.zeros(n, dtype=T.int64, device="cuda")
+    plan.compress_and_measure(dev, out, None, sse, None)
+    T.cuda.synchronize()
+    for t in (3, 200):
+        got = out[t * h * w:(t + 1) * h * w].cpu().numpy().reshape(h, w)
+        want, s, _ = codec.compress_kept(frames[t], codec.mask_zonal(8))
+        assert np.array_equal(got, want) and int(sse[t]) == s
+    ref = mod.Plan([h] * n, [w] * n, [w] * n, [i * h * w for i in range(n)], in_dtype=mod.U8,
+                   coef_dtype=mod.I32, qmode=mod.Q_ZONAL, r=8, backend=mod.BACKEND_VALU)
+    out2 = T.empty_like(dev)
+    sse2 = T.zeros(n, dtype=T.int64, device="cuda")
+    ref.compress_and_measure(dev, out2, None, sse2, None)
+    T.cuda.synchronize()
+    assert T.equal(out, out2) and T.equal(sse, sse2)
+
+
+# ----------------------------------------------------------------------------
+# Exact DCT-II on BF16 / F16 operands (comparison transform).
+
+def _dct_bound(xc, eps):
+    """|Y_gpu - C Xc C^T| <= ((1+eps)^3 - 1 + 2^-20) |C| |Xc| |C|^T elementwise:
+    C rounded once (both sides), the row-pass result rounded once, FP32
+    accumulation error far below the operand rounding."""
+    c = np.abs(tf.dct_matrix())
+    mag = c @ np.abs(xc) @ c.T
+    return ((1 + eps) ** 3 - 1 + 2.0 ** -20) * mag
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_dct_mfma_error_bound(batch_u8, prec):
+    T = torch()
+    mod = A()
+    plan = batch_u8.plan(coef_dtype=mod.I32)
+    y = batch_u8.coef_tensor(T.float32)
+    plan.dct_forward(batch_u8.dev, y, mod.F16 if prec == "f16" else mod.BF16)
+    T.cuda.synchronize()
+    eps = 2.0 ** -11 if prec == "f16" else 2.0 ** -8
+    worst_abs, worst_rel = 0.0, 0.0
+    for got, im in zip(batch_u8.split_coef(y), batch_u8.images):
+        xc = codec.image_to_blocks(im).astype(np.float64) - 128.0
+        ref = tf.dct_forward(xc)
+        err = np.abs(got - ref)
+        assert np.all(err <= _dct_bound(xc, eps))
+        worst_abs = max(worst_abs, float(err.max()))
+        worst_rel = max(worst_rel, float(err.max() / max(1.0, np.abs(ref).max())))
+    print(f"DCT-II {prec}: max abs error {worst_abs:.4g}, relative to max|Y| {worst_rel:.3g}")

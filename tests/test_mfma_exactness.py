@@ -1,0 +1,50 @@
+"""Host-side proofs of the preconditions the matrix-core kernels rely on for
+bit-exactness (see the header of kernels_mfma.hip): worst-case ranges of
+every intermediate over all 8-bit blocks and all retention masks, and the
+float32 rounding of the final numerator."""
+import numpy as np
+
+from oracle import codec
+from oracle import transform as tf
+
+
+def _box_max(K, lo=-128, hi=127):
+    pos = np.where(K > 0, K, 0)
+    neg = np.where(K < 0, K, 0)
+    mx = (pos * hi + neg * lo).sum(axis=(-2, -1))
+    mn = (pos * lo + neg * hi).sum(axis=(-2, -1))
+    return float(np.maximum(np.abs(mx), np.abs(mn)).max())
+
+
+def test_intermediate_ranges_all_masks():
+    T = tf.T.astype(np.float64)
+    w = tf.inverse_weights().astype(np.float64)
+    KP = np.einsum("fb,ia->ifab", T, np.eye(16))           # P = Xc T^T
+    KZ = np.einsum("ua,vb->uvab", T, T)                    # Z = T Xc T^T
+    assert _box_max(KP) <= 2048                            # fp16-exact
+    assert _box_max(KZ) <= 32768
+    masks = [codec.mask_none()] + [codec.mask_zonal(r) for r in range(1, 17)] + \
+            [codec.mask_zigzag(r) for r in range(1, 257)]
+    umax = nmax = 0.0
+    for M in masks:
+        KU = np.einsum("u,ui,uf,ufab->ifab", w, T, M.astype(float), KZ)
+        KN = np.einsum("f,fj,ifab->ijab", w, T, KU)
+        umax = max(umax, _box_max(KU))
+        nmax = max(nmax, _box_max(KN))
+    # 1536 + U 2^-11 must stay inside [1024, 2048), where fp16 steps by 1.
+    assert umax / 2048 < 512
+    # N 2^-11 (with the stage-4 partial sums) must stay below 1024 so that a
+    # multiple of 2^-11 is exact in float32; N itself far below 2^24.
+    assert nmax / 2048 + 96 < 1024 and nmax < 2**24
+    assert umax == 212544 and nmax == 1648452
+
+
+def test_final_rounding_is_exact():
+    n = np.arange(-1648452, 1648453, dtype=np.int64)
+    s = n.astype(np.longdouble) / 2048                      # exact in float32 too
+    c = np.longdouble(np.float32(8.0 / 9.0))
+    off = np.longdouble(np.float32(128.0 + 1.0 / 4096.0))
+    t = (s * c + off).astype(np.float32)                    # one rounding: the FMA
+    got = np.clip(np.rint(t), 0, 255).astype(np.int64)      # cvt_pk_u8: nearest-even, saturating
+    want = np.clip(np.floor_divide(n + 1152, 2304) + 128, 0, 255)
+    assert np.array_equal(got, want)
