@@ -15,6 +15,19 @@ constexpr int kStripBlocks = 8;
 constexpr int kWavesPerGroup = 4;
 constexpr int kGroupThreads = 64 * kWavesPerGroup;
 
+// Minimum resident workgroups per CU requested from the compiler for the
+// fused kernels (bounds their VGPR use); tuned on the target.
+#ifndef ADCT16_VALU_MIN_WG
+#define ADCT16_VALU_MIN_WG 1
+#endif
+#ifndef ADCT16_MFMA_MIN_WG
+#define ADCT16_MFMA_MIN_WG 1
+#endif
+// Blocks of a strip carried through the matrix-core stages together.
+#ifndef ADCT16_MFMA_BATCH
+#define ADCT16_MFMA_BATCH 8
+#endif
+
 struct ImageDesc {
   int64_t offset;       // element offset of row 0 in the packed image buffer
   int64_t block_begin;  // index of the image's first block in coefficient buffers

@@ -200,7 +200,7 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
   float best = 1e30f;
   std::vector<int> backends = {ADCT16_BACKEND_VALU};
   if (mfma_supported(p)) backends.push_back(ADCT16_BACKEND_MFMA);
-  const int cands[] = {1, 2, 3, 4, 6, 8};
+  const int cands[] = {2, 4, 6, 8, 12};
   adct16_status st = ADCT16_OK;
   for (int b : backends) {
     for (int w : cands) {

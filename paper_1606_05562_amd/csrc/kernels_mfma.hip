@@ -47,21 +47,26 @@ __device__ __forceinline__ unsigned load_dword_u8(const uint8_t* img, const Imag
   return r;
 }
 
-// Reconstruct the 8 blocks of a strip from their dwords (all lanes busy).
+// Reconstruct the 8 blocks of a strip from their dwords (all lanes busy),
+// ADCT16_MFMA_BATCH blocks at a time.
 template <bool ZIGZAG>
 __device__ __forceinline__ void roundtrip8(const unsigned (&x)[kStripBlocks], unsigned (&out)[kStripBlocks],
                                            const MfmaConsts& k, const bool (&keepz)[4]) {
-  f4 z[kStripBlocks];
+  constexpr int NB = ADCT16_MFMA_BATCH;
 #pragma unroll
-  for (int b = 0; b < kStripBlocks; ++b) {
-    z[b] = fwd_block(x[b], k);
-    if constexpr (ZIGZAG) {
+  for (int b0 = 0; b0 < kStripBlocks; b0 += NB) {
+    f4 z[NB];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) z[b][v] = keepz[v] ? z[b][v] : 0.0f;
+    for (int b = 0; b < NB; ++b) {
+      z[b] = fwd_block(x[b0 + b], k);
+      if constexpr (ZIGZAG) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) z[b][v] = keepz[v] ? z[b][v] : 0.0f;
+      }
     }
-  }
 #pragma unroll
-  for (int b = 0; b < kStripBlocks; ++b) out[b] = round_pack(inv_block(z[b], k));
+    for (int b = 0; b < NB; ++b) out[b0 + b] = round_pack(inv_block(z[b], k));
+  }
 }
 
 __device__ __forceinline__ unsigned sse4(unsigned a, unsigned r) {
@@ -69,8 +74,42 @@ __device__ __forceinline__ unsigned sse4(unsigned a, unsigned r) {
          2u * __builtin_amdgcn_udot4(a, r, 0u, false);
 }
 
+// Interior strips are read with one 16-byte load per lane per 4 blocks
+// (lane 16g+q: row q of block 4h+g), prefetched one strip ahead, and turned
+// into the operand layout (lane 16g+q: dword g of row q of each block) by a
+// 4x4 dword transpose through LDS (conflict-free: consecutive lanes touch
+// consecutive dwords on both sides).
+__device__ __forceinline__ void rows_to_operands(int* lds, int g, int q, const uint4 (&r)[2],
+                                                 unsigned (&x)[kStripBlocks]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int4* w = reinterpret_cast<int4*>(lds + (g * 16 + q) * 4);
+    *w = make_int4((int)r[h].x, (int)r[h].y, (int)r[h].z, (int)r[h].w);
+    wave_lds_sync();
+#pragma unroll
+    for (int b = 0; b < 4; ++b) x[4 * h + b] = (unsigned)lds[(b * 16 + q) * 4 + g];
+    wave_lds_sync();
+  }
+}
+
+// The inverse transpose: lane 16g+q ends with row q of blocks g and 4+g.
+__device__ __forceinline__ void operands_to_rows(int* lds, int g, int q, const unsigned (&o)[kStripBlocks],
+                                                 uint4 (&r)[2]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) lds[(b * 16 + q) * 4 + g] = (int)o[4 * h + b];
+    wave_lds_sync();
+    const int4 v = *reinterpret_cast<const int4*>(lds + (g * 16 + q) * 4);
+    r[h] = make_uint4((unsigned)v.x, (unsigned)v.y, (unsigned)v.z, (unsigned)v.w);
+    wave_lds_sync();
+  }
+}
+
 template <bool ZIGZAG, int OUT>
-__global__ __launch_bounds__(kGroupThreads) void k_mfma_fused(Params P) {
+__global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fused(Params P) {
+  __shared__ int lds_all[kWavesPerGroup * 256];
+  int* lds = lds_all + (threadIdx.x >> 6) * 256;
   const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
   const MfmaConsts k = make_consts(q, g, P.tables->rsep);
   bool keepz[4];
@@ -82,25 +121,48 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_fused(Params P) {
   if (!cursor_init(c, P)) return;
   SseAcc acc;
   int since_flush = 0;
+  // Prefetch state: rows of the next interior strip.
+  auto interior = [&](const StripCursor& cc) { return (cc.sxi * kStripBlocks + kStripBlocks) * 16 <= cc.d.w; };
+  auto row_off = [&](const StripCursor& cc) {
+    return cc.d.offset + (int64_t)min(cc.sy * 16 + q, cc.d.h - 1) * cc.d.pitch + cc.sxi * kStripBlocks * 16;
+  };
+  uint4 nr[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+  if (interior(c)) {
+    const uint4* src = reinterpret_cast<const uint4*>(in + row_off(c));
+    nr[0] = src[g];
+    nr[1] = src[4 + g];
+  }
   for (;;) {
     const int y0 = c.sy * 16;
     const int y = min(y0 + q, c.d.h - 1);
     const bool rowok = (y0 + q) < c.d.h;
     const int b0 = c.sxi * kStripBlocks;
     const int64_t off = c.d.offset + (int64_t)y * c.d.pitch;
+    const bool full = interior(c);
+    const uint4 cr[2] = {nr[0], nr[1]};
+    const ImageDesc d = c.d;
+    const int img = c.img;
+    const bool changed = cursor_next(c, P);
+    const bool done = c.s >= c.s_end;
+    if (!done && interior(c)) {  // prefetch the next strip
+      const uint4* src = reinterpret_cast<const uint4*>(in + row_off(c));
+      nr[0] = src[g];
+      nr[1] = src[4 + g];
+    }
     unsigned x[kStripBlocks], out[kStripBlocks];
-    if ((b0 + kStripBlocks) * 16 <= c.d.w) {
-      // Interior strip: eight whole blocks, no per-block tests.
-      const uint8_t* src = in + off + b0 * 16 + 4 * g;
-#pragma unroll
-      for (int b = 0; b < kStripBlocks; ++b) x[b] = *reinterpret_cast<const unsigned*>(src + 16 * b);
+    if (full) {
+      rows_to_operands(lds, g, q, cr, x);
       roundtrip8<ZIGZAG>(x, out, k, keepz);
-      if (rowok) {
-        if constexpr (OUT == OUT_U8) {
-          uint8_t* dst = outp + off + b0 * 16 + 4 * g;
-#pragma unroll
-          for (int b = 0; b < kStripBlocks; ++b) *reinterpret_cast<unsigned*>(dst + 16 * b) = out[b];
+      if constexpr (OUT == OUT_U8) {
+        uint4 rows[2];
+        operands_to_rows(lds, g, q, out, rows);
+        if (rowok) {
+          uint4* dst = reinterpret_cast<uint4*>(outp + off + b0 * 16);
+          dst[g] = rows[0];
+          dst[4 + g] = rows[1];
         }
+      }
+      if (rowok) {
         unsigned s = 0;
 #pragma unroll
         for (int b = 0; b < kStripBlocks; ++b) s += sse4(x[b], out[b]);
@@ -109,16 +171,16 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_fused(Params P) {
     } else {
       // Right-edge strip: fewer blocks and / or a partial last block
       // (columns past the width repeat the last one).
-      const int nb = min(kStripBlocks, c.d.bx - b0);
+      const int nb = min(kStripBlocks, d.bx - b0);
 #pragma unroll
       for (int b = 0; b < kStripBlocks; ++b)
-        x[b] = b < nb ? load_dword_u8(in, c.d, y, (b0 + b) * 16 + 4 * g) : 0u;
+        x[b] = b < nb ? load_dword_u8(in, d, y, (b0 + b) * 16 + 4 * g) : 0u;
       roundtrip8<ZIGZAG>(x, out, k, keepz);
       if (rowok) {
 #pragma unroll
         for (int b = 0; b < kStripBlocks; ++b) {
           const int x0 = (b0 + b) * 16 + 4 * g;
-          const int n = b < nb ? min(4, c.d.w - x0) : 0;
+          const int n = b < nb ? min(4, d.w - x0) : 0;
           if (n > 0) {
             if constexpr (OUT == OUT_U8) {
               uint8_t* o = outp + off + x0;
@@ -131,9 +193,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_fused(Params P) {
         }
       }
     }
-    const int img = c.img;
-    const bool changed = cursor_next(c, P);
-    const bool done = c.s >= c.s_end;
     if (changed || done || ++since_flush == 1024) {
       acc.flush(P.sse, img);
       since_flush = 0;

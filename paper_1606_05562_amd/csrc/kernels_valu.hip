@@ -413,7 +413,7 @@ __device__ __forceinline__ void recon_i16(const int (&t)[16], const double (&f)[
 }
 
 template <int IN, int MODE, int QOUT, int OUT>
-__global__ __launch_bounds__(kGroupThreads) void k_fused(Params P) {
+__global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Params P) {
   __shared__ int lds_all[kWavesPerGroup * kWaveLds];
   int* lds = lds_all + (threadIdx.x >> 6) * kWaveLds;
   const int lane = threadIdx.x & 63, x = lane & 15, p = lane >> 4;
