@@ -1,17 +1,20 @@
 """Throughput of the 16x16 approximate-DCT hot path on one MI355X.
 
-Workload (default): 256 synthetic luma frames of 1920x1088 uint8 (AR(1)
+Default workload: 256 synthetic luma frames of 1920x1088 uint8 (AR(1)
 fields, rho = 0.95, plus 8 translating 64x64 flat rectangles per frame).
 One step = one adct16_compress_and_measure call over the whole batch:
-forward transform (Eq. (1) butterflies) -> zonal retention of the top-left
-r x r coefficients -> exact inverse -> reconstruction written to HBM ->
-per-frame SSE and PSNR.  Inputs are resident in HBM before timing starts.
+forward transform -> zonal retention of the top-left r x r coefficients ->
+exact inverse -> reconstruction written to HBM -> per-frame SSE and PSNR.
+Inputs are resident in HBM before timing starts.
 
-Prints one JSON line (see the contract in the repository documentation).
+    python bench.py [--steps K] [--warmup W] [--workload luma|ragged|residual]
+
+Prints one JSON line.  --gpus N > 1 is refused (one-GPU build).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 N_FRAMES, H, W = 256, 1088, 1920
+COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_hbm_counters.json")
 
 
 def _parse():
@@ -31,15 +35,27 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["luma", "ragged", "residual"], default="luma")
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--backend", choices=["auto", "valu", "mfma"], default="auto")
-    ap.add_argument("--frames", type=int, default=N_FRAMES)
+    ap.add_argument("--frames", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=128)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run one plain device copy of the input size (for HBM counter scaling)")
+                    help="also run one plain device copy of the input size (HBM counter scaling)")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    csrc = os.path.join(ROOT, "paper_1606_05562_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
 
 
 def _events_ms(fn, reps, stream):
@@ -54,32 +70,49 @@ def _events_ms(fn, reps, stream):
     return e0.elapsed_time(e1) / reps
 
 
-def _cpu_baseline(frames, r, n):
+def _traffic(kernel_name: str):
+    """HBM bytes per launch of the fused kernel from committed rocprofv3 PMC
+    runs (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter
+    reads for a plain device copy of known size); None if the kernel
+    sources changed since the counters were taken."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except OSError:
+        return None
+    if c.get("source_sha256") != kernel_source_hash() or c.get("kernel") != kernel_name:
+        return None
+    copy_kib = c["copy_bytes"] / 1024.0
+    fetch = c["fetch_kib"] * copy_kib / c["copy_fetch_kib"]
+    write = c["write_kib"] * copy_kib / c["copy_write_kib"]
+    return (fetch + write) * 1024.0
+
+
+def _cpu_baseline(frames, keep_r, n):
     """The oracle, as it stands, on the first n frames, one frame per thread."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import codec
-    keep = codec.mask_zonal(r)
+    keep = codec.mask_zonal(keep_r)
     cores = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
     with ThreadPoolExecutor(cores) as ex:
         list(ex.map(lambda t: codec.compress_kept(frames[t], keep), range(n)))
     dt = time.perf_counter() - t0
-    return {"value": round(n * H * W / dt / 1e9, 6), "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} of the {N_FRAMES} frames (fwd + zonal r={r} + inverse + PSNR), {dt:.1f} s wall"}
+    h, w = frames.shape[1:]
+    return {"value": round(n * h * w / dt / 1e9, 6), "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} of the {len(frames)} frames, forward + zonal r={keep_r} + inverse + PSNR "
+                      f"({dt:.1f} s wall on {cores} threads)"}
 
 
-def main():
-    args = _parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported "
-                                   "(blocks, images and frames are independent: shard frames per GPU)"}))
-        sys.exit(2)
-    import torch
+def _fused_kernel_name(plan_info):
+    if plan_info["backend"] == "mfma":
+        return "k_mfma_fused<false, true, 1>"
+    return "k_fused<0, 0, 5, 1>"
 
-    import paper_1606_05562_amd as A
+
+def bench_luma(args, A, torch):
     from synth import BASE_SEED, luma_batch
-
-    n = args.frames
+    n = args.frames or N_FRAMES
     frames = luma_batch(BASE_SEED + 2, n, H, W)
     dev = torch.from_numpy(frames.reshape(-1)).cuda()
     out = torch.empty_like(dev)
@@ -87,9 +120,13 @@ def main():
     psnr = torch.zeros(n, dtype=torch.float64, device="cuda")
     offs = [i * H * W for i in range(n)]
     backend = {"auto": A.BACKEND_AUTO, "valu": A.BACKEND_VALU, "mfma": A.BACKEND_MFMA}[args.backend]
-    plan = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32,
-                  qmode=A.Q_ZONAL, r=args.r, backend=backend,
-                  flags=A.FLAG_AUTOTUNE if backend == A.BACKEND_AUTO else 0)
+
+    def make(be, r=args.r, flags=0):
+        return A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32,
+                      qmode=A.Q_ZONAL, r=r, backend=be, flags=flags)
+
+    plan = make(backend, flags=A.FLAG_AUTOTUNE if backend == A.BACKEND_AUTO else 0)
+    info = json.loads(plan.info())
     stream = torch.cuda.current_stream()
     step = lambda: plan.compress_and_measure(dev, out, None, sse, psnr)
     for _ in range(args.warmup):
@@ -102,15 +139,18 @@ def main():
     npx = n * H * W
     value = npx / (ms * 1e-3) / 1e9
 
-    # Dominant kernel: the fused persistent kernel (plus the tiny SSE clear),
-    # timed on its own stream without the PSNR finalisation.
+    # Dominant kernel: the fused persistent kernel (plus a 1-thread-per-image
+    # clear of the SSE accumulators), timed on the launch stream.
     kms = _events_ms(lambda: plan.compress_and_measure(dev, out, None, sse, None), args.steps, stream)
-    alg_bytes = 2 * npx  # read 8-bit input, write 8-bit reconstruction
+    alg_bytes = 2 * npx  # read the 8-bit input once, write the 8-bit reconstruction once
     achieved = alg_bytes / (kms * 1e-3) / 1e9
-
+    kname = _fused_kernel_name(info)
+    traffic = _traffic(kname)
     if args.calibrate_copy:
         torch.cuda.synchronize()
         out.copy_(dev)  # plain copy kernel: reads npx bytes, writes npx bytes
+        torch.cuda.synchronize()
+        step()
         torch.cuda.synchronize()
     res = {
         "metric": "Gpixel/s 2D fwd+quant+inv 16x16 (MFMA vs VALU), % HBM peak, bit-exact",
@@ -118,52 +158,134 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "wall_ms_per_step": round(wall, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"{n} luma frames {W}x{H} uint8, AR(1) rho=0.95 + 8 moving 64x64 rectangles; "
-                               f"fused forward -> zonal r={args.r} -> inverse -> recon -> per-frame PSNR",
-                   "frames": n, "height": H, "width": W, "r": args.r, "plan": json.loads(plan.info())},
+        "config": {"workload": f"{n} luma frames {W}x{H} uint8 (AR(1) rho=0.95 + 8 moving 64x64 flat "
+                               f"rectangles): forward -> zonal r={args.r} -> inverse -> reconstruction -> "
+                               f"per-frame PSNR, one fused launch",
+                   "frames": n, "height": H, "width": W, "r": args.r, "plan": info},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_fused<IN_U8,MODE_MASK,CF_NONE,OUT_U8>", "kernel_ms": round(kms, 4)},
-        "psnr_mean_db": round(float(psnr[torch.isfinite(psnr)].mean()), 4) if n else None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": round(traffic / 1e9, 4) if traffic else None,
+                     "traffic_unit": "GB per launch", "algorithmic_bytes": alg_bytes,
+                     "kernel": kname, "kernel_ms": round(kms, 4)},
+        "psnr_mean_db": round(float(psnr[torch.isfinite(psnr)].mean()), 4),
     }
     if not args.no_variants:
-        variants = {}
-        for name, be in (("valu", A.BACKEND_VALU), ("mfma", A.BACKEND_MFMA)):
-            try:
-                p2 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32,
-                            qmode=A.Q_ZONAL, r=args.r, backend=be)
-            except A.Adct16Error as e:
-                variants[name] = f"unavailable: {e}"
-                continue
-            f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)
-            f()
-            vms = _events_ms(f, max(3, args.steps // 2), stream)
-            variants[f"fused_{name}_gpix_s"] = round(npx / (vms * 1e-3) / 1e9, 4)
+        v = {}
+        for name, be, fl in (("valu", A.BACKEND_VALU, 0), ("mfma", A.BACKEND_MFMA, 0),
+                             ("mfma_explicit_coef", A.BACKEND_MFMA, A.FLAG_EXPLICIT_COEF)):
+            for r in (args.r, 16):
+                p2 = make(be, r=r, flags=A.FLAG_AUTOTUNE | fl)
+                f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)
+                f()
+                vms = _events_ms(f, max(3, args.steps // 2), stream)
+                v[f"fused_{name}_r{r}_gpix_s"] = round(npx / (vms * 1e-3) / 1e9, 4)
         # Unfused pipeline through HBM: forward (int16 centred Z) -> retention
         # in place -> inverse -> measure.
         p3 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I16, qmode=A.Q_ZONAL,
                     r=args.r, backend=A.BACKEND_VALU)
         coef = torch.empty(p3.num_blocks * 256, dtype=torch.int16, device="cuda")
-        fw = lambda: p3.forward(dev, coef)
-        qz = lambda: p3.quantise(coef, coef)
-        iv = lambda: p3.inverse(coef, out)
-        ms_ = lambda: p3.measure(dev, out, sse, psnr)
-        for f in (fw, qz, iv, ms_):
+        stages = {"forward_u8_to_i16": (lambda: p3.forward(dev, coef), 3),
+                  "quantise_i16_inplace": (lambda: p3.quantise(coef, coef), 4),
+                  "inverse_i16_to_u8": (lambda: p3.inverse(coef, out), 3),
+                  "measure_u8": (lambda: p3.measure(dev, out, sse, psnr), 2)}
+        tot = 0.0
+        for key, (f, bpp) in stages.items():
             f()
-        reps = max(3, args.steps // 2)
-        t_fw = _events_ms(fw, reps, stream)
-        t_qz = _events_ms(qz, reps, stream)
-        t_iv = _events_ms(iv, reps, stream)
-        t_ms = _events_ms(ms_, reps, stream)
-        variants["unfused_gpix_s"] = round(npx / ((t_fw + t_qz + t_iv + t_ms) * 1e-3) / 1e9, 4)
-        variants["forward_u8_to_i16_gbs"] = round(3 * npx / (t_fw * 1e-3) / 1e9, 1)
-        variants["quantise_i16_inplace_gbs"] = round(4 * npx / (t_qz * 1e-3) / 1e9, 1)
-        variants["inverse_i16_to_u8_gbs"] = round(3 * npx / (t_iv * 1e-3) / 1e9, 1)
-        variants["measure_u8_gbs"] = round(2 * npx / (t_ms * 1e-3) / 1e9, 1)
-        res["variants"] = variants
+            t = _events_ms(f, max(3, args.steps // 2), stream)
+            tot += t
+            v[f"{key}_gbs"] = round(bpp * npx / (t * 1e-3) / 1e9, 1)
+        v["unfused_pipeline_gpix_s"] = round(npx / (tot * 1e-3) / 1e9, 4)
+        p4 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32, backend=A.BACKEND_MFMA)
+        coef32 = torch.empty(p4.num_blocks * 256, dtype=torch.int32, device="cuda")
+        f = lambda: p4.forward(dev, coef32)
+        f()
+        t = _events_ms(f, max(3, args.steps // 2), stream)
+        v["forward_mfma_u8_to_i32_gbs"] = round(5 * npx / (t * 1e-3) / 1e9, 1)
+        res["variants"] = v
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = _cpu_baseline(frames, args.r, min(args.cpu_frames, n))
-    print(json.dumps(res), flush=True)
+    return res
+
+
+def bench_ragged(args, A, torch):
+    """64 uint8 images, sides uniform in 64..3840 rounded up to 16, mixed
+    content; one fused forward -> zonal r -> inverse -> per-image PSNR."""
+    from synth import BASE_SEED, pack_images, ragged_batch
+    ims = ragged_batch(BASE_SEED + 4, args.frames or 64)
+    buf, hs, ws, ps, offs = pack_images(ims)
+    dev = torch.from_numpy(buf).cuda()
+    out = torch.empty_like(dev)
+    n = len(ims)
+    sse = torch.zeros(n, dtype=torch.int64, device="cuda")
+    psnr = torch.zeros(n, dtype=torch.float64, device="cuda")
+    plan = A.Plan(hs, ws, ps, offs, in_dtype=A.U8, coef_dtype=A.I32, qmode=A.Q_ZONAL, r=args.r,
+                  flags=A.FLAG_AUTOTUNE)
+    stream = torch.cuda.current_stream()
+    step = lambda: plan.compress_and_measure(dev, out, None, sse, psnr)
+    for _ in range(args.warmup):
+        step()
+    ms = _events_ms(step, args.steps, stream)
+    npx = int(sum(h * w for h, w in zip(hs, ws)))
+    return {"metric": "Gpixel/s 2D fwd+quant+inv 16x16, ragged batch", "value": round(npx / (ms * 1e-3) / 1e9, 4),
+            "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": f"{n} uint8 images, sides U[64,3840] rounded to 16, "
+                                   f"{npx / 1e6:.1f} Mpx; zonal r={args.r}", "plan": json.loads(plan.info())},
+            "roofline": {"bound": "hbm", "achieved": round(2 * npx / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(2 * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+
+
+def bench_residual(args, A, torch):
+    """4:2:0 int16 residual frames (Y 3840x2160, U/V 1920x1080); uniform
+    quantiser q in {8, 16, 32}; per frame one fused call (levels and
+    reconstruction written, per-plane PSNR) replayed from a HIP graph."""
+    from synth import BASE_SEED, pack_images, yuv420_residual_frame
+    nf = args.frames or 8
+    planes = []
+    for t in range(nf):
+        planes += yuv420_residual_frame(BASE_SEED + 5, t)
+    per = len(planes) // nf
+    # one packed buffer per frame so that each frame has its own graph
+    bufs = [pack_images(planes[i * per:(i + 1) * per]) for i in range(nf)]
+    npx = sum(p.size for p in planes)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for q in (8, 16, 32):
+        graphs, keep = [], []
+        for buf, hs, ws, ps, offs in bufs:
+            dev = torch.from_numpy(buf).cuda()
+            rec = torch.empty_like(dev)
+            plan = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, qmode=A.Q_UNIFORM, q=q,
+                          qcoef_dtype=A.I16, out_dtype=A.I16)
+            lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
+            sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
+            psnr = torch.zeros(len(hs), dtype=torch.float64, device="cuda")
+            graphs.append(plan.graph(dev, rec, lv, sse, psnr))
+            keep.append((plan, dev, rec, lv, sse, psnr))
+        run = lambda: [g.launch() for g in graphs]
+        run()
+        ms = _events_ms(run, max(2, args.steps // 4), stream)
+        out[f"q{q}_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
+        out[f"q{q}_psnr_y_db"] = round(float(keep[0][5][0]), 4)
+    return {"metric": "Gsample/s 2D fwd+quant+inv 16x16, 4:2:0 int16 residual stream, graph per frame",
+            "value": out["q16_gsample_s"], "unit": "Gsample/s", "n_gpus": 1, "steps": args.steps,
+            "dtype": "i16/f32/f64", "data": "synthetic", "higher_is_better": True,
+            "config": {"workload": f"{nf} frames 3840x2160 4:2:0 int16 residuals (AR(1) frames, per-block "
+                                   f"motion +-8), uniform q in {{8,16,32}}, levels + reconstruction written",
+                       "per_q": out}}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported "
+                                   "(blocks, images and frames are independent: frames shard across GPUs)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1606_05562_amd as A
+    fn = {"luma": bench_luma, "ragged": bench_ragged, "residual": bench_residual}[args.workload]
+    print(json.dumps(fn(args, A, torch)), flush=True)
 
 
 if __name__ == "__main__":

@@ -80,19 +80,28 @@ typedef enum adct16_qmode {
 typedef enum adct16_backend {
   ADCT16_BACKEND_AUTO = 0,  /* autotuned (flag ADCT16_FLAG_AUTOTUNE) or the built-in default */
   ADCT16_BACKEND_VALU = 1,  /* 60-addition butterflies of Eq. (1) on the vector ALUs */
-  ADCT16_BACKEND_MFMA = 2   /* T as a dense {0,+1,-1} int8 contraction on the matrix cores */
+  ADCT16_BACKEND_MFMA = 2   /* T as a dense {0,+1,-1} operand of FP16 matrix-core products,
+                               every product and sum exact; used by adct16_forward and by
+                               the fused call for U8 input, mask modes, U8 (or no) output
+                               and no d_qcoef; other cases run the VALU kernels */
 } adct16_backend;
 
 enum {
-  ADCT16_FLAG_AUTOTUNE = 1  /* time the candidate kernels at plan creation */
+  ADCT16_FLAG_AUTOTUNE = 1,      /* time the candidate kernels at plan creation */
+  ADCT16_FLAG_EXPLICIT_COEF = 2  /* matrix-core fused call: form the coefficients Z of every
+                                    block explicitly even for separable masks (by default the
+                                    forward column pass, the zonal retention and the inverse
+                                    column pass are applied as one exact contraction with
+                                    G = T^T diag(w m) T; results are identical) */
 };
 
 /*
  * Batch descriptor, read by adct16_plan_create (arrays are copied).
  *
  * in_dtype    ADCT16_U8 (8-bit images, Section 4) or ADCT16_I16 (prediction
- *             residuals, Section 5.3).  The MFMA backend needs U8 or, for
- *             I16, samples in [-255, 255]; the VALU backend takes any int16.
+ *             residuals, Section 5.3).  The MFMA backend needs U8 input,
+ *             a mask qmode and U8 out_dtype (else ADCT16_E_MODE); the VALU
+ *             backend takes any int16.
  * coef_dtype  output of adct16_forward:
  *               ADCT16_I32  Z = T A T^T exactly;
  *               ADCT16_I16  (U8 input only) Z of the centred block A - 128,
@@ -146,7 +155,7 @@ adct16_status adct16_plan_info(adct16_plan plan, char *buf, int32_t buf_len);
 
 /* Section 4, forward: d_in (in_dtype) -> d_coef (coef_dtype, block-major).
  * Evaluates T by the 60-addition factorisation of Eq. (1) (VALU backend)
- * or as an exact int8 contraction (MFMA backend); results are identical. */
+ * or as exact FP16 matrix-core products (MFMA backend); results are identical. */
 adct16_status adct16_forward(adct16_plan plan, const void *d_in, void *d_coef, void *stream);
 
 /* Section 4, retention (mask modes) or the uniform quantiser (Section 2: S

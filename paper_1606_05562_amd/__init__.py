@@ -25,6 +25,7 @@ Q_NONE, Q_ZONAL, Q_ZIGZAG, Q_UNIFORM = 0, 1, 2, 3
 # adct16_backend
 BACKEND_AUTO, BACKEND_VALU, BACKEND_MFMA = 0, 1, 2
 FLAG_AUTOTUNE = 1
+FLAG_EXPLICIT_COEF = 2
 
 _TORCH_DTYPE_CODES = {"torch.uint8": U8, "torch.int16": I16, "torch.int32": I32, "torch.float32": F32}
 

@@ -124,7 +124,7 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void*
   // The matrix-core fused kernel writes reconstructions and errors; a call
   // that also asks for the retained coefficients runs the vector kernel.
   if (backend == ADCT16_BACKEND_MFMA && qk == CF_NONE)
-    e = launch_mfma_fused(p->d.qmode == ADCT16_Q_ZIGZAG, ok, P, grid, s);
+    e = launch_mfma_fused(p->d.qmode == ADCT16_Q_ZIGZAG, !(p->d.flags & ADCT16_FLAG_EXPLICIT_COEF), ok, P, grid, s);
   else
     e = launch_valu_fused(p->in_kind, p->mode, qk, ok, P, grid, s);
   if (e != hipSuccess) return hip_fail(e, "fused kernel");
@@ -138,18 +138,19 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void*
 // The matrix-core kernels cover 8-bit input with retention masks (the
 // uniform quantiser's inverse runs in float64 on the vector ALUs).
 bool mfma_supported(const adct16_plan_s* p) {
-  return p->in_kind == IN_U8 && p->mode == MODE_MASK && p->out_kind != OUT_I16;
+  return p->in_kind == IN_U8 && p->mode == MODE_MASK && p->out_kind == OUT_U8;
 }
 
 // Autotuning: time the fused call for each candidate (backend, workgroups
 // per CU) on a scratch batch of the plan's own geometry, keep the fastest.
 // Results are cached per process and, if ADCT16_TUNE_CACHE names a file,
-// across processes (key: device arch, CU count, call shape).
+// across processes (key: device arch, CU count, call shape, mask kind).
 std::mutex g_tune_mu;
 
 std::string tune_key(const adct16_plan_s* p, const char* arch) {
   std::ostringstream k;
-  k << arch << "/cu" << p->cu_count << "/in" << p->in_kind << "/m" << p->mode << "/o" << p->out_kind
+  k << arch << "/cu" << p->cu_count << "/in" << p->in_kind << "/m" << p->mode << "/q" << p->d.qmode
+    << "/o" << p->out_kind << "/f" << (p->d.flags & ADCT16_FLAG_EXPLICIT_COEF)
     << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips);
   return k.str();
 }
@@ -200,7 +201,7 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
   float best = 1e30f;
   std::vector<int> backends = {ADCT16_BACKEND_VALU};
   if (mfma_supported(p)) backends.push_back(ADCT16_BACKEND_MFMA);
-  const int cands[] = {2, 4, 6, 8, 12};
+  const int cands[] = {1, 2, 3, 4, 6, 8, 12};
   adct16_status st = ADCT16_OK;
   for (int b : backends) {
     for (int w : cands) {
@@ -373,7 +374,7 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   if (d->backend == ADCT16_BACKEND_MFMA) {
     if (!mfma_supported(p)) {
       adct16_plan_destroy(p);
-      return fail(ADCT16_E_MODE, "MFMA backend supports U8 input, retention modes and U8/F32 output");
+      return fail(ADCT16_E_MODE, "MFMA backend supports U8 input, retention modes and U8 output");
     }
     p->backend = ADCT16_BACKEND_MFMA;
     p->tuned = "requested";

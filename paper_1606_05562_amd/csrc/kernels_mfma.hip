@@ -49,23 +49,28 @@ __device__ __forceinline__ unsigned load_dword_u8(const uint8_t* img, const Imag
 
 // Reconstruct the 8 blocks of a strip from their dwords (all lanes busy),
 // ADCT16_MFMA_BATCH blocks at a time.
-template <bool ZIGZAG>
+template <bool ZIGZAG, bool COLLAPSE>
 __device__ __forceinline__ void roundtrip8(const unsigned (&x)[kStripBlocks], unsigned (&out)[kStripBlocks],
                                            const MfmaConsts& k, const bool (&keepz)[4]) {
   constexpr int NB = ADCT16_MFMA_BATCH;
 #pragma unroll
   for (int b0 = 0; b0 < kStripBlocks; b0 += NB) {
-    f4 z[NB];
+    if constexpr (COLLAPSE) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      z[b] = fwd_block(x[b0 + b], k);
-      if constexpr (ZIGZAG) {
+      for (int b = 0; b < NB; ++b) out[b0 + b] = round_pack(collapsed_block(x[b0 + b], k));
+    } else {
+      f4 z[NB];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) z[b][v] = keepz[v] ? z[b][v] : 0.0f;
+      for (int b = 0; b < NB; ++b) {
+        z[b] = fwd_block(x[b0 + b], k);
+        if constexpr (ZIGZAG) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) z[b][v] = keepz[v] ? z[b][v] : 0.0f;
+        }
       }
-    }
 #pragma unroll
-    for (int b = 0; b < NB; ++b) out[b0 + b] = round_pack(inv_block(z[b], k));
+      for (int b = 0; b < NB; ++b) out[b0 + b] = round_pack(inv_block(z[b], k));
+    }
   }
 }
 
@@ -106,7 +111,7 @@ __device__ __forceinline__ void operands_to_rows(int* lds, int g, int q, const u
   }
 }
 
-template <bool ZIGZAG, int OUT>
+template <bool ZIGZAG, bool COLLAPSE, int OUT>
 __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fused(Params P) {
   __shared__ int lds_all[kWavesPerGroup * 256];
   int* lds = lds_all + (threadIdx.x >> 6) * 256;
@@ -152,7 +157,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
     unsigned x[kStripBlocks], out[kStripBlocks];
     if (full) {
       rows_to_operands(lds, g, q, cr, x);
-      roundtrip8<ZIGZAG>(x, out, k, keepz);
+      roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
       if constexpr (OUT == OUT_U8) {
         uint4 rows[2];
         operands_to_rows(lds, g, q, out, rows);
@@ -175,7 +180,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
 #pragma unroll
       for (int b = 0; b < kStripBlocks; ++b)
         x[b] = b < nb ? load_dword_u8(in, d, y, (b0 + b) * 16 + 4 * g) : 0u;
-      roundtrip8<ZIGZAG>(x, out, k, keepz);
+      roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
       if (rowok) {
 #pragma unroll
         for (int b = 0; b < kStripBlocks; ++b) {
@@ -321,11 +326,17 @@ hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStre
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma_fused(bool zigzag, int out_kind, const Params& P, int grid, hipStream_t s) {
-  if (!zigzag && out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, OUT_U8>), grid, s, P);
-  if (!zigzag && out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, OUT_NONE>), grid, s, P);
-  if (zigzag && out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<true, OUT_U8>), grid, s, P);
-  if (zigzag && out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<true, OUT_NONE>), grid, s, P);
+hipError_t launch_mfma_fused(bool zigzag, bool collapse, int out_kind, const Params& P, int grid, hipStream_t s) {
+  if (zigzag) {
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_U8>), grid, s, P);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_NONE>), grid, s, P);
+  } else if (collapse) {
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_U8>), grid, s, P);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_NONE>), grid, s, P);
+  } else {
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_U8>), grid, s, P);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_NONE>), grid, s, P);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -64,6 +64,7 @@ struct MfmaConsts {
   uint4 w3;      // stage-3 B: w_u T[u][q] 2^-11 for u = 4g..4g+3, twice (one per digit)
   uint2 w4;      // stage-4 A: w_f T[f][q] for f = 4g..4g+3
   f4 c4;         // stage-4 accumulator start: -1536 sum_f w_f T[f][j], j = 4g+v
+  uint2 gq;      // collapsed stages 2-3: G[q][4g..4g+3] 2^-11, G = T^T diag(w m) T
 };
 
 __device__ __forceinline__ MfmaConsts make_consts(int q, int g, int r_sep) {
@@ -82,6 +83,17 @@ __device__ __forceinline__ MfmaConsts make_consts(int q, int g, int r_sep) {
   const unsigned w30 = pack_h(w3[0], w3[1]), w31 = pack_h(w3[2], w3[3]);
   k.w3 = make_uint4(w30, w31, w30, w31);
   k.w4 = make_uint2(pack_h(w4[0], w4[1]), pack_h(w4[2], w4[3]));
+  // G = T^T diag(w m) T (m: retained rows / columns of a separable mask) is
+  // symmetric with |G| <= 68; G 2^-11 is exact in fp16.
+  float gv[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int kk = 4 * g + m;
+    int acc = 0;
+    for (int u = 0; u < r_sep; ++u) acc += kW[u] * kT[u][q] * kT[u][kk];
+    gv[m] = (float)acc * (1.0f / 2048.0f);
+  }
+  k.gq = make_uint2(pack_h(gv[0], gv[1]), pack_h(gv[2], gv[3]));
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int j = 4 * g + v;
@@ -107,16 +119,37 @@ __device__ __forceinline__ f4 fwd_block(unsigned xdw, const MfmaConsts& k) {
   return mma16(k.tq, ph, zero);                                    // Z_c[4g+v][q]
 }
 
+// Stage 4 from U' = 1536 + U 2^-11 (U'[v] = U[q][4g+v]); returns
+// s[v] = N[q][4g+v] / 2048.  U' lies in [1024, 2048), where fp16 steps by 1:
+// A = floor(U') (the round-toward-zero pack) and B = fract(U') (a multiple
+// of 2^-11 in [0, 1)) are both exact in fp16.
+__device__ __forceinline__ f4 stage4(f4 u, const MfmaConsts& k) {
+  const unsigned A0 = h2bits(u[0], u[1]), A1 = h2bits(u[2], u[3]);
+  const unsigned B0 = h2bits(__builtin_amdgcn_fractf(u[0]), __builtin_amdgcn_fractf(u[1]));
+  const unsigned B1 = h2bits(__builtin_amdgcn_fractf(u[2]), __builtin_amdgcn_fractf(u[3]));
+  const f4 sa = mma16(k.w4, make_uint2(A0, A1), k.c4);
+  return mma16(k.w4, make_uint2(B0, B1), sa);
+}
+
 // Inverse stages 3-4 from Z_c (already masked); returns s[v] = N[q][4g+v] / 2048.
 __device__ __forceinline__ f4 inv_block(f4 z, const MfmaConsts& k) {
   const unsigned a0 = h2bits(z[0], z[1]), a1 = h2bits(z[2], z[3]);
   const unsigned b0 = residual_pair(a0, z[0], z[1]), b1 = residual_pair(a1, z[2], z[3]);
   const f4 c3 = {1536.0f, 1536.0f, 1536.0f, 1536.0f};
   const f4 u = mma32(make_uint4(a0, a1, b0, b1), k.w3, c3);       // 1536 + U[q][4g+v] 2^-11
-  const unsigned A0 = h2bits(u[0], u[1]), A1 = h2bits(u[2], u[3]);
-  const unsigned B0 = residual_pair(A0, u[0], u[1]), B1 = residual_pair(A1, u[2], u[3]);
-  const f4 sa = mma16(k.w4, make_uint2(A0, A1), k.c4);
-  return mma16(k.w4, make_uint2(B0, B1), sa);
+  return stage4(u, k);
+}
+
+// Separable masks: forward row pass, then U^T = P^T G^T in one contraction
+// (the forward column pass, the retention and the inverse column pass
+// together: T^T diag(w m) T P = T^T (w .* m .* T P)), then stage 4.
+__device__ __forceinline__ f4 collapsed_block(unsigned xdw, const MfmaConsts& k) {
+  const f4 c1 = {k.c1, k.c1, k.c1, k.c1};
+  const f4 p = mma16(bytes_to_h4(xdw), k.tq, c1);                 // P_c[4g+v][q], columns masked
+  const uint2 ph = make_uint2(pack_h(p[0], p[1]), pack_h(p[2], p[3]));
+  const f4 c3 = {1536.0f, 1536.0f, 1536.0f, 1536.0f};
+  const f4 u = mma16(ph, k.gq, c3);                                 // 1536 + U[q][4g+v] 2^-11
+  return stage4(u, k);
 }
 
 __device__ __forceinline__ unsigned round_pack(f4 s) {

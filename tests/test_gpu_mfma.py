@@ -60,9 +60,9 @@ def test_mfma_forward_bit_exact(batch_u8, cd):
         assert np.array_equal(got.astype(np.int64), want)
 
 
-def _fused(batch, backend, qmode, r):
+def _fused(batch, backend, qmode, r, flags=0):
     T = torch()
-    plan = batch.plan(coef_dtype=A().I32, qmode=qmode, r=r, backend=backend)
+    plan = batch.plan(coef_dtype=A().I32, qmode=qmode, r=r, backend=backend, flags=flags)
     out = batch.empty_like_images(np.uint8, 1)
     sse = T.zeros(len(batch.images), dtype=T.int64, device="cuda")
     psnr = T.zeros(len(batch.images), dtype=T.float64, device="cuda")
@@ -74,10 +74,13 @@ def _fused(batch, backend, qmode, r):
 CASES = [(1, r) for r in (1, 2, 3, 5, 8, 9, 12, 16)] + [(0, 16)] + [(2, r) for r in (1, 16, 100, 181, 256)]
 
 
+@pytest.mark.parametrize("explicit", [False, True])
 @pytest.mark.parametrize("qmode,r", CASES)
-def test_mfma_fused_bit_exact(batch_u8, qmode, r):
+def test_mfma_fused_bit_exact(batch_u8, qmode, r, explicit):
+    # explicit: coefficients formed per block; otherwise separable masks use
+    # the single contraction with G = T^T diag(w m) T.
     keep = {0: codec.mask_none(), 1: codec.mask_zonal(r), 2: codec.mask_zigzag(r)}[qmode]
-    recs, sse, psnr = _fused(batch_u8, A().BACKEND_MFMA, qmode, r)
+    recs, sse, psnr = _fused(batch_u8, A().BACKEND_MFMA, qmode, r, A().FLAG_EXPLICIT_COEF if explicit else 0)
     for i, (got, im) in enumerate(zip(recs, batch_u8.images)):
         want, s, p = codec.compress_kept(im, keep)
         assert np.array_equal(got, want), f"image {i}"
@@ -85,12 +88,13 @@ def test_mfma_fused_bit_exact(batch_u8, qmode, r):
         assert (math.isinf(p) and math.isinf(psnr[i])) or abs(psnr[i] - p) <= 1e-3
 
 
-@pytest.mark.parametrize("qmode,r", [(1, 8), (1, 16), (2, 181), (1, 1)])
-def test_mfma_equals_adder_kernel_on_extremes(batch_worst, qmode, r):
-    a = _fused(batch_worst, A().BACKEND_MFMA, qmode, r)
+@pytest.mark.parametrize("explicit", [False, True])
+@pytest.mark.parametrize("qmode,r", [(1, 8), (1, 16), (2, 181), (1, 1), (0, 16)])
+def test_mfma_equals_adder_kernel_on_extremes(batch_worst, qmode, r, explicit):
+    a = _fused(batch_worst, A().BACKEND_MFMA, qmode, r, A().FLAG_EXPLICIT_COEF if explicit else 0)
     b = _fused(batch_worst, A().BACKEND_VALU, qmode, r)
     assert np.array_equal(a[0][0], b[0][0]) and np.array_equal(a[1], b[1])
-    keep = {1: codec.mask_zonal(r), 2: codec.mask_zigzag(r)}[qmode]
+    keep = {0: codec.mask_none(), 1: codec.mask_zonal(r), 2: codec.mask_zigzag(r)}[qmode]
     want, s, _ = codec.compress_kept(batch_worst.images[0], keep)
     assert np.array_equal(a[0][0], want) and a[1][0] == s
 
@@ -161,3 +165,13 @@ def test_dct_mfma_error_bound(batch_u8, prec):
         worst_abs = max(worst_abs, float(err.max()))
         worst_rel = max(worst_rel, float(err.max() / max(1.0, np.abs(ref).max())))
     print(f"DCT-II {prec}: max abs error {worst_abs:.4g}, relative to max|Y| {worst_rel:.3g}")
+
+
+@pytest.mark.parametrize("kw", [dict(in_dtype=2, out_dtype=2), dict(out_dtype=4), dict(qmode=3, q=8)])
+def test_mfma_unsupported_plans_rejected(kw):
+    mod = A()
+    args = dict(in_dtype=mod.U8, coef_dtype=mod.I32, qmode=mod.Q_ZONAL, r=8, backend=mod.BACKEND_MFMA)
+    args.update(kw)
+    with pytest.raises(mod.Adct16Error) as e:
+        mod.Plan([32], [32], [32], [0], **args)
+    assert e.value.status == mod.E_MODE
