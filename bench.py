@@ -146,6 +146,9 @@ def bench_luma(args, A, torch):
     achieved = alg_bytes / (kms * 1e-3) / 1e9
     kname = _fused_kernel_name(info)
     traffic = _traffic(kname)
+    # Attainable-bandwidth context: a plain device copy of the same bytes.
+    cms = _events_ms(lambda: out.copy_(dev), args.steps, stream)
+    copy_gbs = alg_bytes / (cms * 1e-3) / 1e9
     if args.calibrate_copy:
         torch.cuda.synchronize()
         out.copy_(dev)  # plain copy kernel: reads npx bytes, writes npx bytes
@@ -166,7 +169,8 @@ def bench_luma(args, A, torch):
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(traffic / 1e9, 4) if traffic else None,
                      "traffic_unit": "GB per launch", "algorithmic_bytes": alg_bytes,
-                     "kernel": kname, "kernel_ms": round(kms, 4)},
+                     "kernel": kname, "kernel_ms": round(kms, 4),
+                     "copy_same_bytes_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "psnr_mean_db": round(float(psnr[torch.isfinite(psnr)].mean()), 4),
     }
     if not args.no_variants:

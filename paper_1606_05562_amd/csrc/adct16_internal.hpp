@@ -23,6 +23,10 @@ constexpr int kGroupThreads = 64 * kWavesPerGroup;
 #ifndef ADCT16_MFMA_MIN_WG
 #define ADCT16_MFMA_MIN_WG 1
 #endif
+// Non-temporal 16-byte loads and stores in the matrix-core fused kernel.
+#ifndef ADCT16_MFMA_NT
+#define ADCT16_MFMA_NT 1
+#endif
 // Blocks of a strip carried through the matrix-core stages together.
 #ifndef ADCT16_MFMA_BATCH
 #define ADCT16_MFMA_BATCH 8
@@ -38,6 +42,12 @@ struct ImageDesc {
   int32_t pad[2];
 };
 static_assert(sizeof(ImageDesc) == 56, "ImageDesc layout");
+
+// One block row (16 image rows) of one image: the unit of work that the
+// matrix-core fused kernel hands out to wavefronts cyclically.
+struct RowTask {
+  int32_t img, sy;
+};
 
 // Per-plan constant tables, indexed u * 16 + v.
 struct Tables {
@@ -69,6 +79,8 @@ struct Params {
   void* qcoef;
   unsigned long long* sse;
   double* psnr;
+  const RowTask* rows;  // every block row of the batch, image by image
+  int64_t n_rows;
 };
 
 // Launchers (return hipSuccess or the launch error).  `grid` is the number

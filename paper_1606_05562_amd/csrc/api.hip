@@ -81,6 +81,8 @@ struct adct16_plan_s {
   int64_t n_blocks = 0, n_strips = 0;
   ImageDesc* d_images = nullptr;
   Tables* d_tables = nullptr;
+  RowTask* d_rows = nullptr;
+  int64_t n_rows = 0;
   unsigned long long* d_sse_ws = nullptr;
   int grid = 0;           // persistent workgroups for the strip kernels
   int backend = ADCT16_BACKEND_VALU;   // resolved backend of the fused/forward calls
@@ -101,6 +103,8 @@ Params base_params(const adct16_plan_s* p) {
   P.n_strips = p->n_strips;
   P.n_blocks = p->n_blocks;
   P.tables = p->d_tables;
+  P.rows = p->d_rows;
+  P.n_rows = p->n_rows;
   return P;
 }
 
@@ -355,11 +359,17 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
     t.deqc[u] = uniform ? (double)d->q / std::sqrt((double)kNorm[u]) : 0.0;
   }
   t.rsep = d->qmode == ADCT16_Q_ZONAL ? d->r : 16;
+  std::vector<RowTask> rows;
+  for (size_t i = 0; i < images.size(); ++i)
+    for (int sy = 0; sy < images[i].by; ++sy) rows.push_back(RowTask{(int32_t)i, sy});
+  p->n_rows = (int64_t)rows.size();
   bool ok = hipMalloc(&p->d_images, sizeof(ImageDesc) * images.size()) == hipSuccess &&
             hipMalloc(&p->d_tables, sizeof(Tables)) == hipSuccess &&
+            hipMalloc(&p->d_rows, sizeof(RowTask) * rows.size()) == hipSuccess &&
             hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size()) == hipSuccess;
   ok = ok && hipMemcpy(p->d_images, images.data(), sizeof(ImageDesc) * images.size(), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->d_tables, &t, sizeof t, hipMemcpyHostToDevice) == hipSuccess;
+       hipMemcpy(p->d_tables, &t, sizeof t, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p->d_rows, rows.data(), sizeof(RowTask) * rows.size(), hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
     adct16_plan_destroy(p);
     return fail(ADCT16_E_NOMEM, "plan allocation failed");
@@ -399,6 +409,7 @@ adct16_status adct16_plan_destroy(adct16_plan p) {
   if (!p) return fail(ADCT16_E_NULL, "plan is NULL");
   if (p->d_images) hipFree(p->d_images);
   if (p->d_tables) hipFree(p->d_tables);
+  if (p->d_rows) hipFree(p->d_rows);
   if (p->d_sse_ws) hipFree(p->d_sse_ws);
   delete p;
   return ADCT16_OK;

@@ -79,130 +79,226 @@ __device__ __forceinline__ unsigned sse4(unsigned a, unsigned r) {
          2u * __builtin_amdgcn_udot4(a, r, 0u, false);
 }
 
-// Interior strips are read with one 16-byte load per lane per 4 blocks
-// (lane 16g+q: row q of block 4h+g), prefetched one strip ahead, and turned
-// into the operand layout (lane 16g+q: dword g of row q of each block) by a
-// 4x4 dword transpose through LDS (conflict-free: consecutive lanes touch
-// consecutive dwords on both sides).
-__device__ __forceinline__ void rows_to_operands(int* lds, int g, int q, const uint4 (&r)[2],
+// Row-wise 16-byte accesses of interior strips: in half h (0, 1) lane
+// 8r + c holds bytes 16c..16c+15 of strip row 8h + r, i.e. row 8h + r of
+// block c, so one load or store instruction covers 8 rows x 128 contiguous
+// bytes (whole cache lines).  A transpose through LDS (layout L[g][q][b] =
+// dword g of row q of block b, 512 dwords per wave) turns this into the
+// operand layout (lane 16g + q: dword g of row q of every block) and back;
+// the b32 accesses touch 64 consecutive dwords, the b128 ones 2-way at most.
+__device__ __forceinline__ void rows_to_operands(int* lds, int r, int c, int g, int q, const uint4 (&rows)[2],
                                                  unsigned (&x)[kStripBlocks]) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    int4* w = reinterpret_cast<int4*>(lds + (g * 16 + q) * 4);
-    *w = make_int4((int)r[h].x, (int)r[h].y, (int)r[h].z, (int)r[h].w);
-    wave_lds_sync();
-#pragma unroll
-    for (int b = 0; b < 4; ++b) x[4 * h + b] = (unsigned)lds[(b * 16 + q) * 4 + g];
-    wave_lds_sync();
+    const int o = (8 * h + r) * kStripBlocks + c;
+    lds[o] = (int)rows[h].x;
+    lds[128 + o] = (int)rows[h].y;
+    lds[256 + o] = (int)rows[h].z;
+    lds[384 + o] = (int)rows[h].w;
   }
+  wave_lds_sync();
+  const int4* p = reinterpret_cast<const int4*>(lds + g * 128 + q * kStripBlocks);
+  const int4 a = p[0], b = p[1];
+  x[0] = (unsigned)a.x; x[1] = (unsigned)a.y; x[2] = (unsigned)a.z; x[3] = (unsigned)a.w;
+  x[4] = (unsigned)b.x; x[5] = (unsigned)b.y; x[6] = (unsigned)b.z; x[7] = (unsigned)b.w;
+  wave_lds_sync();
 }
 
-// The inverse transpose: lane 16g+q ends with row q of blocks g and 4+g.
-__device__ __forceinline__ void operands_to_rows(int* lds, int g, int q, const unsigned (&o)[kStripBlocks],
-                                                 uint4 (&r)[2]) {
+__device__ __forceinline__ void operands_to_rows(int* lds, int r, int c, int g, int q, const unsigned (&o)[kStripBlocks],
+                                                 uint4 (&rows)[2]) {
+  int4* p = reinterpret_cast<int4*>(lds + g * 128 + q * kStripBlocks);
+  p[0] = make_int4((int)o[0], (int)o[1], (int)o[2], (int)o[3]);
+  p[1] = make_int4((int)o[4], (int)o[5], (int)o[6], (int)o[7]);
+  wave_lds_sync();
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
+    const int i = (8 * h + r) * kStripBlocks + c;
+    rows[h] = make_uint4((unsigned)lds[i], (unsigned)lds[128 + i], (unsigned)lds[256 + i], (unsigned)lds[384 + i]);
+  }
+  wave_lds_sync();
+}
+
+// Streaming accesses: every byte of the batch is read once and written once,
+// so the 16-byte row accesses carry the non-temporal hint.
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld_row16(const uint8_t* p) {
+#if ADCT16_MFMA_NT
+  const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+#else
+  return *reinterpret_cast<const uint4*>(p);
+#endif
+}
+__device__ __forceinline__ void st_row16(uint8_t* p, const uint4& v) {
+#if ADCT16_MFMA_NT
+  const v4u w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<v4u*>(p));
+#else
+  *reinterpret_cast<uint4*>(p) = v;
+#endif
+}
+
+// The fields of an image that the fused kernel uses, held in scalars.
+struct ImgGeom {
+  int64_t offset;
+  int32_t h, w, pitch, bx, sx;
+};
+
+__device__ __forceinline__ ImgGeom geom_of(const ImageDesc* __restrict__ images, int i) {
+  ImgGeom m;
+  m.offset = images[i].offset;
+  m.h = images[i].h;
+  m.w = images[i].w;
+  m.pitch = images[i].pitch;
+  m.bx = images[i].bx;
+  m.sx = images[i].sx;
+  return m;
+}
+
+// One dword of block row q (columns 4g..4g+3), edge-extended.
+__device__ __forceinline__ unsigned load_dword_edge(const uint8_t* img, const ImgGeom& d, int y, int x0) {
+  const int64_t off = d.offset + (int64_t)y * d.pitch;
+  if (x0 + 3 < d.w) return *reinterpret_cast<const unsigned*>(img + off + x0);
+  unsigned r = 0;
+  for (int k = 0; k < 4; ++k) r |= (unsigned)img[off + min(x0 + k, d.w - 1)] << (8 * k);
+  return r;
+}
+
+// Edge strip: fewer than 8 blocks, a partial last block (columns past the
+// width repeat the last one) and / or rows past the height (the last row
+// repeated, neither written nor counted).  Dword loads and stores.
+template <bool ZIGZAG, bool COLLAPSE, int OUT>
+__device__ __forceinline__ void edge_strip(const ImgGeom& d, int sy, int sxi, const uint8_t* in, uint8_t* outp,
+                                           const MfmaConsts& k, const bool (&keepz)[4], int g, int q,
+                                           SseAcc& acc) {
+  const int y0 = sy * 16;
+  const int y = min(y0 + q, d.h - 1);
+  const bool rowok = (y0 + q) < d.h;
+  const int b0 = sxi * kStripBlocks;
+  const int64_t off = d.offset + (int64_t)y * d.pitch;
+  const int nb = min(kStripBlocks, d.bx - b0);
+  unsigned x[kStripBlocks], out[kStripBlocks];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) lds[(b * 16 + q) * 4 + g] = (int)o[4 * h + b];
-    wave_lds_sync();
-    const int4 v = *reinterpret_cast<const int4*>(lds + (g * 16 + q) * 4);
-    r[h] = make_uint4((unsigned)v.x, (unsigned)v.y, (unsigned)v.z, (unsigned)v.w);
-    wave_lds_sync();
+  for (int b = 0; b < kStripBlocks; ++b) x[b] = b < nb ? load_dword_edge(in, d, y, (b0 + b) * 16 + 4 * g) : 0u;
+  roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
+  if (!rowok) return;
+#pragma unroll
+  for (int b = 0; b < kStripBlocks; ++b) {
+    const int x0 = (b0 + b) * 16 + 4 * g;
+    const int n = b < nb ? min(4, d.w - x0) : 0;
+    if (n > 0) {
+      if constexpr (OUT == OUT_U8) {
+        uint8_t* o = outp + off + x0;
+        if (n == 4) *reinterpret_cast<unsigned*>(o) = out[b];
+        else for (int j = 0; j < n; ++j) o[j] = (uint8_t)(out[b] >> (8 * j));
+      }
+      const unsigned m = n >= 4 ? 0xffffffffu : ((1u << (8 * n)) - 1u);
+      acc.lane += sse4(x[b] & m, out[b] & m);
+    }
   }
 }
 
+// Work distribution: wavefront w of W takes block rows w, w + W, w + 2W, ...
+// of the batch (the row table lists them image by image) and walks each row
+// strip by strip, so that at any time the wavefronts of the chip stream
+// through one contiguous window of the batch.  The rows of the next interior
+// strip (possibly in the next block row) are loaded one strip ahead; the
+// stores of interior strips are unconditional, and each branch ends with an
+// explicit wait for everything but its own stores, so that the loads of the
+// next strip never wait for the stores of the previous one.  The image and row tables
+// are separate read-only, non-aliased arguments so that their uniform reads
+// inside the loop are scalar loads.
 template <bool ZIGZAG, bool COLLAPSE, int OUT>
-__global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fused(Params P) {
-  __shared__ int lds_all[kWavesPerGroup * 256];
-  int* lds = lds_all + (threadIdx.x >> 6) * 256;
-  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
+__global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fused(
+    Params P, const ImageDesc* __restrict__ images, const RowTask* __restrict__ rows) {
+  __shared__ int lds_all[kWavesPerGroup * 512];
+  int* lds = lds_all + (threadIdx.x >> 6) * 512;
+  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4, r = lane >> 3, c = lane & 7;
   const MfmaConsts k = make_consts(q, g, P.tables->rsep);
   bool keepz[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) keepz[v] = P.tables->wkeep[(4 * g + v) * 16 + q] != 0;
   const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
   uint8_t* outp = reinterpret_cast<uint8_t*>(P.out);
-  StripCursor c;
-  if (!cursor_init(c, P)) return;
-  SseAcc acc;
-  int since_flush = 0;
-  // Prefetch state: rows of the next interior strip.
-  auto interior = [&](const StripCursor& cc) { return (cc.sxi * kStripBlocks + kStripBlocks) * 16 <= cc.d.w; };
-  auto row_off = [&](const StripCursor& cc) {
-    return cc.d.offset + (int64_t)min(cc.sy * 16 + q, cc.d.h - 1) * cc.d.pitch + cc.sxi * kStripBlocks * 16;
+  const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
+  int64_t t = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
+  if (t >= P.n_rows) return;
+  int img = rows[t].img, sy = rows[t].sy, sxi = 0;
+  ImgGeom d = geom_of(images, img);
+  auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
+    return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
+  };
+  // this lane's first 16 bytes of strip (ssy, ssxi): row 16 ssy + r, block 8 ssxi + c
+  auto lane_off = [&](const ImgGeom& dd, int ssy, int ssxi) {
+    return dd.offset + (int64_t)(ssy * 16 + r) * dd.pitch + ssxi * (16 * kStripBlocks) + 16 * c;
   };
   uint4 nr[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
-  if (interior(c)) {
-    const uint4* src = reinterpret_cast<const uint4*>(in + row_off(c));
-    nr[0] = src[g];
-    nr[1] = src[4 + g];
+  if (interior(d, sy, 0)) {
+    const int64_t o = lane_off(d, sy, 0);
+    nr[0] = ld_row16(in + o);
+    nr[1] = ld_row16(in + o + 8 * (int64_t)d.pitch);
+    // complete these loads here rather than at the loop head, where the
+    // wait would also cover the previous strip's stores
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters unchanged
   }
+  SseAcc acc;
   for (;;) {
-    const int y0 = c.sy * 16;
-    const int y = min(y0 + q, c.d.h - 1);
-    const bool rowok = (y0 + q) < c.d.h;
-    const int b0 = c.sxi * kStripBlocks;
-    const int64_t off = c.d.offset + (int64_t)y * c.d.pitch;
-    const bool full = interior(c);
-    const uint4 cr[2] = {nr[0], nr[1]};
-    const ImageDesc d = c.d;
-    const int img = c.img;
-    const bool changed = cursor_next(c, P);
-    const bool done = c.s >= c.s_end;
-    if (!done && interior(c)) {  // prefetch the next strip
-      const uint4* src = reinterpret_cast<const uint4*>(in + row_off(c));
-      nr[0] = src[g];
-      nr[1] = src[4 + g];
+    // the strip after this one
+    int nimg = img, nsy = sy, nsxi = sxi + 1;
+    ImgGeom nd = d;
+    bool more = true;
+    if (nsxi == d.sx) {
+      t += W;
+      more = t < P.n_rows;
+      if (more) {
+        nimg = rows[t].img;
+        nsy = rows[t].sy;
+        nsxi = 0;
+        if (nimg != img) nd = geom_of(images, nimg);
+      }
     }
-    unsigned x[kStripBlocks], out[kStripBlocks];
-    if (full) {
-      rows_to_operands(lds, g, q, cr, x);
+    const uint4 cr[2] = {nr[0], nr[1]};
+    // issued inside each branch below, so that no load is outstanding where
+    // the branches join
+    auto prefetch = [&]() {
+      if (more && interior(nd, nsy, nsxi)) {
+        const int64_t o = lane_off(nd, nsy, nsxi);
+        nr[0] = ld_row16(in + o);
+        nr[1] = ld_row16(in + o + 8 * (int64_t)nd.pitch);
+      }
+    };
+    if (interior(d, sy, sxi)) {
+      prefetch();
+      unsigned x[kStripBlocks], out[kStripBlocks];
+      rows_to_operands(lds, r, c, g, q, cr, x);
       roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
       if constexpr (OUT == OUT_U8) {
-        uint4 rows[2];
-        operands_to_rows(lds, g, q, out, rows);
-        if (rowok) {
-          uint4* dst = reinterpret_cast<uint4*>(outp + off + b0 * 16);
-          dst[g] = rows[0];
-          dst[4 + g] = rows[1];
-        }
+        uint4 orow[2];
+        operands_to_rows(lds, r, c, g, q, out, orow);
+        const int64_t o = lane_off(d, sy, sxi);
+        st_row16(outp + o, orow[0]);
+        st_row16(outp + o + 8 * (int64_t)d.pitch, orow[1]);
+        // the prefetched rows were issued before these two stores: wait for
+        // everything but the stores (vmcnt(2))
+        __builtin_amdgcn_s_waitcnt(0x0F72);
+      } else {
+        __builtin_amdgcn_s_waitcnt(0x0F70);
       }
-      if (rowok) {
-        unsigned s = 0;
+      unsigned s = 0;
 #pragma unroll
-        for (int b = 0; b < kStripBlocks; ++b) s += sse4(x[b], out[b]);
-        acc.lane += s;
-      }
+      for (int b = 0; b < kStripBlocks; ++b) s += sse4(x[b], out[b]);
+      acc.lane += s;
     } else {
-      // Right-edge strip: fewer blocks and / or a partial last block
-      // (columns past the width repeat the last one).
-      const int nb = min(kStripBlocks, d.bx - b0);
-#pragma unroll
-      for (int b = 0; b < kStripBlocks; ++b)
-        x[b] = b < nb ? load_dword_u8(in, d, y, (b0 + b) * 16 + 4 * g) : 0u;
-      roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
-      if (rowok) {
-#pragma unroll
-        for (int b = 0; b < kStripBlocks; ++b) {
-          const int x0 = (b0 + b) * 16 + 4 * g;
-          const int n = b < nb ? min(4, d.w - x0) : 0;
-          if (n > 0) {
-            if constexpr (OUT == OUT_U8) {
-              uint8_t* o = outp + off + x0;
-              if (n == 4) *reinterpret_cast<unsigned*>(o) = out[b];
-              else for (int j = 0; j < n; ++j) o[j] = (uint8_t)(out[b] >> (8 * j));
-            }
-            const unsigned m = n >= 4 ? 0xffffffffu : ((1u << (8 * n)) - 1u);
-            acc.lane += sse4(x[b] & m, out[b] & m);
-          }
-        }
-      }
+      prefetch();
+      edge_strip<ZIGZAG, COLLAPSE, OUT>(d, sy, sxi, in, outp, k, keepz, g, q, acc);
+      __builtin_amdgcn_s_waitcnt(0x0F70);
     }
-    if (changed || done || ++since_flush == 1024) {
-      acc.flush(P.sse, img);
-      since_flush = 0;
-    }
-    if (done) break;
+    if (!more || nimg != img) acc.flush(P.sse, img);
+    if (!more) break;
+    img = nimg;
+    sy = nsy;
+    sxi = nsxi;
+    d = nd;
   }
 }
 
@@ -328,14 +424,14 @@ hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStre
 
 hipError_t launch_mfma_fused(bool zigzag, bool collapse, int out_kind, const Params& P, int grid, hipStream_t s) {
   if (zigzag) {
-    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_U8>), grid, s, P);
-    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_NONE>), grid, s, P);
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_U8>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_NONE>), grid, s, P, P.images, P.rows);
   } else if (collapse) {
-    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_U8>), grid, s, P);
-    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_NONE>), grid, s, P);
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_U8>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_NONE>), grid, s, P, P.images, P.rows);
   } else {
-    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_U8>), grid, s, P);
-    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_NONE>), grid, s, P);
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_U8>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_NONE>), grid, s, P, P.images, P.rows);
   }
   return hipErrorInvalidValue;
 }
