@@ -47,14 +47,18 @@ def _parse():
     return ap.parse_args()
 
 
+# Device-side sources of the fused kernels (host API code excluded).
+KERNEL_SOURCES = ["adct16_internal.hpp", "device_common.hpp", "kernels_mfma.hip", "kernels_valu.hip",
+                  "mfma_stages.hpp"]
+
+
 def kernel_source_hash() -> str:
     csrc = os.path.join(ROOT, "paper_1606_05562_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 

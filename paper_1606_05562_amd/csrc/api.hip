@@ -192,43 +192,59 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
   int64_t in_elems = 0;
   for (size_t i = 0; i < p->images.size(); ++i)
     in_elems = std::max<int64_t>(in_elems, p->images[i].offset + (int64_t)p->images[i].h * p->images[i].pitch);
-  const int es = esize(p->d.in_dtype);
-  void *din = nullptr, *dout = nullptr;
-  if (hipMalloc(&din, in_elems * es + 64) != hipSuccess) return fail(ADCT16_E_NOMEM, "autotune scratch");
-  if (hipMalloc(&dout, in_elems * es + 64) != hipSuccess) { hipFree(din); return fail(ADCT16_E_NOMEM, "autotune scratch"); }
-  hipMemset(din, 0x5a, in_elems * es);
-  hipStream_t s;
-  hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
-  float best = 1e30f;
+  const size_t bytes = (size_t)in_elems * esize(p->d.in_dtype);
+  // Resources released on every exit.
+  struct Scratch {
+    void *din = nullptr, *dout = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Scratch() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (s) (void)hipStreamDestroy(s);
+      if (din) (void)hipFree(din);
+      if (dout) (void)hipFree(dout);
+    }
+  } w;
+  if (hipMalloc(&w.din, bytes + 64) != hipSuccess || hipMalloc(&w.dout, bytes + 64) != hipSuccess)
+    return fail(ADCT16_E_NOMEM, "autotune scratch");
+  hipError_t e = hipMemset(w.din, 0x5a, bytes);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&w.e0);
+  if (e == hipSuccess) e = hipEventCreate(&w.e1);
+  if (e != hipSuccess) return hip_fail(e, "autotune set-up");
+  // Candidates are timed round-robin, one launch at a time, and each keeps
+  // its fastest launch: clocks drift over a few milliseconds of sustained
+  // load, and a sequential sweep would favour whichever ran first.
+  struct Cand { int backend, wgpc, grid; float best; };
+  std::vector<Cand> cands;
   std::vector<int> backends = {ADCT16_BACKEND_VALU};
   if (mfma_supported(p)) backends.push_back(ADCT16_BACKEND_MFMA);
-  const int cands[] = {1, 2, 3, 4, 6, 8, 12};
-  adct16_status st = ADCT16_OK;
-  for (int b : backends) {
-    for (int w : cands) {
-      const int grid = (int)std::min<int64_t>(p->cu_count * w, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup);
-      st = compress_impl(p, b, grid, din, p->out_kind == OUT_F32 ? nullptr : dout, nullptr, nullptr, nullptr, s);
-      if (st != ADCT16_OK) break;
-      hipEventRecord(e0, s);
-      const int reps = 3;
-      for (int r = 0; r < reps; ++r) compress_impl(p, b, grid, din, p->out_kind == OUT_F32 ? nullptr : dout, nullptr, nullptr, nullptr, s);
-      hipEventRecord(e1, s);
-      hipEventSynchronize(e1);
-      float ms = 0;
-      hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) { best = ms; best_b = b; best_w = w; }
-    }
-    if (st != ADCT16_OK) break;
+  for (int b : backends)
+    for (int wg : {1, 2, 3, 4, 6, 8, 12})
+      cands.push_back({b, wg, (int)std::min<int64_t>(p->cu_count * wg, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup), 1e30f});
+  void* const tout = p->out_kind == OUT_F32 ? nullptr : w.dout;
+  for (const Cand& c : cands) {  // warm-up (code objects, clocks)
+    adct16_status st = compress_impl(p, c.backend, c.grid, w.din, tout, nullptr, nullptr, nullptr, w.s);
+    if (st != ADCT16_OK) return st;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipStreamDestroy(s);
-  hipFree(din);
-  hipFree(dout);
-  if (st != ADCT16_OK) return st;
+  for (int round = 0; round < 4; ++round) {
+    for (Cand& c : cands) {
+      e = hipEventRecord(w.e0, w.s);
+      if (e != hipSuccess) return hip_fail(e, "autotune event");
+      adct16_status st = compress_impl(p, c.backend, c.grid, w.din, tout, nullptr, nullptr, nullptr, w.s);
+      if (st != ADCT16_OK) return st;
+      e = hipEventRecord(w.e1, w.s);
+      if (e == hipSuccess) e = hipEventSynchronize(w.e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, w.e0, w.e1);
+      if (e != hipSuccess) return hip_fail(e, "autotune timing");
+      c.best = std::min(c.best, ms);
+    }
+  }
+  float best = 1e30f;
+  for (const Cand& c : cands)
+    if (c.best < best) { best = c.best; best_b = c.backend; best_w = c.wgpc; }
   p->backend = best_b;
   p->grid = (int)std::min<int64_t>(p->cu_count * best_w, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup);
   std::ostringstream t;
@@ -407,10 +423,11 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
 
 adct16_status adct16_plan_destroy(adct16_plan p) {
   if (!p) return fail(ADCT16_E_NULL, "plan is NULL");
-  if (p->d_images) hipFree(p->d_images);
-  if (p->d_tables) hipFree(p->d_tables);
-  if (p->d_rows) hipFree(p->d_rows);
-  if (p->d_sse_ws) hipFree(p->d_sse_ws);
+  // nothing useful can be done about a failed free on teardown
+  if (p->d_images) (void)hipFree(p->d_images);
+  if (p->d_tables) (void)hipFree(p->d_tables);
+  if (p->d_rows) (void)hipFree(p->d_rows);
+  if (p->d_sse_ws) (void)hipFree(p->d_sse_ws);
   delete p;
   return ADCT16_OK;
 }
@@ -557,7 +574,7 @@ adct16_status adct16_graph_create(adct16_plan p, const void* d_in, void* d_out, 
     e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) st = hip_fail(e, "graph instantiate");
   }
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (st != ADCT16_OK) {
     adct16_graph_destroy(g);
     return st;
@@ -574,8 +591,8 @@ adct16_status adct16_graph_launch(adct16_graph g, void* stream) {
 
 adct16_status adct16_graph_destroy(adct16_graph g) {
   if (!g) return fail(ADCT16_E_NULL, "graph is NULL");
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
   return ADCT16_OK;
 }
