@@ -213,6 +213,33 @@ adct16_status adct16_graph_create(adct16_plan plan, const void *d_in, void *d_ou
 adct16_status adct16_graph_launch(adct16_graph graph, void *stream);
 adct16_status adct16_graph_destroy(adct16_graph graph);
 
+/* ---- Host-side functions (no device involved, synchronous) ------------ */
+
+typedef enum adct16_matrix {
+  ADCT16_MATRIX_APPROX = 0,  /* C_hat = S T, the proposed orthogonal approximation (Section 2) */
+  ADCT16_MATRIX_T = 1,       /* T itself, entries in {0, +1, -1} (Section 2) */
+  ADCT16_MATRIX_WHT = 2,     /* Walsh-Hadamard matrix in natural (Sylvester) order, / 4 */
+  ADCT16_MATRIX_DCT = 3      /* orthonormal DCT-II, a_0 = 1/4, a_k = 1/sqrt(8) */
+} adct16_matrix;
+
+/* The 16x16 matrix `which` into m (256 doubles, row-major, host memory).
+ * ADCT16_E_NULL if m is NULL, ADCT16_E_MODE for an unknown `which`. */
+adct16_status adct16_transform_matrix(int32_t which, double *m);
+
+/* Section 3, Table 2: similarity and coding measures of the 16-point
+ * transform ct (256 doubles, row-major, host memory, rows = basis vectors)
+ * against the orthonormal DCT-II, for the first-order Markov model
+ * R_ij = rho^|i-j| (Section 3.2).  out (5 doubles, host memory):
+ *   out[0] DCT distortion   d2  = 1 - (1/16) sum_i (C ct^T)_ii^2
+ *   out[1] total error energy   = pi ||C - ct||_F^2
+ *   out[2] MSE                  = (1/16) tr((C - ct) R (C - ct)^T)
+ *   out[3] coding gain (dB)     = 10 log10( mean_i s_ii / (prod_i s_ii ||ct_i||)^(1/16) ),
+ *                                  s = ct R ct^T
+ *   out[4] transform efficiency (%) = sum_i |s_ii| / sum_ij |s_ij| * 100
+ * ADCT16_E_NULL for NULL pointers; ADCT16_E_MODE if rho is outside (0, 1),
+ * ct has a non-finite entry or a zero row. */
+adct16_status adct16_transform_measures(const double *ct, double rho, double *out);
+
 const char *adct16_status_string(adct16_status status);
 const char *adct16_last_error_string(void);
 

@@ -26,6 +26,8 @@ Q_NONE, Q_ZONAL, Q_ZIGZAG, Q_UNIFORM = 0, 1, 2, 3
 BACKEND_AUTO, BACKEND_VALU, BACKEND_MFMA = 0, 1, 2
 FLAG_AUTOTUNE = 1
 FLAG_EXPLICIT_COEF = 2
+# adct16_matrix
+MATRIX_APPROX, MATRIX_T, MATRIX_WHT, MATRIX_DCT = 0, 1, 2, 3
 
 _TORCH_DTYPE_CODES = {"torch.uint8": U8, "torch.int16": I16, "torch.int32": I32, "torch.float32": F32}
 
@@ -34,6 +36,7 @@ EXPORTED = [
     "adct16_forward", "adct16_quantise", "adct16_inverse", "adct16_measure",
     "adct16_compress_and_measure", "adct16_dct_forward", "adct16_forward_1d", "adct16_inverse_1d",
     "adct16_graph_create", "adct16_graph_launch", "adct16_graph_destroy",
+    "adct16_transform_matrix", "adct16_transform_measures",
     "adct16_status_string", "adct16_last_error_string",
 ]
 
@@ -85,6 +88,9 @@ def _load():
         "adct16_graph_create": [vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)],
         "adct16_graph_launch": [vp, vp],
         "adct16_graph_destroy": [vp],
+        "adct16_transform_matrix": [i32, ctypes.POINTER(ctypes.c_double)],
+        "adct16_transform_measures": [ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -236,6 +242,29 @@ def forward_1d(x, y, stream=None):
 def inverse_1d(x, y, stream=None):
     """y = T^T x for each row of an (n, 16) int32 device tensor."""
     _check(_lib.adct16_inverse_1d(_ptr(x), _ptr(y), x.shape[0], _stream(stream)))
+
+
+def transform_matrix(which: int = MATRIX_APPROX):
+    """The 16x16 matrix ``which`` (MATRIX_APPROX, MATRIX_T, MATRIX_WHT,
+    MATRIX_DCT) as a float64 numpy array."""
+    import numpy as np
+    m = np.empty((16, 16), dtype=np.float64)
+    _check(_lib.adct16_transform_matrix(which, m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return m
+
+
+def transform_measures(ct, rho: float = 0.95) -> dict:
+    """Table 2 measures of the 16x16 transform ``ct`` against the DCT-II:
+    d2, epsilon (total error energy), mse, cg (coding gain, dB), eta
+    (transform efficiency, %)."""
+    import numpy as np
+    a = np.ascontiguousarray(ct, dtype=np.float64)
+    if a.shape != (16, 16):
+        raise ValueError("ct must be 16x16")
+    out = np.empty(5, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(_lib.adct16_transform_measures(a.ctypes.data_as(dp), float(rho), out.ctypes.data_as(dp)))
+    return dict(zip(("d2", "epsilon", "mse", "cg", "eta"), out.tolist()))
 
 
 def status_string(st: int) -> str:

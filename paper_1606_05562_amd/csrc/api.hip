@@ -256,6 +256,10 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
 
 }  // namespace
 
+namespace adct16 {
+void set_last_error(const char* msg) { g_last_error = msg; }
+}  // namespace adct16
+
 extern "C" {
 
 const char* adct16_status_string(adct16_status st) {

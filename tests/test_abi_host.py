@@ -116,3 +116,72 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(os.path, "exists", lambda p: False)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+# ---------------------------------------------------------------------------
+# Host-side library functions: transform matrices and the Table 2 measures
+# (Section 3).  They need no device, so they run here.
+
+def _golden_table2():
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", "table2.json")) as f:
+        return json.load(f)
+
+
+def test_transform_matrices_match_their_definitions():
+    import numpy as np
+    from scipy.fft import dct
+    from scipy.linalg import hadamard
+    from oracle import transform as tf
+    A = _mod()
+    assert np.array_equal(A.transform_matrix(A.MATRIX_T), tf.T.astype(np.float64))
+    assert np.max(np.abs(A.transform_matrix(A.MATRIX_APPROX) - tf.c_hat())) < 1e-15
+    assert np.array_equal(A.transform_matrix(A.MATRIX_WHT), hadamard(16) / 4.0)
+    assert np.max(np.abs(A.transform_matrix(A.MATRIX_DCT) - dct(np.eye(16), type=2, norm="ortho", axis=0))) < 1e-14
+    for w in (A.MATRIX_APPROX, A.MATRIX_WHT, A.MATRIX_DCT):
+        m = A.transform_matrix(w)
+        assert np.max(np.abs(m @ m.T - np.eye(16))) < 1e-14
+
+
+@pytest.mark.parametrize("row,which", [("Proposed", 0), ("WHT", 2), ("DCT", 3)])
+def test_transform_measures_reproduce_table2(row, which):
+    # Each printed value of Table 2 to its printed number of decimals.
+    A = _mod()
+    got = A.transform_measures(A.transform_matrix(which), 0.95)
+    for k, txt in _golden_table2()["rows"][row].items():
+        dec = len(txt.split(".")[1]) if "." in txt else 4
+        assert abs(got[k] - float(txt)) <= 0.5 * 10.0 ** (-dec) + 1e-12, (row, k, got[k])
+
+
+def test_transform_measures_equal_oracle_on_other_matrices():
+    import numpy as np
+    from oracle import metrics
+    from oracle import transform as tf
+    A = _mod()
+    rng = np.random.default_rng(5)
+    q, _ = np.linalg.qr(rng.standard_normal((16, 16)))
+    for ct, rho in ((q, 0.95), (tf.c_hat(), 0.5), (A.transform_matrix(A.MATRIX_WHT), 0.9)):
+        got = A.transform_measures(ct, rho)
+        want = metrics.table2_row(tf.dct_matrix(), ct, rho)
+        for k in want:
+            assert abs(got[k] - want[k]) <= 1e-10 * max(1.0, abs(want[k])), k
+
+
+def test_transform_measures_errors():
+    import numpy as np
+    A = _mod()
+    m = A.transform_matrix(A.MATRIX_APPROX)
+    for rho in (0.0, 1.0, -0.5, float("nan")):
+        with pytest.raises(A.Adct16Error) as e:
+            A.transform_measures(m, rho)
+        assert e.value.status == A.E_MODE
+    bad = m.copy()
+    bad[3] = 0.0
+    with pytest.raises(A.Adct16Error) as e:
+        A.transform_measures(bad)
+    assert e.value.status == A.E_MODE
+    with pytest.raises(A.Adct16Error) as e:
+        A.transform_matrix(9)
+    assert e.value.status == A.E_MODE
+    assert A.lib().adct16_transform_matrix(0, None) == A.E_NULL
+    assert A.lib().adct16_transform_measures(None, 0.95, None) == A.E_NULL
