@@ -220,27 +220,41 @@ def bench_ragged(args, A, torch):
     content; one fused forward -> zonal r -> inverse -> per-image PSNR."""
     from synth import BASE_SEED, pack_images, ragged_batch
     ims = ragged_batch(BASE_SEED + 4, args.frames or 64)
-    buf, hs, ws, ps, offs = pack_images(ims)
+    # rows padded to whole 128-byte cache lines (the batch layout is ours to choose)
+    buf, hs, ws, ps, offs = pack_images(ims, align_elems=128, pitch_multiple=128)
     dev = torch.from_numpy(buf).cuda()
     out = torch.empty_like(dev)
     n = len(ims)
     sse = torch.zeros(n, dtype=torch.int64, device="cuda")
     psnr = torch.zeros(n, dtype=torch.float64, device="cuda")
+    backend = {"auto": A.BACKEND_AUTO, "valu": A.BACKEND_VALU, "mfma": A.BACKEND_MFMA}[args.backend]
     plan = A.Plan(hs, ws, ps, offs, in_dtype=A.U8, coef_dtype=A.I32, qmode=A.Q_ZONAL, r=args.r,
-                  flags=A.FLAG_AUTOTUNE)
+                  backend=backend, flags=A.FLAG_AUTOTUNE)
     stream = torch.cuda.current_stream()
     step = lambda: plan.compress_and_measure(dev, out, None, sse, psnr)
     for _ in range(args.warmup):
         step()
     ms = _events_ms(step, args.steps, stream)
     npx = int(sum(h * w for h, w in zip(hs, ws)))
-    return {"metric": "Gpixel/s 2D fwd+quant+inv 16x16, ragged batch", "value": round(npx / (ms * 1e-3) / 1e9, 4),
-            "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "u8", "data": "synthetic",
-            "config": {"workload": f"{n} uint8 images, sides U[64,3840] rounded to 16, "
-                                   f"{npx / 1e6:.1f} Mpx; zonal r={args.r}", "plan": json.loads(plan.info())},
-            "roofline": {"bound": "hbm", "achieved": round(2 * npx / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(2 * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    res = {"metric": "Gpixel/s 2D fwd+quant+inv 16x16, ragged batch", "value": round(npx / (ms * 1e-3) / 1e9, 4),
+           "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": f"{n} uint8 images, sides U[64,3840] rounded to 16, "
+                                  f"{npx / 1e6:.1f} Mpx; zonal r={args.r}", "plan": json.loads(plan.info())},
+           "roofline": {"bound": "hbm", "achieved": round(2 * npx / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(2 * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    if not args.no_variants:
+        v = {}
+        for name, be in (("valu", A.BACKEND_VALU), ("mfma", A.BACKEND_MFMA)):
+            p2 = A.Plan(hs, ws, ps, offs, in_dtype=A.U8, coef_dtype=A.I32, qmode=A.Q_ZONAL, r=args.r,
+                        backend=be, flags=A.FLAG_AUTOTUNE)
+            f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)
+            f()
+            t = _events_ms(f, args.steps, stream)
+            v[f"{name}_gpix_s"] = round(npx / (t * 1e-3) / 1e9, 4)
+            v[f"{name}_plan"] = json.loads(p2.info())
+        res["variants"] = v
+    return res
 
 
 def bench_residual(args, A, torch):
@@ -264,7 +278,7 @@ def bench_residual(args, A, torch):
             dev = torch.from_numpy(buf).cuda()
             rec = torch.empty_like(dev)
             plan = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, qmode=A.Q_UNIFORM, q=q,
-                          qcoef_dtype=A.I16, out_dtype=A.I16)
+                          qcoef_dtype=A.I16, out_dtype=A.I16, flags=A.FLAG_AUTOTUNE)
             lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
             sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
             psnr = torch.zeros(len(hs), dtype=torch.float64, device="cuda")
@@ -275,6 +289,22 @@ def bench_residual(args, A, torch):
         ms = _events_ms(run, max(2, args.steps // 4), stream)
         out[f"q{q}_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
         out[f"q{q}_psnr_y_db"] = round(float(keep[0][5][0]), 4)
+        del graphs, keep
+        # the whole stream as one batch (one plan, one launch)
+        buf, hs, ws, ps, offs = pack_images(planes)
+        dev = torch.from_numpy(buf).cuda()
+        rec = torch.empty_like(dev)
+        plan = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, qmode=A.Q_UNIFORM, q=q,
+                      qcoef_dtype=A.I16, out_dtype=A.I16, flags=A.FLAG_AUTOTUNE)
+        lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
+        sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
+        psnr = torch.zeros(len(hs), dtype=torch.float64, device="cuda")
+        f = lambda: plan.compress_and_measure(dev, rec, lv, sse, psnr)
+        f()
+        ms = _events_ms(f, max(2, args.steps // 4), stream)
+        out[f"q{q}_one_launch_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
+        out[f"q{q}_one_launch_plan"] = json.loads(plan.info())
+        del dev, rec, lv
     return {"metric": "Gsample/s 2D fwd+quant+inv 16x16, 4:2:0 int16 residual stream, graph per frame",
             "value": out["q16_gsample_s"], "unit": "Gsample/s", "n_gpus": 1, "steps": args.steps,
             "dtype": "i16/f32/f64", "data": "synthetic", "higher_is_better": True,

@@ -30,6 +30,11 @@
  *   a multiple of 16; offset*esize and pitch*esize multiples of 16 bytes;
  *   the buffer base 16-byte aligned.  Reconstructions use the same
  *   offsets and pitches as the input (in elements of their own type).
+ *   Performance: with pitches, offsets and buffers that are multiples of
+ *   128 bytes, every row segment the matrix-core kernel moves is a whole
+ *   cache line and it streams with non-temporal accesses; other layouts
+ *   give the same results more slowly (adct16_plan_info reports
+ *   "rows_line_aligned").
  * - Blocks are numbered in raster order per image; images follow each other.
  *   Coefficient buffers are block-major: block b occupies 256 consecutive
  *   elements, element u*16+v holding coefficient (u, v), u the vertical and
@@ -87,7 +92,9 @@ typedef enum adct16_backend {
 } adct16_backend;
 
 enum {
-  ADCT16_FLAG_AUTOTUNE = 1,      /* time the candidate kernels at plan creation */
+  ADCT16_FLAG_AUTOTUNE = 1,      /* time the candidate launch shapes (and, with
+                                    ADCT16_BACKEND_AUTO, both backends) of the fused call at
+                                    plan creation on scratch buffers (allocates) */
   ADCT16_FLAG_EXPLICIT_COEF = 2  /* matrix-core fused call: form the coefficients Z of every
                                     block explicitly even for separable masks (by default the
                                     forward column pass, the zonal retention and the inverse

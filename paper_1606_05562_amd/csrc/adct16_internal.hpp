@@ -23,10 +23,6 @@ constexpr int kGroupThreads = 64 * kWavesPerGroup;
 #ifndef ADCT16_MFMA_MIN_WG
 #define ADCT16_MFMA_MIN_WG 1
 #endif
-// Non-temporal 16-byte loads and stores in the matrix-core fused kernel.
-#ifndef ADCT16_MFMA_NT
-#define ADCT16_MFMA_NT 1
-#endif
 // Blocks of a strip carried through the matrix-core stages together.
 #ifndef ADCT16_MFMA_BATCH
 #define ADCT16_MFMA_BATCH 8
@@ -39,15 +35,22 @@ struct ImageDesc {
   int32_t h, w, pitch;  // true size and row pitch (elements)
   int32_t bx, by;       // blocks across / down
   int32_t sx;           // strips across = ceil(bx / 8)
-  int32_t pad[2];
+  int64_t task_begin;   // index of the image's first task in the task table
 };
 static_assert(sizeof(ImageDesc) == 56, "ImageDesc layout");
 
-// One block row (16 image rows) of one image: the unit of work that the
-// matrix-core fused kernel hands out to wavefronts cyclically.
+// Up to kTaskStrips consecutive strips of one block row of one image: the
+// unit of work that the matrix-core fused kernel deals out to wavefronts
+// cyclically (strips sx0 .. min(sx0 + kTaskStrips, sx) - 1 of block row sy).
+#ifndef ADCT16_TASK_STRIPS
+#define ADCT16_TASK_STRIPS 4
+#endif
+constexpr int kTaskStrips = ADCT16_TASK_STRIPS;
 struct RowTask {
-  int32_t img, sy;
+  int32_t img;
+  int16_t sy, sx0;
 };
+static_assert(sizeof(RowTask) == 8, "RowTask layout");
 
 // Per-plan constant tables, indexed u * 16 + v.
 struct Tables {
@@ -79,14 +82,16 @@ struct Params {
   void* qcoef;
   unsigned long long* sse;
   double* psnr;
-  const RowTask* rows;  // every block row of the batch, image by image
+  const RowTask* rows;  // the batch's strips in tasks, image by image, row by row
   int64_t n_rows;
+  uint32_t* task_sse;   // per-task SSE partials (matrix-core fused kernel)
 };
 
 // Launchers (return hipSuccess or the launch error).  `grid` is the number
 // of workgroups of kGroupThreads threads for the persistent strip kernels.
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 hipError_t launch_psnr_finalize(const Params& P, hipStream_t s);
+hipError_t launch_task_sse_reduce(const Params& P, hipStream_t s);
 hipError_t launch_valu_forward(int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s);
 hipError_t launch_valu_fused(int in_kind, int mode, int qout_kind, int out_kind, const Params& P,
                              int grid, hipStream_t s);
@@ -97,7 +102,8 @@ hipError_t launch_measure(int in_kind, int out_kind, const Params& P, int grid, 
 hipError_t launch_1d(bool inverse, const int32_t* x, int32_t* y, int64_t n, hipStream_t s);
 
 hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStream_t s);
-hipError_t launch_mfma_fused(bool zigzag, bool collapse, int out_kind, const Params& P, int grid, hipStream_t s);
+hipError_t launch_mfma_fused(bool zigzag, bool collapse, int out_kind, bool nt, const Params& P, int grid,
+                             hipStream_t s);
 hipError_t launch_dct_mfma(int in_kind, int precision, const Params& P, float* y, int grid,
                            hipStream_t s);
 

@@ -83,6 +83,8 @@ struct adct16_plan_s {
   Tables* d_tables = nullptr;
   RowTask* d_rows = nullptr;
   int64_t n_rows = 0;
+  uint32_t* d_task_sse = nullptr;  // per-task SSE partials of the matrix-core fused kernel
+  bool lines_aligned = false;       // every pitch and image offset a multiple of 128 bytes
   unsigned long long* d_sse_ws = nullptr;
   int grid = 0;           // persistent workgroups for the strip kernels
   int backend = ADCT16_BACKEND_VALU;   // resolved backend of the fused/forward calls
@@ -105,6 +107,7 @@ Params base_params(const adct16_plan_s* p) {
   P.tables = p->d_tables;
   P.rows = p->d_rows;
   P.n_rows = p->n_rows;
+  P.task_sse = p->d_task_sse;
   return P;
 }
 
@@ -121,16 +124,27 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void*
   P.qcoef = d_qcoef;
   P.sse = d_sse ? reinterpret_cast<unsigned long long*>(d_sse) : p->d_sse_ws;
   P.psnr = d_psnr;
-  hipError_t e = launch_zero_u64(P.sse, P.n_images, s);
-  if (e != hipSuccess) return hip_fail(e, "zero SSE");
   const int qk = d_qcoef ? p->qcoef_kind : CF_NONE;
   const int ok = d_out ? p->out_kind : OUT_NONE;
-  // The matrix-core fused kernel writes reconstructions and errors; a call
-  // that also asks for the retained coefficients runs the vector kernel.
-  if (backend == ADCT16_BACKEND_MFMA && qk == CF_NONE)
-    e = launch_mfma_fused(p->d.qmode == ADCT16_Q_ZIGZAG, !(p->d.flags & ADCT16_FLAG_EXPLICIT_COEF), ok, P, grid, s);
-  else
-    e = launch_valu_fused(p->in_kind, p->mode, qk, ok, P, grid, s);
+  hipError_t e;
+  // The matrix-core fused kernel writes reconstructions and per-task SSE
+  // partials, which a second kernel sums per image (SSE and PSNR); a call
+  // that also asks for the retained coefficients runs the vector kernel,
+  // which accumulates per image directly.
+  if (backend == ADCT16_BACKEND_MFMA && qk == CF_NONE) {
+    // whole-cache-line rows: streaming (non-temporal) accesses pay off
+    const bool nt = p->lines_aligned && (reinterpret_cast<uintptr_t>(d_in) & 127) == 0 &&
+                    (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 127) == 0);
+    e = launch_mfma_fused(p->d.qmode == ADCT16_Q_ZIGZAG, !(p->d.flags & ADCT16_FLAG_EXPLICIT_COEF), ok, nt, P,
+                          grid, s);
+    if (e != hipSuccess) return hip_fail(e, "fused kernel");
+    e = launch_task_sse_reduce(P, s);
+    if (e != hipSuccess) return hip_fail(e, "SSE reduction kernel");
+    return ADCT16_OK;
+  }
+  e = launch_zero_u64(P.sse, P.n_images, s);
+  if (e != hipSuccess) return hip_fail(e, "zero SSE");
+  e = launch_valu_fused(p->in_kind, p->mode, qk, ok, P, grid, s);
   if (e != hipSuccess) return hip_fail(e, "fused kernel");
   if (d_psnr) {
     e = launch_psnr_finalize(P, s);
@@ -153,7 +167,7 @@ std::mutex g_tune_mu;
 
 std::string tune_key(const adct16_plan_s* p, const char* arch) {
   std::ostringstream k;
-  k << arch << "/cu" << p->cu_count << "/in" << p->in_kind << "/m" << p->mode << "/q" << p->d.qmode
+  k << arch << "/cu" << p->cu_count << "/b" << p->d.backend << "/in" << p->in_kind << "/m" << p->mode << "/q" << p->d.qmode
     << "/o" << p->out_kind << "/f" << (p->d.flags & ADCT16_FLAG_EXPLICIT_COEF)
     << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips);
   return k.str();
@@ -218,8 +232,9 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
   // load, and a sequential sweep would favour whichever ran first.
   struct Cand { int backend, wgpc, grid; float best; };
   std::vector<Cand> cands;
-  std::vector<int> backends = {ADCT16_BACKEND_VALU};
-  if (mfma_supported(p)) backends.push_back(ADCT16_BACKEND_MFMA);
+  std::vector<int> backends;
+  if (p->d.backend != ADCT16_BACKEND_MFMA) backends.push_back(ADCT16_BACKEND_VALU);
+  if (p->d.backend != ADCT16_BACKEND_VALU && mfma_supported(p)) backends.push_back(ADCT16_BACKEND_MFMA);
   for (int b : backends)
     for (int wg : {1, 2, 3, 4, 6, 8, 12})
       cands.push_back({b, wg, (int)std::min<int64_t>(p->cu_count * wg, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup), 1e30f});
@@ -358,6 +373,9 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   p->mode = uniform ? MODE_UNIFORM : MODE_MASK;
   p->n_blocks = blocks;
   p->n_strips = strips;
+  p->lines_aligned = true;
+  for (const ImageDesc& g : images)
+    if (((int64_t)g.pitch * es) % 128 || (g.offset * es) % 128) p->lines_aligned = false;
 
   // constant tables
   Tables t;
@@ -380,12 +398,17 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   }
   t.rsep = d->qmode == ADCT16_Q_ZONAL ? d->r : 16;
   std::vector<RowTask> rows;
-  for (size_t i = 0; i < images.size(); ++i)
-    for (int sy = 0; sy < images[i].by; ++sy) rows.push_back(RowTask{(int32_t)i, sy});
+  for (size_t i = 0; i < images.size(); ++i) {
+    images[i].task_begin = (int64_t)rows.size();
+    for (int sy = 0; sy < images[i].by; ++sy)
+      for (int sx0 = 0; sx0 < images[i].sx; sx0 += kTaskStrips)
+        rows.push_back(RowTask{(int32_t)i, (int16_t)sy, (int16_t)sx0});
+  }
   p->n_rows = (int64_t)rows.size();
   bool ok = hipMalloc(&p->d_images, sizeof(ImageDesc) * images.size()) == hipSuccess &&
             hipMalloc(&p->d_tables, sizeof(Tables)) == hipSuccess &&
             hipMalloc(&p->d_rows, sizeof(RowTask) * rows.size()) == hipSuccess &&
+            hipMalloc(&p->d_task_sse, sizeof(uint32_t) * rows.size()) == hipSuccess &&
             hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size()) == hipSuccess;
   ok = ok && hipMemcpy(p->d_images, images.data(), sizeof(ImageDesc) * images.size(), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_tables, &t, sizeof t, hipMemcpyHostToDevice) == hipSuccess &&
@@ -401,22 +424,20 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   int wgpc = 4;
   if (const char* env = getenv("ADCT16_WG_PER_CU")) wgpc = std::max(1, std::min(64, atoi(env)));
   p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)p->cu_count * wgpc, max_groups));
-  if (d->backend == ADCT16_BACKEND_MFMA) {
-    if (!mfma_supported(p)) {
-      adct16_plan_destroy(p);
-      return fail(ADCT16_E_MODE, "MFMA backend supports U8 input, retention modes and U8 output");
-    }
-    p->backend = ADCT16_BACKEND_MFMA;
-    p->tuned = "requested";
-  } else if (d->backend == ADCT16_BACKEND_VALU) {
-    p->backend = ADCT16_BACKEND_VALU;
-    p->tuned = "requested";
-  } else if (d->flags & ADCT16_FLAG_AUTOTUNE) {
+  if (d->backend == ADCT16_BACKEND_MFMA && !mfma_supported(p)) {
+    adct16_plan_destroy(p);
+    return fail(ADCT16_E_MODE, "MFMA backend supports U8 input, retention modes and U8 output");
+  }
+  if (d->flags & ADCT16_FLAG_AUTOTUNE) {
+    // a requested backend restricts the search to its launch shapes
     adct16_status st = autotune(p, prop.gcnArchName);
     if (st != ADCT16_OK) {
       adct16_plan_destroy(p);
       return st;
     }
+  } else if (d->backend == ADCT16_BACKEND_MFMA || d->backend == ADCT16_BACKEND_VALU) {
+    p->backend = d->backend;
+    p->tuned = "requested";
   } else {
     p->backend = ADCT16_BACKEND_VALU;
     p->tuned = "default";
@@ -431,6 +452,7 @@ adct16_status adct16_plan_destroy(adct16_plan p) {
   if (p->d_images) (void)hipFree(p->d_images);
   if (p->d_tables) (void)hipFree(p->d_tables);
   if (p->d_rows) (void)hipFree(p->d_rows);
+  if (p->d_task_sse) (void)hipFree(p->d_task_sse);
   if (p->d_sse_ws) (void)hipFree(p->d_sse_ws);
   delete p;
   return ADCT16_OK;
@@ -449,7 +471,8 @@ adct16_status adct16_plan_info(adct16_plan p, char* buf, int32_t len) {
   std::ostringstream o;
   o << "{\"backend\": \"" << (p->backend == ADCT16_BACKEND_MFMA ? "mfma" : "valu") << "\", \"grid\": " << p->grid
     << ", \"threads\": " << kGroupThreads << ", \"strips\": " << p->n_strips << ", \"blocks\": " << p->n_blocks
-    << ", \"cus\": " << p->cu_count << ", \"choice\": \"" << p->tuned << "\"}";
+    << ", \"cus\": " << p->cu_count << ", \"rows_line_aligned\": " << (p->lines_aligned ? "true" : "false")
+    << ", \"choice\": \"" << p->tuned << "\"}";
   const std::string s = o.str();
   if ((int32_t)s.size() + 1 > len) return fail(ADCT16_E_SHAPE, "buffer too small (%d needed)", (int)s.size() + 1);
   memcpy(buf, s.c_str(), s.size() + 1);

@@ -118,24 +118,29 @@ __device__ __forceinline__ void operands_to_rows(int* lds, int r, int c, int g, 
   wave_lds_sync();
 }
 
-// Streaming accesses: every byte of the batch is read once and written once,
-// so the 16-byte row accesses carry the non-temporal hint.
+// Streaming accesses: every byte of the batch is read once and written
+// once, so when the row segments are whole cache lines (128-byte aligned
+// pitches, offsets and buffers) the 16-byte row accesses carry the
+// non-temporal hint.  With unaligned rows a segment straddles two lines that
+// neighbouring strips share, and the hint would make them fetch it twice.
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
+template <bool NT>
 __device__ __forceinline__ uint4 ld_row16(const uint8_t* p) {
-#if ADCT16_MFMA_NT
-  const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
-  return make_uint4(v.x, v.y, v.z, v.w);
-#else
-  return *reinterpret_cast<const uint4*>(p);
-#endif
+  if constexpr (NT) {
+    const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+  } else {
+    return *reinterpret_cast<const uint4*>(p);
+  }
 }
+template <bool NT>
 __device__ __forceinline__ void st_row16(uint8_t* p, const uint4& v) {
-#if ADCT16_MFMA_NT
-  const v4u w = {v.x, v.y, v.z, v.w};
-  __builtin_nontemporal_store(w, reinterpret_cast<v4u*>(p));
-#else
-  *reinterpret_cast<uint4*>(p) = v;
-#endif
+  if constexpr (NT) {
+    const v4u w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<v4u*>(p));
+  } else {
+    *reinterpret_cast<uint4*>(p) = v;
+  }
 }
 
 // The fields of an image that the fused kernel uses, held in scalars.
@@ -143,17 +148,6 @@ struct ImgGeom {
   int64_t offset;
   int32_t h, w, pitch, bx, sx;
 };
-
-__device__ __forceinline__ ImgGeom geom_of(const ImageDesc* __restrict__ images, int i) {
-  ImgGeom m;
-  m.offset = images[i].offset;
-  m.h = images[i].h;
-  m.w = images[i].w;
-  m.pitch = images[i].pitch;
-  m.bx = images[i].bx;
-  m.sx = images[i].sx;
-  return m;
-}
 
 // One dword of block row q (columns 4g..4g+3), edge-extended.
 __device__ __forceinline__ unsigned load_dword_edge(const uint8_t* img, const ImgGeom& d, int y, int x0) {
@@ -170,7 +164,7 @@ __device__ __forceinline__ unsigned load_dword_edge(const uint8_t* img, const Im
 template <bool ZIGZAG, bool COLLAPSE, int OUT>
 __device__ __forceinline__ void edge_strip(const ImgGeom& d, int sy, int sxi, const uint8_t* in, uint8_t* outp,
                                            const MfmaConsts& k, const bool (&keepz)[4], int g, int q,
-                                           SseAcc& acc) {
+                                           unsigned& sse) {
   const int y0 = sy * 16;
   const int y = min(y0 + q, d.h - 1);
   const bool rowok = (y0 + q) < d.h;
@@ -193,22 +187,67 @@ __device__ __forceinline__ void edge_strip(const ImgGeom& d, int sy, int sxi, co
         else for (int j = 0; j < n; ++j) o[j] = (uint8_t)(out[b] >> (8 * j));
       }
       const unsigned m = n >= 4 ? 0xffffffffu : ((1u << (8 * n)) - 1u);
-      acc.lane += sse4(x[b] & m, out[b] & m);
+      sse += sse4(x[b] & m, out[b] & m);
     }
   }
 }
 
-// Work distribution: wavefront w of W takes block rows w, w + W, w + 2W, ...
-// of the batch (the row table lists them image by image) and walks each row
-// strip by strip, so that at any time the wavefronts of the chip stream
-// through one contiguous window of the batch.  The rows of the next interior
-// strip (possibly in the next block row) are loaded one strip ahead; the
-// stores of interior strips are unconditional, and each branch ends with an
-// explicit wait for everything but its own stores, so that the loads of the
-// next strip never wait for the stores of the previous one.  The image and row tables
-// are separate read-only, non-aliased arguments so that their uniform reads
-// inside the loop are scalar loads.
-template <bool ZIGZAG, bool COLLAPSE, int OUT>
+// Task registers: lane k of a wavefront holds the table entry and the image
+// geometry of its task t0 + k W (the k-th of its next 64 tasks), gathered
+// with one set of vector loads; the task in use is read back with readlane.
+// The table latency is paid once per 64 tasks instead of once per task.
+struct TaskRegs {
+  int sy, sx0, off_lo, off_hi, h, w, pitch, bx, sx;
+};
+
+__device__ __forceinline__ TaskRegs gather_tasks(const ImageDesc* __restrict__ images,
+                                                 const RowTask* __restrict__ rows, int64_t t0, int64_t W,
+                                                 int64_t n, int lane) {
+  TaskRegs tr = {0, 0, 0, 0, 1, 1, 0, 0, 1};
+  const int64_t tk = t0 + (int64_t)lane * W;
+  if (tk < n) {
+    const RowTask e = rows[tk];
+    const ImageDesc* d = images + e.img;
+    const int64_t off = d->offset;
+    tr.sy = e.sy;
+    tr.sx0 = e.sx0;
+    tr.off_lo = (int)(uint32_t)off;
+    tr.off_hi = (int)(off >> 32);
+    tr.h = d->h;
+    tr.w = d->w;
+    tr.pitch = d->pitch;
+    tr.bx = d->bx;
+    tr.sx = d->sx;
+  }
+  // complete the gather here, so that reading a task (every few strips)
+  // never waits on memory; vmcnt(0), other counters unchanged
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  return tr;
+}
+
+__device__ __forceinline__ ImgGeom task_geom(const TaskRegs& tr, int k) {
+  ImgGeom m;
+  m.offset = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(tr.off_hi, k) << 32) |
+                       (uint32_t)__builtin_amdgcn_readlane(tr.off_lo, k));
+  m.h = __builtin_amdgcn_readlane(tr.h, k);
+  m.w = __builtin_amdgcn_readlane(tr.w, k);
+  m.pitch = __builtin_amdgcn_readlane(tr.pitch, k);
+  m.bx = __builtin_amdgcn_readlane(tr.bx, k);
+  m.sx = __builtin_amdgcn_readlane(tr.sx, k);
+  return m;
+}
+
+// Work distribution: wavefront w of W takes tasks w, w + W, w + 2W, ... of
+// the batch (the task table lists runs of up to four strips of one block
+// row, image by image and row by row) and walks each task strip by strip,
+// so that at any time the wavefronts of the chip stream through one
+// contiguous window of the batch, while short tasks keep the work per
+// wavefront even.  The rows of the next interior strip (possibly of the
+// next task) are loaded one strip ahead; the stores of interior strips are
+// unconditional, and each branch ends with an explicit wait for everything
+// but its own stores, so that the loads of the next strip never wait for
+// the stores of the previous one.
+template <bool ZIGZAG, bool COLLAPSE, int OUT, bool NT>
 __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fused(
     Params P, const ImageDesc* __restrict__ images, const RowTask* __restrict__ rows) {
   __shared__ int lds_all[kWavesPerGroup * 512];
@@ -221,10 +260,14 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
   uint8_t* outp = reinterpret_cast<uint8_t*>(P.out);
   const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
-  int64_t t = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
-  if (t >= P.n_rows) return;
-  int img = rows[t].img, sy = rows[t].sy, sxi = 0;
-  ImgGeom d = geom_of(images, img);
+  int64_t t0 = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
+  if (t0 >= P.n_rows) return;
+  TaskRegs tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
+  int kk = 0;  // current task: t0 + kk W
+  int sy = __builtin_amdgcn_readlane(tr.sy, 0);
+  int sxi = __builtin_amdgcn_readlane(tr.sx0, 0);
+  ImgGeom d = task_geom(tr, 0);
+  int sxe = min(sxi + kTaskStrips, d.sx);  // end of the current task
   auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
     return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
   };
@@ -233,28 +276,40 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
     return dd.offset + (int64_t)(ssy * 16 + r) * dd.pitch + ssxi * (16 * kStripBlocks) + 16 * c;
   };
   uint4 nr[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
-  if (interior(d, sy, 0)) {
-    const int64_t o = lane_off(d, sy, 0);
-    nr[0] = ld_row16(in + o);
-    nr[1] = ld_row16(in + o + 8 * (int64_t)d.pitch);
+  if (interior(d, sy, sxi)) {
+    const int64_t o = lane_off(d, sy, sxi);
+    nr[0] = ld_row16<NT>(in + o);
+    nr[1] = ld_row16<NT>(in + o + 8 * (int64_t)d.pitch);
     // complete these loads here rather than at the loop head, where the
     // wait would also cover the previous strip's stores
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters unchanged
   }
-  SseAcc acc;
+  // SSE: per lane over the current task, reduced across the wavefront at
+  // the end of the task and stored as that task's partial (at most 16
+  // strips x 2048 pixels x 255^2 < 2^32); a second kernel sums the partials
+  // of each image.  No atomics: tasks of one image run on many wavefronts at
+  // once, and contended atomics would serialise them.
+  static_assert(kTaskStrips <= 16, "per-task SSE must fit 32 bits");
+  unsigned lane_sse = 0;
+  int64_t tcur = t0;  // index of the current task
   for (;;) {
     // the strip after this one
-    int nimg = img, nsy = sy, nsxi = sxi + 1;
+    const bool task_end = sxi + 1 == sxe;
+    int nsy = sy, nsxi = sxi + 1, nsxe = sxe;
     ImgGeom nd = d;
     bool more = true;
-    if (nsxi == d.sx) {
-      t += W;
-      more = t < P.n_rows;
+    if (task_end) {
+      if (++kk == 64) {  // next 64 tasks
+        kk = 0;
+        t0 += 64 * W;
+        tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
+      }
+      more = t0 + kk * W < P.n_rows;
       if (more) {
-        nimg = rows[t].img;
-        nsy = rows[t].sy;
-        nsxi = 0;
-        if (nimg != img) nd = geom_of(images, nimg);
+        nsy = __builtin_amdgcn_readlane(tr.sy, kk);
+        nsxi = __builtin_amdgcn_readlane(tr.sx0, kk);
+        nd = task_geom(tr, kk);
+        nsxe = min(nsxi + kTaskStrips, nd.sx);
       }
     }
     const uint4 cr[2] = {nr[0], nr[1]};
@@ -263,8 +318,8 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
     auto prefetch = [&]() {
       if (more && interior(nd, nsy, nsxi)) {
         const int64_t o = lane_off(nd, nsy, nsxi);
-        nr[0] = ld_row16(in + o);
-        nr[1] = ld_row16(in + o + 8 * (int64_t)nd.pitch);
+        nr[0] = ld_row16<NT>(in + o);
+        nr[1] = ld_row16<NT>(in + o + 8 * (int64_t)nd.pitch);
       }
     };
     if (interior(d, sy, sxi)) {
@@ -276,28 +331,31 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
         uint4 orow[2];
         operands_to_rows(lds, r, c, g, q, out, orow);
         const int64_t o = lane_off(d, sy, sxi);
-        st_row16(outp + o, orow[0]);
-        st_row16(outp + o + 8 * (int64_t)d.pitch, orow[1]);
+        st_row16<NT>(outp + o, orow[0]);
+        st_row16<NT>(outp + o + 8 * (int64_t)d.pitch, orow[1]);
         // the prefetched rows were issued before these two stores: wait for
         // everything but the stores (vmcnt(2))
         __builtin_amdgcn_s_waitcnt(0x0F72);
       } else {
         __builtin_amdgcn_s_waitcnt(0x0F70);
       }
-      unsigned s = 0;
 #pragma unroll
-      for (int b = 0; b < kStripBlocks; ++b) s += sse4(x[b], out[b]);
-      acc.lane += s;
+      for (int b = 0; b < kStripBlocks; ++b) lane_sse += sse4(x[b], out[b]);
     } else {
       prefetch();
-      edge_strip<ZIGZAG, COLLAPSE, OUT>(d, sy, sxi, in, outp, k, keepz, g, q, acc);
+      edge_strip<ZIGZAG, COLLAPSE, OUT>(d, sy, sxi, in, outp, k, keepz, g, q, lane_sse);
       __builtin_amdgcn_s_waitcnt(0x0F70);
     }
-    if (!more || nimg != img) acc.flush(P.sse, img);
+    if (task_end) {
+      const unsigned task_sum = wave_sum_u32(lane_sse);
+      if (lane == 0) P.task_sse[tcur] = task_sum;
+      lane_sse = 0;
+      tcur = t0 + kk * W;
+    }
     if (!more) break;
-    img = nimg;
     sy = nsy;
     sxi = nsxi;
+    sxe = nsxe;
     d = nd;
   }
 }
@@ -422,18 +480,25 @@ hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStre
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma_fused(bool zigzag, bool collapse, int out_kind, const Params& P, int grid, hipStream_t s) {
+template <bool NT>
+hipError_t launch_mfma_fused_nt(bool zigzag, bool collapse, int out_kind, const Params& P, int grid, hipStream_t s) {
   if (zigzag) {
-    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_U8>), grid, s, P, P.images, P.rows);
-    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_NONE>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_U8, NT>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_NONE, NT>), grid, s, P, P.images, P.rows);
   } else if (collapse) {
-    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_U8>), grid, s, P, P.images, P.rows);
-    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_NONE>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_U8, NT>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_NONE, NT>), grid, s, P, P.images, P.rows);
   } else {
-    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_U8>), grid, s, P, P.images, P.rows);
-    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_NONE>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_U8, NT>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_NONE, NT>), grid, s, P, P.images, P.rows);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_mfma_fused(bool zigzag, bool collapse, int out_kind, bool nt, const Params& P, int grid,
+                             hipStream_t s) {
+  return nt ? launch_mfma_fused_nt<true>(zigzag, collapse, out_kind, P, grid, s)
+            : launch_mfma_fused_nt<false>(zigzag, collapse, out_kind, P, grid, s);
 }
 
 hipError_t launch_dct_mfma(int in_kind, int precision, const Params& P, float* y, int grid, hipStream_t s) {

@@ -699,6 +699,24 @@ __global__ void k_psnr(Params P) {
   }
 }
 
+// Per-image SSE from the per-task partials of the matrix-core fused kernel
+// (one wavefront per image; an image's tasks are contiguous), and PSNR.
+__global__ __launch_bounds__(64) void k_task_sse_reduce(Params P) {
+  const int i = blockIdx.x;
+  const int64_t b = P.images[i].task_begin;
+  const int64_t e = i + 1 < P.n_images ? P.images[i + 1].task_begin : P.n_rows;
+  unsigned long long v = 0;
+  for (int64_t t = b + threadIdx.x; t < e; t += 64) v += P.task_sse[t];
+  v = wave_sum_u64(v);
+  if (threadIdx.x == 0) {
+    P.sse[i] = v;
+    if (P.psnr) {
+      const ImageDesc& d = P.images[i];
+      P.psnr[i] = v == 0 ? __builtin_huge_val() : 10.0 * log10(65025.0 * (double)d.h * (double)d.w / (double)v);
+    }
+  }
+}
+
 template <bool INV>
 __global__ void k_1d(const int32_t* x, int32_t* y, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -726,6 +744,11 @@ __global__ void k_1d(const int32_t* x, int32_t* y, int64_t n) {
 
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_task_sse_reduce(const Params& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_task_sse_reduce, dim3(P.n_images), dim3(64), 0, s, P);
   return hipGetLastError();
 }
 

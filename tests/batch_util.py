@@ -8,10 +8,10 @@ from synth import pack_images
 
 
 class Batch:
-    def __init__(self, images: list[np.ndarray]):
+    def __init__(self, images: list[np.ndarray], align: int = 16):
         import torch
         self.images = images
-        self.buf, self.h, self.w, self.p, self.o = pack_images(images)
+        self.buf, self.h, self.w, self.p, self.o = pack_images(images, align_elems=align, pitch_multiple=align)
         self.dtype = self.buf.dtype
         self.dev = torch.from_numpy(self.buf.copy()).cuda()
         self.blocks = [((h + 15) // 16) * ((w + 15) // 16) for h, w in zip(self.h, self.w)]

@@ -99,11 +99,14 @@ def test_mfma_equals_adder_kernel_on_extremes(batch_worst, qmode, r, explicit):
     assert np.array_equal(a[0][0], want) and a[1][0] == s
 
 
-def test_mfma_ragged():
+@pytest.mark.parametrize("align", [16, 128])
+def test_mfma_ragged(align):
+    # align 128: whole-cache-line rows, the streaming (non-temporal) variant
     rng = np.random.default_rng(21)
     sizes = [(int(x), int(y)) for x, y in rng.integers(16, 300, size=(7, 2))]
+    sizes += [(272, 384), (32, 128)]  # widths that are whole strips
     ims = [mixed_image(BASE_SEED + 4, k, h, w) for k, (h, w) in enumerate(sizes)]
-    b = Batch(ims)
+    b = Batch(ims, align)
     recs, sse, _ = _fused(b, A().BACKEND_MFMA, A().Q_ZONAL, 8)
     for i, (got, im) in enumerate(zip(recs, ims)):
         want, s, _ = codec.compress_kept(im, codec.mask_zonal(8))
