@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   // of each image.  No atomics: tasks of one image run on many wavefronts at
   // once, and contended atomics would serialise them.
   static_assert(kTaskStrips <= 16, "per-task SSE must fit 32 bits");
-  unsigned lane_sse = 0;
+  unsigned lane_sse = 0, sum_aa = 0, sum_rr = 0, sum_ar = 0;
   int64_t tcur = t0;  // index of the current task
   for (;;) {
     // the strip after this one
@@ -339,17 +339,24 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
       } else {
         __builtin_amdgcn_s_waitcnt(0x0F70);
       }
+      // sum (a - r)^2 = sum a^2 + sum r^2 - 2 sum a r, each accumulated in
+      // the dot product's own addend
 #pragma unroll
-      for (int b = 0; b < kStripBlocks; ++b) lane_sse += sse4(x[b], out[b]);
+      for (int b = 0; b < kStripBlocks; ++b) {
+        sum_aa = __builtin_amdgcn_udot4(x[b], x[b], sum_aa, false);
+        sum_rr = __builtin_amdgcn_udot4(out[b], out[b], sum_rr, false);
+        sum_ar = __builtin_amdgcn_udot4(x[b], out[b], sum_ar, false);
+      }
     } else {
       prefetch();
       edge_strip<ZIGZAG, COLLAPSE, OUT>(d, sy, sxi, in, outp, k, keepz, g, q, lane_sse);
       __builtin_amdgcn_s_waitcnt(0x0F70);
     }
     if (task_end) {
-      const unsigned task_sum = wave_sum_u32(lane_sse);
+      // modular arithmetic: the true lane total is below 2^32
+      const unsigned task_sum = wave_sum_u32(lane_sse + sum_aa + sum_rr - 2u * sum_ar);
       if (lane == 0) P.task_sse[tcur] = task_sum;
-      lane_sse = 0;
+      lane_sse = sum_aa = sum_rr = sum_ar = 0;
       tcur = t0 + kk * W;
     }
     if (!more) break;

@@ -127,6 +127,12 @@ __device__ __forceinline__ f4 stage4(f4 u, const MfmaConsts& k) {
   const unsigned A0 = h2bits(u[0], u[1]), A1 = h2bits(u[2], u[3]);
   const unsigned B0 = h2bits(__builtin_amdgcn_fractf(u[0]), __builtin_amdgcn_fractf(u[1]));
   const unsigned B1 = h2bits(__builtin_amdgcn_fractf(u[2]), __builtin_amdgcn_fractf(u[3]));
+  // Two chained products, integer digit first.  One K = 32 product would
+  // let the hardware add the integer terms (|sum| up to 16 * 6 * 2048) and
+  // the 2^-11 terms in any order, and such partial sums need 29 significand
+  // bits; chained, every partial sum stays an integer below 2^24 or a
+  // multiple of 2^-11 below 2^12.  (Stage 3's K = 32 product is exact: all
+  // its terms are multiples of 2^-11 and their magnitudes sum below 2^12.)
   const f4 sa = mma16(k.w4, make_uint2(A0, A1), k.c4);
   return mma16(k.w4, make_uint2(B0, B1), sa);
 }
