@@ -209,6 +209,17 @@ def bench_luma(args, A, torch):
         f()
         t = _events_ms(f, max(3, args.steps // 2), stream)
         v["forward_mfma_u8_to_i32_gbs"] = round(5 * npx / (t * 1e-3) / 1e9, 1)
+        p5 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32, backend=A.BACKEND_MFMA,
+                    flags=A.FLAG_MFMA_INT8)
+        f = lambda: p5.forward(dev, coef32)
+        f()
+        t = _events_ms(f, max(3, args.steps // 2), stream)
+        v["forward_mfma_int8_u8_to_i32_gbs"] = round(5 * npx / (t * 1e-3) / 1e9, 1)
+        p6 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32, backend=A.BACKEND_VALU)
+        f = lambda: p6.forward(dev, coef32)
+        f()
+        t = _events_ms(f, max(3, args.steps // 2), stream)
+        v["forward_valu_u8_to_i32_gbs"] = round(5 * npx / (t * 1e-3) / 1e9, 1)
         res["variants"] = v
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = _cpu_baseline(frames, args.r, min(args.cpu_frames, n))

@@ -95,11 +95,15 @@ enum {
   ADCT16_FLAG_AUTOTUNE = 1,      /* time the candidate launch shapes (and, with
                                     ADCT16_BACKEND_AUTO, both backends) of the fused call at
                                     plan creation on scratch buffers (allocates) */
-  ADCT16_FLAG_EXPLICIT_COEF = 2  /* matrix-core fused call: form the coefficients Z of every
+  ADCT16_FLAG_EXPLICIT_COEF = 2, /* matrix-core fused call: form the coefficients Z of every
                                     block explicitly even for separable masks (by default the
                                     forward column pass, the zonal retention and the inverse
                                     column pass are applied as one exact contraction with
                                     G = T^T diag(w m) T; results are identical) */
+  ADCT16_FLAG_MFMA_INT8 = 4      /* adct16_forward with the MFMA backend: int8 products with
+                                    int32 accumulation (the pixels centred to int8, the
+                                    column pass on base-64 hi/lo digit planes of the row-pass
+                                    result) instead of FP16 products; results are identical */
 };
 
 /*

@@ -26,6 +26,7 @@ Q_NONE, Q_ZONAL, Q_ZIGZAG, Q_UNIFORM = 0, 1, 2, 3
 BACKEND_AUTO, BACKEND_VALU, BACKEND_MFMA = 0, 1, 2
 FLAG_AUTOTUNE = 1
 FLAG_EXPLICIT_COEF = 2
+FLAG_MFMA_INT8 = 4
 # adct16_matrix
 MATRIX_APPROX, MATRIX_T, MATRIX_WHT, MATRIX_DCT = 0, 1, 2, 3
 

@@ -102,6 +102,7 @@ hipError_t launch_measure(int in_kind, int out_kind, const Params& P, int grid, 
 hipError_t launch_1d(bool inverse, const int32_t* x, int32_t* y, int64_t n, hipStream_t s);
 
 hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStream_t s);
+hipError_t launch_mfma_forward_i8(int coef_kind, const Params& P, int grid, hipStream_t s);
 hipError_t launch_mfma_fused(bool zigzag, bool collapse, int out_kind, bool nt, const Params& P, int grid,
                              hipStream_t s);
 hipError_t launch_dct_mfma(int in_kind, int precision, const Params& P, float* y, int grid,

@@ -488,7 +488,8 @@ adct16_status adct16_forward(adct16_plan p, const void* d_in, void* d_coef, void
   P.coef = d_coef;
   hipError_t e;
   if (p->backend == ADCT16_BACKEND_MFMA && p->coef_kind != CF_F32)
-    e = launch_mfma_forward(p->coef_kind, P, p->grid, (hipStream_t)stream);
+    e = (p->d.flags & ADCT16_FLAG_MFMA_INT8) ? launch_mfma_forward_i8(p->coef_kind, P, p->grid, (hipStream_t)stream)
+                                             : launch_mfma_forward(p->coef_kind, P, p->grid, (hipStream_t)stream);
   else
     e = launch_valu_forward(p->in_kind, p->coef_kind, P, p->grid, (hipStream_t)stream);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "forward kernel");

@@ -412,6 +412,94 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P) {
 }
 
 // ---------------------------------------------------------------------------
+// Forward transform as int8 products with int32 accumulation (exact: every
+// operand is a small integer and int32 sums do not round).
+//
+//   row pass     P = Xc T^T, Xc = X - 128 in int8 (the pixel byte with its
+//                top bit flipped); K = 16 of the instruction's 32 slots
+//                carry data, the rest are zero.  |P| <= 2048.
+//   column pass  Z^T = P^T T^T with P split into signed base-64 digits,
+//                P = 64 hi + lo, lo = P & 63 in [0, 63], hi = P >> 6 in
+//                [-32, 31]; each lane packs the digits of the four P values
+//                it holds (rows 4g..4g+3 of column q) into its 8 K slots, and
+//                the constant operand carries T and 64 T in the same slots,
+//                so one instruction forms T P.  Stage 2 runs transposed:
+//                lane 16g + q ends with Z[q][4g..4g+3].
+//   DC           Z = Zc + 32768 at (0, 0) for int32 output (accumulator
+//                start); the centred int16 form is Zc itself.
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ i4v mma_i8(uint2 a, uint2 b, i4v c) {
+  const long av = (long)(((uint64_t)a.y << 32) | a.x), bv = (long)(((uint64_t)b.y << 32) | b.x);
+  return __builtin_amdgcn_mfma_i32_16x16x32_i8(av, bv, c, 0, 0, 0);
+}
+
+// Bytes 0 of four int32 values, in order, as one dword.
+__device__ __forceinline__ unsigned pack_low_bytes(int a, int b, int c, int d) {
+  const unsigned ab = __builtin_amdgcn_perm((unsigned)b, (unsigned)a, 0x0c0c0400u);
+  const unsigned cd = __builtin_amdgcn_perm((unsigned)d, (unsigned)c, 0x0c0c0400u);
+  return __builtin_amdgcn_perm(cd, ab, 0x05040100u);
+}
+
+__device__ __forceinline__ unsigned t_bytes(int row, int c0) {
+  unsigned r = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r |= (unsigned)(uint8_t)kT[row][c0 + j] << (8 * j);
+  return r;
+}
+
+template <int CF>
+__global__ __launch_bounds__(kGroupThreads) void k_mfma_forward_i8(Params P) {
+  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
+  // stage-1 B: T[q][8g..8g+7] for g < 2 (K = image column), zero otherwise
+  const uint2 b1 = g < 2 ? make_uint2(t_bytes(q, 8 * g), t_bytes(q, 8 * g + 4)) : make_uint2(0u, 0u);
+  // stage-2 B: column u = q; slots j < 4: T[q][4g + j], slots j >= 4: 64 T[q][4g + j - 4]
+  unsigned t64 = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) t64 |= (unsigned)(uint8_t)(64 * kT[q][4 * g + j]) << (8 * j);
+  const uint2 b2 = make_uint2(t_bytes(q, 4 * g), t64);
+  const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
+  StripCursor c;
+  if (!cursor_init(c, P)) return;
+  do {
+    const int y = min(c.sy * 16 + q, c.d.h - 1);
+    const int b0 = c.sxi * kStripBlocks;
+    const int nb = min(kStripBlocks, c.d.bx - b0);
+    const int64_t rowblk = c.d.block_begin + (int64_t)c.sy * c.d.bx + b0;
+    uint2 x[kStripBlocks];
+#pragma unroll
+    for (int b = 0; b < kStripBlocks; ++b) {
+      x[b] = make_uint2(0u, 0u);
+      if (g < 2 && b < nb) {
+        const int x0 = (b0 + b) * 16 + 8 * g;
+        x[b] = make_uint2(load_dword_u8(in, c.d, y, x0) ^ 0x80808080u, load_dword_u8(in, c.d, y, x0 + 4) ^ 0x80808080u);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kStripBlocks; ++b) {
+      if (b < nb) {
+        const i4v zero = {0, 0, 0, 0};
+        const i4v p = mma_i8(x[b], b1, zero);  // P[4g+v][q]
+        const uint2 digits = make_uint2(pack_low_bytes(p[0], p[1], p[2], p[3]) & 0x3f3f3f3fu,
+                                        pack_low_bytes(p[0] >> 6, p[1] >> 6, p[2] >> 6, p[3] >> 6));
+        i4v init = {0, 0, 0, 0};
+        if constexpr (CF == CF_I32)
+          if (q == 0 && g == 0) init[0] = 32768;
+        const i4v z = mma_i8(digits, b2, init);  // Z[q][4g+v]
+        const int64_t base = (rowblk + b) * 256 + q * 16 + 4 * g;
+        if constexpr (CF == CF_I32) {
+          *reinterpret_cast<int4*>(reinterpret_cast<int*>(P.coef) + base) = make_int4(z[0], z[1], z[2], z[3]);
+        } else {
+          const unsigned lo = ((unsigned)z[0] & 0xffffu) | ((unsigned)z[1] << 16);
+          const unsigned hi = ((unsigned)z[2] & 0xffffu) | ((unsigned)z[3] << 16);
+          *reinterpret_cast<uint2*>(reinterpret_cast<int16_t*>(P.coef) + base) = make_uint2(lo, hi);
+        }
+      }
+    }
+  } while (cursor_next(c, P), c.s < c.s_end);
+}
+
+// ---------------------------------------------------------------------------
 // Exact DCT-II comparison transform, Y = C X C^T, operands rounded to BF16
 // or F16, FP32 accumulation.  Stage 2 runs transposed for row-wise stores.
 __device__ __forceinline__ float dct_c(int k, int m) {
@@ -480,6 +568,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_dct(Params P, float* Y) {
     hipLaunchKernelGGL((kernel), dim3(grid), dim3(kGroupThreads), 0, (s), __VA_ARGS__); \
     return hipGetLastError();                                                          \
   } while (0)
+
+hipError_t launch_mfma_forward_i8(int coef_kind, const Params& P, int grid, hipStream_t s) {
+  if (coef_kind == CF_I32) ADCT16_MLAUNCH((k_mfma_forward_i8<CF_I32>), grid, s, P);
+  if (coef_kind == CF_I16C) ADCT16_MLAUNCH((k_mfma_forward_i8<CF_I16C>), grid, s, P);
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStream_t s) {
   if (coef_kind == CF_I32) ADCT16_MLAUNCH((k_mfma_forward<CF_I32>), grid, s, P);

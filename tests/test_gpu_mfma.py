@@ -45,10 +45,14 @@ def batch_worst():
     return Batch([img])
 
 
+@pytest.mark.parametrize("int8", [False, True])
 @pytest.mark.parametrize("cd", ["i32", "i16"])
-def test_mfma_forward_bit_exact(batch_u8, cd):
+def test_mfma_forward_bit_exact(batch_u8, cd, int8):
+    # int8: int8 products with int32 accumulation on hi/lo digit planes;
+    # otherwise exact FP16 products
     T = torch()
-    plan = batch_u8.plan(coef_dtype=A().I32 if cd == "i32" else A().I16, backend=A().BACKEND_MFMA)
+    plan = batch_u8.plan(coef_dtype=A().I32 if cd == "i32" else A().I16, backend=A().BACKEND_MFMA,
+                         flags=A().FLAG_MFMA_INT8 if int8 else 0)
     coef = batch_u8.coef_tensor(T.int32 if cd == "i32" else T.int16)
     plan.forward(batch_u8.dev, coef)
     T.cuda.synchronize()
@@ -97,6 +101,18 @@ def test_mfma_equals_adder_kernel_on_extremes(batch_worst, qmode, r, explicit):
     keep = {0: codec.mask_none(), 1: codec.mask_zonal(r), 2: codec.mask_zigzag(r)}[qmode]
     want, s, _ = codec.compress_kept(batch_worst.images[0], keep)
     assert np.array_equal(a[0][0], want) and a[1][0] == s
+
+
+@pytest.mark.parametrize("int8", [False, True])
+def test_mfma_forward_extremes(batch_worst, int8):
+    # sign patterns of the rows of T reach |P| = 2048 and the extreme Z
+    T = torch()
+    plan = batch_worst.plan(coef_dtype=A().I32, backend=A().BACKEND_MFMA, flags=A().FLAG_MFMA_INT8 if int8 else 0)
+    coef = batch_worst.coef_tensor(T.int32)
+    plan.forward(batch_worst.dev, coef)
+    T.cuda.synchronize()
+    got = batch_worst.split_coef(coef)[0]
+    assert np.array_equal(got.astype(np.int64), codec.forward_image(batch_worst.images[0]))
 
 
 @pytest.mark.parametrize("align", [16, 128])
