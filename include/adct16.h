@@ -79,7 +79,10 @@ typedef enum adct16_qmode {
   ADCT16_Q_NONE = 0,     /* keep every coefficient (lossless round trip) */
   ADCT16_Q_ZONAL = 1,    /* keep the top-left r x r coefficients, 1 <= r <= 16 */
   ADCT16_Q_ZIGZAG = 2,   /* keep the first r coefficients of the zig-zag scan, 1 <= r <= 256 (Section 4) */
-  ADCT16_Q_UNIFORM = 3   /* uniform step q >= 1 with S folded into one float32 multiplier */
+  ADCT16_Q_UNIFORM = 3,  /* uniform step q >= 1 with S folded into one float32 multiplier */
+  ADCT16_Q_DEADZONE = 4  /* deadzone quantiser with a QP-scaled step, q = QP in [0, 63]; a
+                            stand-in for the video coder's quantiser of Section 5.3 (see
+                            qcoef_dtype below) */
 } adct16_qmode;
 
 typedef enum adct16_backend {
@@ -100,10 +103,12 @@ enum {
                                     forward column pass, the zonal retention and the inverse
                                     column pass are applied as one exact contraction with
                                     G = T^T diag(w m) T; results are identical) */
-  ADCT16_FLAG_MFMA_INT8 = 4      /* adct16_forward with the MFMA backend: int8 products with
+  ADCT16_FLAG_MFMA_INT8 = 4,     /* adct16_forward with the MFMA backend: int8 products with
                                     int32 accumulation (the pixels centred to int8, the
                                     column pass on base-64 hi/lo digit planes of the row-pass
                                     result) instead of FP16 products; results are identical */
+  ADCT16_FLAG_DEADZONE_INTER = 8 /* deadzone quantiser rounding offset f = 1/6 (inter-coded
+                                    residuals) instead of 1/3 (intra) */
 };
 
 /*
@@ -126,7 +131,15 @@ enum {
  *                           unchanged, the rest zero;
  *               uniform:    levels L_uv = round_half_even(fl32(fl32(Z_uv) *
  *                           M_uv)), M_uv = fl32(1/(sqrt(n_u n_v) q)), stored
- *                           as ADCT16_I16 (saturated) or ADCT16_I32.
+ *                           as ADCT16_I16 (saturated) or ADCT16_I32;
+ *               deadzone:   L_uv = sign(Z_uv) floor(fl32(fl32(fl32(|Z_uv|) M_uv)
+ *                           + f)) with separately rounded multiply and add,
+ *                           M_uv = fl32(Q[QP mod 6] / (sqrt(n_u n_v)
+ *                           2^(14 + QP/6))), Q = {26214, 23302, 20560, 18396,
+ *                           16384, 14564}, f = fl32(1/3) (or 1/6, flag
+ *                           ADCT16_FLAG_DEADZONE_INTER); reconstruction
+ *                           B' = D[QP mod 6] 2^(QP/6) / 64 L, D = {40, 45, 51,
+ *                           57, 64, 72}, then as for the uniform quantiser.
  * out_dtype   reconstruction: ADCT16_U8 (rounded half up, clamped 0..255),
  *             ADCT16_I16 (rounded half up, saturated) or ADCT16_F32 (the
  *             unrounded A').  U8 needs U8 input.
@@ -182,6 +195,14 @@ adct16_status adct16_quantise(adct16_plan plan, const void *d_coef, void *d_qcoe
  * exactly in int32.  Uniform: d_qcoef holds levels L; B' = q L and A' is
  * evaluated in float64. */
 adct16_status adct16_inverse(adct16_plan plan, const void *d_qcoef, void *d_out, void *stream);
+
+/* Rate proxy for the quantisation levels in d_qcoef (qcoef_dtype, block-
+ * major, as written by adct16_quantise or the fused call): per image, the
+ * total length in bits of the signed Exp-Golomb codes se(v) of its levels
+ * (v > 0 -> code number 2v - 1, v <= 0 -> -2v; code number k takes
+ * 2 floor(log2(k + 1)) + 1 bits).  d_bits: n_images int64 (overwritten, 8-
+ * byte aligned).  ADCT16_E_STATE for plans whose qmode produces no levels. */
+adct16_status adct16_rate(adct16_plan plan, const void *d_qcoef, int64_t *d_bits, void *stream);
 
 /* Section 4, quality: per-image SSE over the true pixels and
  * PSNR = 10 log10(255^2 h w / SSE) (+inf when SSE = 0).  d_a is in_dtype,

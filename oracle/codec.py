@@ -113,6 +113,74 @@ def dequantise_uniform(levels: np.ndarray, q: int) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+# Deadzone quantiser with a QP-scaled step.  The paper embeds the transform in
+# a video coder (Section 5.3) without giving that coder's quantiser; this is
+# the usual form of one: six steps per doubling given by integer scales,
+# S folded into one float32 multiplier per coefficient, a rounding offset f
+# below 1/2 (the dead zone), and a matching reconstruction step.
+
+QUANT_SCALE = (26214, 23302, 20560, 18396, 16384, 14564)
+DEQUANT_SCALE = (40, 45, 51, 57, 64, 72)
+
+
+def deadzone_multipliers(qp: int) -> np.ndarray:
+    """M_uv = fl32(Q[qp mod 6] / (sqrt(n_u n_v) 2^(14 + qp // 6)))."""
+    n = tf.row_norms()
+    m = np.empty((BLK, BLK), dtype=np.float32)
+    for u in range(BLK):
+        for v in range(BLK):
+            m[u, v] = np.float32(math.ldexp(QUANT_SCALE[qp % 6] / math.sqrt(float(n[u] * n[v])), -(14 + qp // 6)))
+    return m
+
+
+def deadzone_offset(inter: bool = False) -> np.float32:
+    return np.float32(1.0 / 6.0) if inter else np.float32(1.0 / 3.0)
+
+
+def quantise_deadzone(z: np.ndarray, qp: int, inter: bool = False) -> np.ndarray:
+    """L = sign(Z) floor(fl32(fl32(fl32(|Z|) M) + f)), float32 multiply and
+    add each rounded on its own."""
+    z = np.asarray(z)
+    a = (np.abs(z).astype(np.float32) * deadzone_multipliers(qp)).astype(np.float32)
+    b = (a + deadzone_offset(inter)).astype(np.float32)
+    return (np.sign(z) * np.floor(b)).astype(np.int64)
+
+
+def deadzone_step(qp: int) -> float:
+    """Reconstruction step D[qp mod 6] 2^(qp // 6) / 64 (exact in float64)."""
+    return math.ldexp(float(DEQUANT_SCALE[qp % 6]), qp // 6 - 6)
+
+
+def reconstruct_deadzone(levels: np.ndarray, qp: int, h: int, w: int, out_dtype=np.uint8) -> np.ndarray:
+    a = tf.inverse_real(deadzone_step(qp) * np.asarray(levels, dtype=np.float64))
+    rec = round_half_up_u8(a) if out_dtype == np.uint8 else round_half_up_i16(a)
+    return blocks_to_image(rec, h, w)
+
+
+def compress_deadzone(img: np.ndarray, qp: int, inter: bool = False):
+    """Forward, deadzone quantiser, inverse, measure: (levels, recon, sse, psnr)."""
+    h, w = img.shape
+    lv = quantise_deadzone(forward_image(img), qp, inter)
+    rec = reconstruct_deadzone(lv, qp, h, w, np.uint8 if img.dtype == np.uint8 else np.int16)
+    s = sse(img, rec)
+    return lv, rec, s, psnr_from_sse(s, h * w)
+
+
+def se_code_length(v: int) -> int:
+    """Bits of the signed Exp-Golomb code se(v): code number k = 2v - 1 for
+    v > 0 and -2v otherwise, written as k + 1 in binary preceded by as many
+    zeros as it has bits after the leading one."""
+    k = 2 * v - 1 if v > 0 else -2 * v
+    return 2 * ((k + 1).bit_length() - 1) + 1
+
+
+def rate_bits(levels: np.ndarray) -> int:
+    """Rate proxy: total se(v) length of the levels."""
+    vals, counts = np.unique(np.asarray(levels, dtype=np.int64), return_counts=True)
+    return int(sum(se_code_length(int(v)) * int(c) for v, c in zip(vals, counts)))
+
+
+# ----------------------------------------------------------------------------
 # Reconstruction rounding.
 
 def round_half_up_u8(a: np.ndarray) -> np.ndarray:

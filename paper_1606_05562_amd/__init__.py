@@ -21,12 +21,13 @@ OK, E_NULL, E_SHAPE, E_DTYPE, E_MODE, E_ALIGN, E_NOMEM, E_DEVICE, E_LAUNCH, E_ST
 # adct16_dtype
 U8, I16, I32, F32, BF16, F16 = 1, 2, 3, 4, 5, 6
 # adct16_qmode
-Q_NONE, Q_ZONAL, Q_ZIGZAG, Q_UNIFORM = 0, 1, 2, 3
+Q_NONE, Q_ZONAL, Q_ZIGZAG, Q_UNIFORM, Q_DEADZONE = 0, 1, 2, 3, 4
 # adct16_backend
 BACKEND_AUTO, BACKEND_VALU, BACKEND_MFMA = 0, 1, 2
 FLAG_AUTOTUNE = 1
 FLAG_EXPLICIT_COEF = 2
 FLAG_MFMA_INT8 = 4
+FLAG_DEADZONE_INTER = 8
 # adct16_matrix
 MATRIX_APPROX, MATRIX_T, MATRIX_WHT, MATRIX_DCT = 0, 1, 2, 3
 
@@ -34,7 +35,7 @@ _TORCH_DTYPE_CODES = {"torch.uint8": U8, "torch.int16": I16, "torch.int32": I32,
 
 EXPORTED = [
     "adct16_plan_create", "adct16_plan_destroy", "adct16_plan_num_blocks", "adct16_plan_info",
-    "adct16_forward", "adct16_quantise", "adct16_inverse", "adct16_measure",
+    "adct16_forward", "adct16_quantise", "adct16_inverse", "adct16_measure", "adct16_rate",
     "adct16_compress_and_measure", "adct16_dct_forward", "adct16_forward_1d", "adct16_inverse_1d",
     "adct16_graph_create", "adct16_graph_launch", "adct16_graph_destroy",
     "adct16_transform_matrix", "adct16_transform_measures",
@@ -82,6 +83,7 @@ def _load():
         "adct16_quantise": [vp, vp, vp, vp],
         "adct16_inverse": [vp, vp, vp, vp],
         "adct16_measure": [vp, vp, vp, vp, vp, vp],
+        "adct16_rate": [vp, vp, vp, vp],
         "adct16_compress_and_measure": [vp, vp, vp, vp, vp, vp, vp],
         "adct16_dct_forward": [vp, vp, vp, i32, vp],
         "adct16_forward_1d": [vp, vp, i64, vp],
@@ -153,7 +155,7 @@ class Plan:
         self._p = (ctypes.c_int32 * max(n, 1))(*pitches)
         self._o = (ctypes.c_int64 * max(n, 1))(*offsets)
         if qcoef_dtype is None:
-            qcoef_dtype = I16 if qmode == Q_UNIFORM else (coef_dtype if coef_dtype in (I32, I16) else I32)
+            qcoef_dtype = I16 if qmode in (Q_UNIFORM, Q_DEADZONE) else (coef_dtype if coef_dtype in (I32, I16) else I32)
         if out_dtype is None:
             out_dtype = in_dtype
         d = _Desc(n, self._h, self._w, self._p, self._o, in_dtype, coef_dtype, qcoef_dtype, out_dtype,
@@ -198,6 +200,10 @@ class Plan:
 
     def measure(self, a, b, sse, psnr=None, stream=None):
         _check(_lib.adct16_measure(self._plan, _ptr(a), _ptr(b), _ptr(sse), _ptr(psnr), _stream(stream)))
+
+    def rate(self, qcoef, bits, stream=None):
+        """Per-image signed Exp-Golomb code length (bits, int64) of the levels."""
+        _check(_lib.adct16_rate(self._plan, _ptr(qcoef), _ptr(bits), _stream(stream)))
 
     def compress_and_measure(self, inp, out=None, qcoef=None, sse=None, psnr=None, stream=None):
         _check(_lib.adct16_compress_and_measure(self._plan, _ptr(inp), _ptr(out), _ptr(qcoef), _ptr(sse),

@@ -60,13 +60,14 @@ struct Tables {
   float yscale[256];   // K_uv = fl32(1 / sqrt(n_u n_v))
   double deqc[16];     // q s_v, per horizontal frequency v
   int32_t rsep;        // retained r x r square for separable masks (16 = all; zig-zag masks use wkeep)
-  int32_t pad[3];
+  float qoff;          // deadzone quantiser rounding offset f
+  int32_t pad[2];
 };
 
 enum InKind { IN_U8 = 0, IN_I16 = 1 };
 enum CoefKind { CF_I32 = 0, CF_I16C = 1, CF_F32 = 2, CF_L16 = 3, CF_L32 = 4, CF_NONE = 5 };
 enum OutKind { OUT_NONE = 0, OUT_U8 = 1, OUT_I16 = 2, OUT_F32 = 3 };
-enum ModeKind { MODE_MASK = 0, MODE_UNIFORM = 1 };
+enum ModeKind { MODE_MASK = 0, MODE_UNIFORM = 1, MODE_DEADZONE = 2 };
 
 struct Params {
   const ImageDesc* images;
@@ -100,6 +101,7 @@ hipError_t launch_valu_inverse(int coef_kind, int mode, int out_kind, const Para
 hipError_t launch_quantise(int coef_kind, int mode, int qout_kind, const Params& P, hipStream_t s);
 hipError_t launch_measure(int in_kind, int out_kind, const Params& P, int grid, hipStream_t s);
 hipError_t launch_1d(bool inverse, const int32_t* x, int32_t* y, int64_t n, hipStream_t s);
+hipError_t launch_rate(int level_kind, const Params& P, unsigned long long* bits, hipStream_t s);
 
 hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStream_t s);
 hipError_t launch_mfma_forward_i8(int coef_kind, const Params& P, int grid, hipStream_t s);

@@ -39,6 +39,11 @@ adct16_status hip_fail(hipError_t e, const char* what) {
 
 // Section 2: n_i = (T T^T)_ii, the squared row norms of T; S = diag(1/sqrt(n)).
 constexpr int kNorm[16] = {16, 16, 12, 8, 8, 16, 12, 12, 16, 12, 12, 8, 8, 12, 12, 12};
+// Deadzone quantiser scales per QP mod 6 (the six steps per doubling of the
+// video-coding standards; quant_scale x dequant_scale ~ 2^20).
+constexpr int kQuantScale[6] = {26214, 23302, 20560, 18396, 16384, 14564};
+constexpr int kDequantScale[6] = {40, 45, 51, 57, 64, 72};
+constexpr int kMaxQp = 63;
 
 // Section 4: 16x16 zig-zag scan, anti-diagonal by anti-diagonal starting
 // (0,0), (0,1), (1,0), ...; rank[u*16+v] = scan position.
@@ -309,12 +314,14 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
     return fail(ADCT16_E_DTYPE, "coef_dtype must be I32, F32 or (U8 input) I16");
   if (!(d->out_dtype == ADCT16_I16 || d->out_dtype == ADCT16_F32 || (in_u8 && d->out_dtype == ADCT16_U8)))
     return fail(ADCT16_E_DTYPE, "out_dtype must be I16, F32 or (U8 input) U8");
-  if (d->qmode < ADCT16_Q_NONE || d->qmode > ADCT16_Q_UNIFORM) return fail(ADCT16_E_MODE, "qmode %d", d->qmode);
-  const bool uniform = d->qmode == ADCT16_Q_UNIFORM;
-  if (uniform) {
+  if (d->qmode < ADCT16_Q_NONE || d->qmode > ADCT16_Q_DEADZONE) return fail(ADCT16_E_MODE, "qmode %d", d->qmode);
+  const bool uniform = d->qmode == ADCT16_Q_UNIFORM, deadzone = d->qmode == ADCT16_Q_DEADZONE;
+  const bool levels = uniform || deadzone;
+  if (levels) {
     if (!(d->qcoef_dtype == ADCT16_I16 || d->qcoef_dtype == ADCT16_I32))
-      return fail(ADCT16_E_DTYPE, "uniform levels must be I16 or I32");
-    if (d->q < 1 || d->q > 65535) return fail(ADCT16_E_MODE, "q = %d outside [1, 65535]", d->q);
+      return fail(ADCT16_E_DTYPE, "quantisation levels must be I16 or I32");
+    if (uniform && (d->q < 1 || d->q > 65535)) return fail(ADCT16_E_MODE, "q = %d outside [1, 65535]", d->q);
+    if (deadzone && (d->q < 0 || d->q > kMaxQp)) return fail(ADCT16_E_MODE, "QP = %d outside [0, %d]", d->q, kMaxQp);
   } else {
     if (!(d->qcoef_dtype == ADCT16_I32 || (in_u8 && d->qcoef_dtype == ADCT16_I16)))
       return fail(ADCT16_E_DTYPE, "retained coefficients must be I32 or (U8 input) I16");
@@ -367,10 +374,10 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   p->cu_count = prop.multiProcessorCount;
   p->in_kind = in_u8 ? IN_U8 : IN_I16;
   p->coef_kind = d->coef_dtype == ADCT16_I32 ? CF_I32 : d->coef_dtype == ADCT16_I16 ? CF_I16C : CF_F32;
-  if (uniform) p->qcoef_kind = d->qcoef_dtype == ADCT16_I16 ? CF_L16 : CF_L32;
+  if (levels) p->qcoef_kind = d->qcoef_dtype == ADCT16_I16 ? CF_L16 : CF_L32;
   else p->qcoef_kind = d->qcoef_dtype == ADCT16_I16 ? CF_I16C : CF_I32;
   p->out_kind = d->out_dtype == ADCT16_U8 ? OUT_U8 : d->out_dtype == ADCT16_I16 ? OUT_I16 : OUT_F32;
-  p->mode = uniform ? MODE_UNIFORM : MODE_MASK;
+  p->mode = uniform ? MODE_UNIFORM : deadzone ? MODE_DEADZONE : MODE_MASK;
   p->n_blocks = blocks;
   p->n_strips = strips;
   p->lines_aligned = true;
@@ -392,10 +399,17 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
       t.wall[u * 16 + v] = wuv;
       t.wkeep[u * 16 + v] = keep ? wuv : 0;
       t.yscale[u * 16 + v] = (float)(1.0 / std::sqrt((double)nn));
-      t.qmul[u * 16 + v] = uniform ? (float)(1.0 / (std::sqrt((double)nn) * (double)d->q)) : 0.0f;
+      if (uniform) t.qmul[u * 16 + v] = (float)(1.0 / (std::sqrt((double)nn) * (double)d->q));
+      // deadzone: M = quant_scale[QP mod 6] / (sqrt(n_u n_v) 2^(14 + QP / 6)); sqrt and
+      // the division are correctly rounded, the power of two is exact
+      if (deadzone)
+        t.qmul[u * 16 + v] = (float)(std::ldexp((double)kQuantScale[d->q % 6] / std::sqrt((double)nn), -(14 + d->q / 6)));
     }
-    t.deqc[u] = uniform ? (double)d->q / std::sqrt((double)kNorm[u]) : 0.0;
+    if (uniform) t.deqc[u] = (double)d->q / std::sqrt((double)kNorm[u]);
+    // deadzone reconstruction step: dequant_scale[QP mod 6] 2^(QP / 6) / 64 (exact)
+    if (deadzone) t.deqc[u] = std::ldexp((double)kDequantScale[d->q % 6], d->q / 6 - 6) / std::sqrt((double)kNorm[u]);
   }
+  t.qoff = (d->flags & ADCT16_FLAG_DEADZONE_INTER) ? (float)(1.0 / 6.0) : (float)(1.0 / 3.0);
   t.rsep = d->qmode == ADCT16_Q_ZONAL ? d->r : 16;
   std::vector<RowTask> rows;
   for (size_t i = 0; i < images.size(); ++i) {
@@ -516,8 +530,22 @@ adct16_status adct16_inverse(adct16_plan p, const void* d_qcoef, void* d_out, vo
   Params P = base_params(p);
   P.qcoef = const_cast<void*>(d_qcoef);
   P.out = d_out;
-  hipError_t e = launch_valu_inverse(p->qcoef_kind, p->mode, p->out_kind, P, p->grid, (hipStream_t)stream);
+  // the deadzone levels are reconstructed like uniform ones (step in the tables)
+  hipError_t e = launch_valu_inverse(p->qcoef_kind, p->mode == MODE_DEADZONE ? MODE_UNIFORM : p->mode, p->out_kind,
+                                     P, p->grid, (hipStream_t)stream);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "inverse kernel");
+}
+
+adct16_status adct16_rate(adct16_plan p, const void* d_qcoef, int64_t* d_bits, void* stream) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (p->mode == MODE_MASK) return fail(ADCT16_E_STATE, "the plan's qmode produces no levels");
+  if (!d_qcoef || !d_bits) return fail(ADCT16_E_NULL, "d_qcoef / d_bits is NULL");
+  if (!aligned16(d_qcoef) || (reinterpret_cast<uintptr_t>(d_bits) & 7))
+    return fail(ADCT16_E_ALIGN, "d_qcoef not 16-byte / d_bits not 8-byte aligned");
+  Params P = base_params(p);
+  P.qcoef = const_cast<void*>(d_qcoef);
+  hipError_t e = launch_rate(p->qcoef_kind, P, reinterpret_cast<unsigned long long*>(d_bits), (hipStream_t)stream);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "rate kernel");
 }
 
 adct16_status adct16_measure(adct16_plan p, const void* d_a, const void* d_b, int64_t* d_sse, double* d_psnr,

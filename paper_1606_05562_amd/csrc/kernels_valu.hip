@@ -337,6 +337,22 @@ __global__ __launch_bounds__(kGroupThreads) void k_forward(Params P) {
   } while (cursor_next(c, P), c.s < c.s_end);
 }
 
+// Quantisation level of one integer coefficient Z with its multiplier M
+// (S and the step folded in).  Uniform: round-half-even(fl32(fl32(Z) M)).
+// Deadzone: sign(Z) floor(fl32(fl32(fl32(|Z|) M) + f)); the separate
+// rounded multiply and add (no fused multiply-add) are part of the
+// definition.
+template <int MODE>
+__device__ __forceinline__ int level_of(int z, float m, float f) {
+  if constexpr (MODE == MODE_UNIFORM) {
+    return (int)__builtin_rintf((float)z * m);
+  } else {
+    const float a = __fmul_rn((float)abs(z), m);
+    const int l = (int)floorf(__fadd_rn(a, f));
+    return z < 0 ? -l : l;
+  }
+}
+
 // Retention / quantiser of the column-layout coefficients of one lane.
 // Mask modes multiply by W = w_u w_v keep(u, v) (the inverse weights); the
 // masked coefficients themselves are kept for an optional qcoef output.
@@ -369,8 +385,8 @@ __device__ __forceinline__ void quant_and_inverse(const Params& P, const LaneGeo
     int la[16], lb[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      la[u] = (int)__builtin_rintf((float)za[u] * Mq[u]);
-      lb[u] = (int)__builtin_rintf((float)zb[u] * Mq[u]);
+      la[u] = level_of<MODE>(za[u], Mq[u], P.tables->qoff);
+      lb[u] = level_of<MODE>(zb[u], Mq[u], P.tables->qoff);
     }
     if constexpr (QOUT != CF_NONE) {
       if (g.na > 0) store_col<QOUT>(P.qcoef, g.blka, x, la);
@@ -611,7 +627,7 @@ __global__ __launch_bounds__(256) void k_quantise(Params P) {
     } else {
       if constexpr (CFIN == CF_I16C) z[0] += (u == 0) ? 32768 : 0;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) r[v] = (int)__builtin_rintf((float)z[v] * P.tables->qmul[u * 16 + v]);
+      for (int v = 0; v < 16; ++v) r[v] = level_of<MODE>(z[v], P.tables->qmul[u * 16 + v], P.tables->qoff);
     }
     if constexpr (QOUT == CF_I32 || QOUT == CF_L32) {
       int4* d = reinterpret_cast<int4*>(reinterpret_cast<int*>(P.qcoef) + t * 16);
@@ -787,10 +803,14 @@ static hipError_t fused_in(int mode, int qout, int out_kind, const Params& P, in
     if (qout == CF_NONE) return fused_out<IN, MODE_MASK, CF_NONE>(out_kind, P, grid, s);
     if (qout == CF_I32) return fused_out<IN, MODE_MASK, CF_I32>(out_kind, P, grid, s);
     if (IN == IN_U8 && qout == CF_I16C) return fused_out<IN, MODE_MASK, CF_I16C>(out_kind, P, grid, s);
-  } else {
+  } else if (mode == MODE_UNIFORM) {
     if (qout == CF_NONE) return fused_out<IN, MODE_UNIFORM, CF_NONE>(out_kind, P, grid, s);
     if (qout == CF_L16) return fused_out<IN, MODE_UNIFORM, CF_L16>(out_kind, P, grid, s);
     if (qout == CF_L32) return fused_out<IN, MODE_UNIFORM, CF_L32>(out_kind, P, grid, s);
+  } else {
+    if (qout == CF_NONE) return fused_out<IN, MODE_DEADZONE, CF_NONE>(out_kind, P, grid, s);
+    if (qout == CF_L16) return fused_out<IN, MODE_DEADZONE, CF_L16>(out_kind, P, grid, s);
+    if (qout == CF_L32) return fused_out<IN, MODE_DEADZONE, CF_L32>(out_kind, P, grid, s);
   }
   return hipErrorInvalidValue;
 }
@@ -834,11 +854,16 @@ hipError_t launch_quantise(int coef_kind, int mode, int qout_kind, const Params&
   if (mode == MODE_MASK) {
     if (coef_kind == CF_I32 && qout_kind == CF_I32) ADCT16_QLAUNCH((k_quantise<CF_I32, MODE_MASK, CF_I32>));
     if (coef_kind == CF_I16C && qout_kind == CF_I16C) ADCT16_QLAUNCH((k_quantise<CF_I16C, MODE_MASK, CF_I16C>));
-  } else {
+  } else if (mode == MODE_UNIFORM) {
     if (coef_kind == CF_I32 && qout_kind == CF_L16) ADCT16_QLAUNCH((k_quantise<CF_I32, MODE_UNIFORM, CF_L16>));
     if (coef_kind == CF_I32 && qout_kind == CF_L32) ADCT16_QLAUNCH((k_quantise<CF_I32, MODE_UNIFORM, CF_L32>));
     if (coef_kind == CF_I16C && qout_kind == CF_L16) ADCT16_QLAUNCH((k_quantise<CF_I16C, MODE_UNIFORM, CF_L16>));
     if (coef_kind == CF_I16C && qout_kind == CF_L32) ADCT16_QLAUNCH((k_quantise<CF_I16C, MODE_UNIFORM, CF_L32>));
+  } else {
+    if (coef_kind == CF_I32 && qout_kind == CF_L16) ADCT16_QLAUNCH((k_quantise<CF_I32, MODE_DEADZONE, CF_L16>));
+    if (coef_kind == CF_I32 && qout_kind == CF_L32) ADCT16_QLAUNCH((k_quantise<CF_I32, MODE_DEADZONE, CF_L32>));
+    if (coef_kind == CF_I16C && qout_kind == CF_L16) ADCT16_QLAUNCH((k_quantise<CF_I16C, MODE_DEADZONE, CF_L16>));
+    if (coef_kind == CF_I16C && qout_kind == CF_L32) ADCT16_QLAUNCH((k_quantise<CF_I16C, MODE_DEADZONE, CF_L32>));
   }
 #undef ADCT16_QLAUNCH
   return hipErrorInvalidValue;
@@ -848,6 +873,66 @@ hipError_t launch_measure(int in_kind, int out_kind, const Params& P, int grid, 
   if (in_kind == IN_U8 && out_kind == OUT_U8) ADCT16_LAUNCH((k_measure<IN_U8>), grid, s, P);
   if (in_kind == IN_I16 && out_kind == OUT_I16) ADCT16_LAUNCH((k_measure<IN_I16>), grid, s, P);
   return hipErrorInvalidValue;
+}
+
+// Rate proxy: the length of the signed Exp-Golomb code se(v) of a level v
+// (v > 0 maps to code number 2v - 1, v <= 0 to -2v; code number k takes
+// 2 floor(log2(k + 1)) + 1 bits).
+__device__ __forceinline__ unsigned se_bits(int v) {
+  const unsigned k = v > 0 ? 2u * (unsigned)v - 1u : 2u * (unsigned)(-v);
+  return 2u * (31u - (unsigned)__builtin_clz(k + 1u)) + 1u;
+}
+
+// Per-image sum of se(v) lengths over the block-major levels: one wavefront
+// per strip of 8 blocks' worth of levels at a time, walking the image table.
+template <int LK>
+__global__ __launch_bounds__(256) void k_rate(Params P, unsigned long long* bits) {
+  const int lane = threadIdx.x & 63;
+  StripCursor c;
+  if (!cursor_init(c, P)) return;
+  unsigned long long acc = 0;
+  int img = c.img;
+  for (;;) {
+    const int b0 = c.sxi * kStripBlocks;
+    const int nb = min(kStripBlocks, c.d.bx - b0);
+    const int64_t blk = c.d.block_begin + (int64_t)c.sy * c.d.bx + b0;
+    // nb blocks x 256 levels; lane handles 32 consecutive levels per block pair
+    unsigned s = 0;
+    for (int b = 0; b < nb; ++b) {
+      const int64_t base = (blk + b) * 256 + lane * 4;
+      int v[4];
+      if constexpr (LK == CF_L32) {
+        const int4 q = *reinterpret_cast<const int4*>(reinterpret_cast<const int*>(P.qcoef) + base);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+      } else {
+        const uint2 q = *reinterpret_cast<const uint2*>(reinterpret_cast<const int16_t*>(P.qcoef) + base);
+        v[0] = (int)(short)(q.x & 0xffffu); v[1] = ((int)q.x) >> 16;
+        v[2] = (int)(short)(q.y & 0xffffu); v[3] = ((int)q.y) >> 16;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s += se_bits(v[k]);
+    }
+    acc += s;
+    const bool changed = cursor_next(c, P);
+    const bool done = c.s >= c.s_end;
+    if (changed || done) {
+      const unsigned long long t = wave_sum_u64(acc);
+      if (lane == 0) atomicAdd(bits + img, t);
+      acc = 0;
+      img = c.img;
+    }
+    if (done) break;
+  }
+}
+
+hipError_t launch_rate(int level_kind, const Params& P, unsigned long long* bits, hipStream_t s) {
+  hipError_t e = launch_zero_u64(bits, P.n_images, s);
+  if (e != hipSuccess) return e;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((P.n_strips + kWavesPerGroup - 1) / kWavesPerGroup, 2048));
+  if (level_kind == CF_L32) hipLaunchKernelGGL((k_rate<CF_L32>), dim3(grid), dim3(kGroupThreads), 0, s, P, bits);
+  else if (level_kind == CF_L16) hipLaunchKernelGGL((k_rate<CF_L16>), dim3(grid), dim3(kGroupThreads), 0, s, P, bits);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_1d(bool inverse, const int32_t* x, int32_t* y, int64_t n, hipStream_t s) {

@@ -75,6 +75,9 @@ def test_validation_errors():
     assert _plan_status(qmode=A.Q_ZIGZAG, r=257) == A.E_MODE
     assert _plan_status(qmode=A.Q_UNIFORM, q=0) == A.E_MODE
     assert _plan_status(qmode=A.Q_UNIFORM, qcoef_dtype=A.F32) == A.E_DTYPE
+    assert _plan_status(qmode=A.Q_DEADZONE, q=-1) == A.E_MODE
+    assert _plan_status(qmode=A.Q_DEADZONE, q=64) == A.E_MODE
+    assert _plan_status(qmode=A.Q_DEADZONE, q=30, qcoef_dtype=A.U8) == A.E_DTYPE
     assert _plan_status(qmode=7) == A.E_MODE
     assert _plan_status(backend=5) == A.E_MODE
 
@@ -97,6 +100,7 @@ def test_null_arguments():
     assert lib.adct16_compress_and_measure(None, None, None, None, None, None, None) == A.E_NULL
     assert lib.adct16_forward_1d(None, None, 4, None) == A.E_NULL
     assert lib.adct16_graph_launch(None, None) == A.E_NULL
+    assert lib.adct16_rate(None, None, None, None) == A.E_NULL
     assert lib.adct16_plan_destroy(None) == A.E_NULL
     assert b"NULL" in lib.adct16_last_error_string()
 

@@ -449,3 +449,64 @@ def test_full_size_luma_batch_sampled():
     plan.measure(dev, out, m)
     T.cuda.synchronize()
     assert T.equal(m, sse)
+
+
+# ----------------------------------------------------------------------------
+# Deadzone quantiser (QP-scaled step) and the rate proxy
+
+@pytest.mark.parametrize("qp,inter", [(4, False), (22, False), (27, True), (37, False), (51, True)])
+def test_fused_deadzone_residual(batch_i16, qp, inter):
+    T = torch()
+    plan = batch_i16.plan(coef_dtype=A().I32, qmode=A().Q_DEADZONE, q=qp, qcoef_dtype=A().I16, out_dtype=A().I16,
+                          flags=A().FLAG_DEADZONE_INTER if inter else 0)
+    out = batch_i16.empty_like_images(np.int16)
+    lv = batch_i16.coef_tensor(T.int16)
+    sse = T.zeros(len(batch_i16.images), dtype=T.int64, device="cuda")
+    psnr = T.zeros(len(batch_i16.images), dtype=T.float64, device="cuda")
+    bits = T.zeros(len(batch_i16.images), dtype=T.int64, device="cuda")
+    plan.compress_and_measure(batch_i16.dev, out, lv, sse, psnr)
+    plan.rate(lv, bits)
+    T.cuda.synchronize()
+    for i, (got, lvl, im) in enumerate(zip(batch_i16.unpack(out), batch_i16.split_coef(lv), batch_i16.images)):
+        h, w = im.shape
+        want_lv = codec.quantise_deadzone(codec.forward_image(im), qp, inter)
+        assert np.array_equal(lvl.astype(np.int64), want_lv)
+        assert int(bits[i]) == codec.rate_bits(want_lv)
+        real = tf.inverse_real(codec.deadzone_step(qp) * want_lv.astype(np.float64))
+        _check_near_tie_rounding(got, codec.blocks_to_image(real, h, w))
+        assert int(sse[i]) == codec.sse(im, got)
+        want_rec = codec.reconstruct_deadzone(want_lv, qp, h, w, out_dtype=np.int16)
+        assert _psnr_close(float(psnr[i]), codec.psnr_from_sse(codec.sse(im, want_rec), h * w))
+
+
+@pytest.mark.parametrize("lv_dtype", ["i16", "i32"])
+def test_deadzone_unfused_u8(batch_u8, lv_dtype):
+    # forward -> quantise -> inverse through HBM, levels in either dtype
+    T = torch()
+    qp = 30
+    plan = batch_u8.plan(coef_dtype=A().I32, qmode=A().Q_DEADZONE, q=qp,
+                         qcoef_dtype=A().I16 if lv_dtype == "i16" else A().I32)
+    coef = batch_u8.coef_tensor(T.int32)
+    lv = batch_u8.coef_tensor(T.int16 if lv_dtype == "i16" else T.int32)
+    out = batch_u8.empty_like_images(np.uint8)
+    bits = T.zeros(len(batch_u8.images), dtype=T.int64, device="cuda")
+    plan.forward(batch_u8.dev, coef)
+    plan.quantise(coef, lv)
+    plan.inverse(lv, out)
+    plan.rate(lv, bits)
+    T.cuda.synchronize()
+    for i, (got, lvl, im) in enumerate(zip(batch_u8.unpack(out), batch_u8.split_coef(lv), batch_u8.images)):
+        h, w = im.shape
+        want_lv = codec.quantise_deadzone(codec.forward_image(im), qp)
+        assert np.array_equal(lvl.astype(np.int64), want_lv)
+        assert int(bits[i]) == codec.rate_bits(want_lv)
+        real = tf.inverse_real(codec.deadzone_step(qp) * want_lv.astype(np.float64))
+        _check_near_tie_rounding(got, codec.blocks_to_image(real, h, w), 0, 255)
+
+
+def test_rate_rejects_mask_plans(batch_u8):
+    plan = batch_u8.plan(coef_dtype=A().I32, qmode=A().Q_ZONAL, r=4)
+    T = torch()
+    with pytest.raises(A().Adct16Error) as e:
+        plan.rate(batch_u8.coef_tensor(T.int32), T.zeros(len(batch_u8.images), dtype=T.int64, device="cuda"))
+    assert e.value.status == A().E_STATE

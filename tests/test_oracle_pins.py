@@ -312,6 +312,49 @@ def test_uniform_levels_against_ideal():
 # ----------------------------------------------------------------------------
 # Quality measures.
 
+def test_deadzone_scales_and_steps():
+    # Each quantisation scale times its reconstruction scale is 2^20 to
+    # within 0.01 %, so quantising and reconstructing keeps the amplitude;
+    # the step doubles every six QP, and QP 4 is the unit step.
+    for qs, ds in zip(codec.QUANT_SCALE, codec.DEQUANT_SCALE):
+        assert abs(qs * ds / 2.0 ** 20 - 1.0) < 1e-4
+    for qp in range(0, 58):
+        assert codec.deadzone_step(qp + 6) == 2 * codec.deadzone_step(qp)
+    assert codec.deadzone_step(4) == 1.0
+    n = tf.row_norms()
+    m = codec.deadzone_multipliers(4)
+    for u in range(16):
+        for v in range(16):
+            # M = 1 / sqrt(n_u n_v) at QP 4 (unit step): S folded, nothing else
+            assert abs(float(m[u, v]) * math.sqrt(float(n[u] * n[v])) - 1.0) < 2e-7
+
+
+def test_deadzone_levels_against_exact_rationals():
+    # Away from float32 rounding, L = sign(Y) floor(|Y| / step + f) with Y = S Z S.
+    rng = np.random.default_rng(7)
+    z = rng.integers(-40000, 40000, size=(64, 16, 16))
+    for qp, inter in ((4, False), (22, False), (27, True), (37, True)):
+        got = codec.quantise_deadzone(z, qp, inter)
+        step = codec.deadzone_step(qp)
+        y = np.abs(tf.scale(z)) / step + (1.0 / 6.0 if inter else 1.0 / 3.0)
+        want = np.sign(z) * np.floor(y)
+        near = np.abs(y - np.rint(y)) < 1e-3
+        assert np.array_equal(got[~near], want[~near].astype(np.int64))
+        # dead zone: |Y| below (1 - f) steps gives level 0
+        small = np.abs(tf.scale(z)) < (1.0 - (1.0 / 6.0 if inter else 1.0 / 3.0)) * step * (1 - 1e-6)
+        assert np.all(got[small] == 0)
+
+
+def test_se_code_lengths_against_written_codes():
+    # Build each code word: k + 1 in binary, preceded by (bits - 1) zeros.
+    for v in range(-300, 301):
+        k = 2 * v - 1 if v > 0 else -2 * v
+        word = "0" * ((k + 1).bit_length() - 1) + format(k + 1, "b")
+        assert codec.se_code_length(v) == len(word)
+    assert [codec.se_code_length(v) for v in (0, 1, -1, 2, -2, 3, -3, 4)] == [1, 3, 3, 5, 5, 5, 5, 7]
+    assert codec.rate_bits(np.array([[0, 1], [-1, 4]])) == 1 + 3 + 3 + 7
+
+
 def test_psnr_closed_forms():
     a = np.full((48, 32), 100, dtype=np.uint8)
     assert codec.psnr(a, a) == math.inf
