@@ -35,7 +35,7 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["luma", "ragged", "residual"], default="luma")
+    ap.add_argument("--workload", choices=["luma", "ragged", "residual", "rd"], default="luma")
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--backend", choices=["auto", "valu", "mfma"], default="auto")
     ap.add_argument("--frames", type=int, default=None)
@@ -324,6 +324,47 @@ def bench_residual(args, A, torch):
                        "per_q": out}}
 
 
+def bench_rd(args, A, torch):
+    """Rate-distortion points of the deadzone quantiser on the 4:2:0 int16
+    residual stream: for QP in {22, 27, 32, 37} (inter offset 1/6), one fused
+    launch over all frames (levels and reconstruction written, per-plane SSE),
+    then the signed Exp-Golomb rate proxy of the levels."""
+    from synth import BASE_SEED, pack_images, yuv420_residual_frame
+    nf = args.frames or 8
+    planes = []
+    for t in range(nf):
+        planes += yuv420_residual_frame(BASE_SEED + 5, t)
+    buf, hs, ws, ps, offs = pack_images(planes, align_elems=64, pitch_multiple=64)
+    dev = torch.from_numpy(buf).cuda()
+    rec = torch.empty_like(dev)
+    npx = sum(p.size for p in planes)
+    stream = torch.cuda.current_stream()
+    points = []
+    for qp in (22, 27, 32, 37):
+        plan = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, qmode=A.Q_DEADZONE, q=qp,
+                      qcoef_dtype=A.I16, out_dtype=A.I16, flags=A.FLAG_AUTOTUNE | A.FLAG_DEADZONE_INTER)
+        lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
+        sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
+        bits = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
+        f = lambda: plan.compress_and_measure(dev, rec, lv, sse, None)
+        f()
+        ms = _events_ms(f, max(2, args.steps // 4), stream)
+        plan.rate(lv, bits)
+        torch.cuda.synchronize()
+        y = slice(0, None, 3)  # luma planes
+        s_y = int(sse[y].sum())
+        n_y = sum(hs[i] * ws[i] for i in range(0, len(hs), 3))
+        points.append({"qp": qp, "bits_per_sample": round(int(bits.sum()) / npx, 5),
+                       "psnr_y_db": round(10 * np.log10(65025.0 * n_y / s_y), 4) if s_y else None,
+                       "gsample_s": round(npx / (ms * 1e-3) / 1e9, 4), "plan": json.loads(plan.info())})
+    return {"metric": "Gsample/s 2D fwd+deadzone quant+inv 16x16 with rate proxy, 4:2:0 int16 residual stream",
+            "value": points[1]["gsample_s"], "unit": "Gsample/s", "n_gpus": 1, "steps": args.steps,
+            "dtype": "i16/f32/f64", "data": "synthetic", "higher_is_better": True,
+            "config": {"workload": f"{nf} frames 3840x2160 4:2:0 int16 residuals, deadzone quantiser "
+                                   "(inter offset 1/6), QP 22/27/32/37, levels + reconstruction written",
+                       "rd_curve": points}}
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -333,7 +374,7 @@ def main():
     import torch
 
     import paper_1606_05562_amd as A
-    fn = {"luma": bench_luma, "ragged": bench_ragged, "residual": bench_residual}[args.workload]
+    fn = {"luma": bench_luma, "ragged": bench_ragged, "residual": bench_residual, "rd": bench_rd}[args.workload]
     print(json.dumps(fn(args, A, torch)), flush=True)
 
 

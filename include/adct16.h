@@ -196,6 +196,28 @@ adct16_status adct16_quantise(adct16_plan plan, const void *d_coef, void *d_qcoe
  * evaluated in float64. */
 adct16_status adct16_inverse(adct16_plan plan, const void *d_qcoef, void *d_out, void *stream);
 
+/* Section 4's comparison: every block through the exact orthonormal DCT-II
+ * in float64 (Y = C X C^T), the plan's retention mask (qmode NONE, ZONAL or
+ * ZIGZAG, same r), the inverse C^T Y' C in float64, rounding half up and
+ * clamping to 0..255; with the per-image SSE and PSNR of that
+ * reconstruction (the reference of the APE measure).  U8 input; d_out (U8,
+ * the input layout), d_sse and d_psnr optional as in
+ * adct16_compress_and_measure.  ADCT16_E_STATE for quantiser plans.
+ * Rounded pixels may differ from another float64 evaluation order only
+ * where the real value lies within rounding error of a half-integer. */
+adct16_status adct16_dct_compress_and_measure(adct16_plan plan, const void *d_in, void *d_out,
+                                              int64_t *d_sse, double *d_psnr, void *stream);
+
+/* Section 4, SSIM of d_b against d_a (both U8 in the plan's layout, e.g.
+ * an image batch and its reconstruction): per image, the mean over every
+ * 11x11 window position inside the image of
+ *   ((2 mu_a mu_b + C1)(2 s_ab + C2)) / ((mu_a^2 + mu_b^2 + C1)(s_a + s_b + C2))
+ * with Gaussian-weighted moments (sigma 1.5, weights normalised),
+ * C1 = (0.01 * 255)^2, C2 = (0.03 * 255)^2, in float64.  d_ssim: n_images
+ * doubles (8-byte aligned); NaN for images smaller than 11 x 11.  Needs a
+ * plan with U8 input and output dtypes. */
+adct16_status adct16_ssim(adct16_plan plan, const void *d_a, const void *d_b, double *d_ssim, void *stream);
+
 /* Rate proxy for the quantisation levels in d_qcoef (qcoef_dtype, block-
  * major, as written by adct16_quantise or the fused call): per image, the
  * total length in bits of the signed Exp-Golomb codes se(v) of its levels

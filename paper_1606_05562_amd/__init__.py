@@ -36,6 +36,7 @@ _TORCH_DTYPE_CODES = {"torch.uint8": U8, "torch.int16": I16, "torch.int32": I32,
 EXPORTED = [
     "adct16_plan_create", "adct16_plan_destroy", "adct16_plan_num_blocks", "adct16_plan_info",
     "adct16_forward", "adct16_quantise", "adct16_inverse", "adct16_measure", "adct16_rate",
+    "adct16_dct_compress_and_measure", "adct16_ssim",
     "adct16_compress_and_measure", "adct16_dct_forward", "adct16_forward_1d", "adct16_inverse_1d",
     "adct16_graph_create", "adct16_graph_launch", "adct16_graph_destroy",
     "adct16_transform_matrix", "adct16_transform_measures",
@@ -84,6 +85,8 @@ def _load():
         "adct16_inverse": [vp, vp, vp, vp],
         "adct16_measure": [vp, vp, vp, vp, vp, vp],
         "adct16_rate": [vp, vp, vp, vp],
+        "adct16_dct_compress_and_measure": [vp, vp, vp, vp, vp, vp],
+        "adct16_ssim": [vp, vp, vp, vp, vp],
         "adct16_compress_and_measure": [vp, vp, vp, vp, vp, vp, vp],
         "adct16_dct_forward": [vp, vp, vp, i32, vp],
         "adct16_forward_1d": [vp, vp, i64, vp],
@@ -200,6 +203,15 @@ class Plan:
 
     def measure(self, a, b, sse, psnr=None, stream=None):
         _check(_lib.adct16_measure(self._plan, _ptr(a), _ptr(b), _ptr(sse), _ptr(psnr), _stream(stream)))
+
+    def dct_compress_and_measure(self, inp, out=None, sse=None, psnr=None, stream=None):
+        """The same retention with the exact DCT-II in float64 (comparison)."""
+        _check(_lib.adct16_dct_compress_and_measure(self._plan, _ptr(inp), _ptr(out), _ptr(sse), _ptr(psnr),
+                                                    _stream(stream)))
+
+    def ssim(self, a, b, out, stream=None):
+        """Per-image mean SSIM (float64) of b against a."""
+        _check(_lib.adct16_ssim(self._plan, _ptr(a), _ptr(b), _ptr(out), _stream(stream)))
 
     def rate(self, qcoef, bits, stream=None):
         """Per-image signed Exp-Golomb code length (bits, int64) of the levels."""

@@ -62,6 +62,9 @@ struct Tables {
   int32_t rsep;        // retained r x r square for separable masks (16 = all; zig-zag masks use wkeep)
   float qoff;          // deadzone quantiser rounding offset f
   int32_t pad[2];
+  double dctc[256];    // orthonormal DCT-II C[k][m] (comparison transform), float64
+  double gauss[11];    // SSIM window: normalised 1-D Gaussian, sigma 1.5
+  double pad2;
 };
 
 enum InKind { IN_U8 = 0, IN_I16 = 1 };
@@ -102,6 +105,9 @@ hipError_t launch_quantise(int coef_kind, int mode, int qout_kind, const Params&
 hipError_t launch_measure(int in_kind, int out_kind, const Params& P, int grid, hipStream_t s);
 hipError_t launch_1d(bool inverse, const int32_t* x, int32_t* y, int64_t n, hipStream_t s);
 hipError_t launch_rate(int level_kind, const Params& P, unsigned long long* bits, hipStream_t s);
+hipError_t launch_dct_roundtrip(const Params& P, int grid, hipStream_t s);
+hipError_t launch_ssim(const Params& P, const int64_t* tile_begin, int64_t n_tiles, const void* a, const void* b,
+                       double* ssim, hipStream_t s);
 
 hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStream_t s);
 hipError_t launch_mfma_forward_i8(int coef_kind, const Params& P, int grid, hipStream_t s);

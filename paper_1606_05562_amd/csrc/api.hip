@@ -89,6 +89,8 @@ struct adct16_plan_s {
   RowTask* d_rows = nullptr;
   int64_t n_rows = 0;
   uint32_t* d_task_sse = nullptr;  // per-task SSE partials of the matrix-core fused kernel
+  int64_t* d_ssim_tiles = nullptr;  // SSIM: first tile of each image (n_images + 1 entries)
+  int64_t n_ssim_tiles = 0;
   bool lines_aligned = false;       // every pitch and image offset a multiple of 128 bytes
   unsigned long long* d_sse_ws = nullptr;
   int grid = 0;           // persistent workgroups for the strip kernels
@@ -410,6 +412,21 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
     if (deadzone) t.deqc[u] = std::ldexp((double)kDequantScale[d->q % 6], d->q / 6 - 6) / std::sqrt((double)kNorm[u]);
   }
   t.qoff = (d->flags & ADCT16_FLAG_DEADZONE_INTER) ? (float)(1.0 / 6.0) : (float)(1.0 / 3.0);
+  // comparison transform and SSIM window
+  for (int k = 0; k < 16; ++k)
+    for (int m = 0; m < 16; ++m)
+      t.dctc[k * 16 + m] = (k == 0 ? 0.25 : 1.0 / std::sqrt(8.0)) * std::cos(M_PI * (2 * m + 1) * k / 32.0);
+  {
+    double gs = 0.0;
+    for (int k = 0; k < 11; ++k) gs += (t.gauss[k] = std::exp(-(double)((k - 5) * (k - 5)) / (2.0 * 1.5 * 1.5)));
+    for (int k = 0; k < 11; ++k) t.gauss[k] /= gs;
+  }
+  std::vector<int64_t> ssim_tiles(images.size() + 1, 0);
+  for (size_t i = 0; i < images.size(); ++i) {
+    const int oh = images[i].h - 10, ow = images[i].w - 10;
+    ssim_tiles[i + 1] = ssim_tiles[i] + (oh > 0 && ow > 0 ? (int64_t)((oh + 15) / 16) * ((ow + 31) / 32) : 0);
+  }
+  p->n_ssim_tiles = ssim_tiles.back();
   t.rsep = d->qmode == ADCT16_Q_ZONAL ? d->r : 16;
   std::vector<RowTask> rows;
   for (size_t i = 0; i < images.size(); ++i) {
@@ -423,10 +440,13 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
             hipMalloc(&p->d_tables, sizeof(Tables)) == hipSuccess &&
             hipMalloc(&p->d_rows, sizeof(RowTask) * rows.size()) == hipSuccess &&
             hipMalloc(&p->d_task_sse, sizeof(uint32_t) * rows.size()) == hipSuccess &&
+            hipMalloc(&p->d_ssim_tiles, sizeof(int64_t) * ssim_tiles.size()) == hipSuccess &&
             hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size()) == hipSuccess;
   ok = ok && hipMemcpy(p->d_images, images.data(), sizeof(ImageDesc) * images.size(), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_tables, &t, sizeof t, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->d_rows, rows.data(), sizeof(RowTask) * rows.size(), hipMemcpyHostToDevice) == hipSuccess;
+       hipMemcpy(p->d_rows, rows.data(), sizeof(RowTask) * rows.size(), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p->d_ssim_tiles, ssim_tiles.data(), sizeof(int64_t) * ssim_tiles.size(), hipMemcpyHostToDevice) ==
+           hipSuccess;
   if (!ok) {
     adct16_plan_destroy(p);
     return fail(ADCT16_E_NOMEM, "plan allocation failed");
@@ -467,6 +487,7 @@ adct16_status adct16_plan_destroy(adct16_plan p) {
   if (p->d_tables) (void)hipFree(p->d_tables);
   if (p->d_rows) (void)hipFree(p->d_rows);
   if (p->d_task_sse) (void)hipFree(p->d_task_sse);
+  if (p->d_ssim_tiles) (void)hipFree(p->d_ssim_tiles);
   if (p->d_sse_ws) (void)hipFree(p->d_sse_ws);
   delete p;
   return ADCT16_OK;
@@ -534,6 +555,35 @@ adct16_status adct16_inverse(adct16_plan p, const void* d_qcoef, void* d_out, vo
   hipError_t e = launch_valu_inverse(p->qcoef_kind, p->mode == MODE_DEADZONE ? MODE_UNIFORM : p->mode, p->out_kind,
                                      P, p->grid, (hipStream_t)stream);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "inverse kernel");
+}
+
+adct16_status adct16_dct_compress_and_measure(adct16_plan p, const void* d_in, void* d_out, int64_t* d_sse,
+                                              double* d_psnr, void* stream) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!d_in) return fail(ADCT16_E_NULL, "d_in is NULL");
+  if (p->in_kind != IN_U8 || (d_out && p->out_kind != OUT_U8))
+    return fail(ADCT16_E_DTYPE, "the DCT-II round trip takes U8 input and writes U8 output");
+  if (p->mode != MODE_MASK) return fail(ADCT16_E_STATE, "the DCT-II round trip uses retention masks only");
+  Params P = base_params(p);
+  P.in = d_in;
+  P.out = d_out;
+  P.sse = d_sse ? reinterpret_cast<unsigned long long*>(d_sse) : p->d_sse_ws;
+  P.psnr = d_psnr;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_zero_u64(P.sse, P.n_images, s);
+  if (e == hipSuccess) e = launch_dct_roundtrip(P, p->grid, s);
+  if (e == hipSuccess && d_psnr) e = launch_psnr_finalize(P, s);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "DCT-II round trip");
+}
+
+adct16_status adct16_ssim(adct16_plan p, const void* d_a, const void* d_b, double* d_ssim, void* stream) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!d_a || !d_b || !d_ssim) return fail(ADCT16_E_NULL, "d_a / d_b / d_ssim is NULL");
+  if (p->in_kind != IN_U8 || p->out_kind != OUT_U8) return fail(ADCT16_E_DTYPE, "SSIM compares U8 images");
+  if (reinterpret_cast<uintptr_t>(d_ssim) & 7) return fail(ADCT16_E_ALIGN, "d_ssim not 8-byte aligned");
+  Params P = base_params(p);
+  hipError_t e = launch_ssim(P, p->d_ssim_tiles, p->n_ssim_tiles, d_a, d_b, d_ssim, (hipStream_t)stream);
+  return e == hipSuccess ? ADCT16_OK : hip_fail(e, "SSIM kernels");
 }
 
 adct16_status adct16_rate(adct16_plan p, const void* d_qcoef, int64_t* d_bits, void* stream) {

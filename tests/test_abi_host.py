@@ -101,6 +101,8 @@ def test_null_arguments():
     assert lib.adct16_forward_1d(None, None, 4, None) == A.E_NULL
     assert lib.adct16_graph_launch(None, None) == A.E_NULL
     assert lib.adct16_rate(None, None, None, None) == A.E_NULL
+    assert lib.adct16_dct_compress_and_measure(None, None, None, None, None, None) == A.E_NULL
+    assert lib.adct16_ssim(None, None, None, None, None) == A.E_NULL
     assert lib.adct16_plan_destroy(None) == A.E_NULL
     assert b"NULL" in lib.adct16_last_error_string()
 

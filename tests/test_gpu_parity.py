@@ -8,6 +8,7 @@ summation order), so a pixel may differ by one only where the oracle's
 value lies within 1e-9 of a rounding tie; every other pixel must match.
 """
 import math
+import warnings
 
 import numpy as np
 import pytest
@@ -510,3 +511,54 @@ def test_rate_rejects_mask_plans(batch_u8):
     with pytest.raises(A().Adct16Error) as e:
         plan.rate(batch_u8.coef_tensor(T.int32), T.zeros(len(batch_u8.images), dtype=T.int64, device="cuda"))
     assert e.value.status == A().E_STATE
+
+
+# ----------------------------------------------------------------------------
+# Section 4's comparison: exact DCT-II round trip, SSIM and APE
+
+@pytest.mark.parametrize("qmode,r", [(1, 4), (2, 16), (2, 100), (0, 16)])
+def test_dct_roundtrip_and_ape(batch_u8, qmode, r):
+    T = torch()
+    keep = {0: codec.mask_none(), 1: codec.mask_zonal(r), 2: codec.mask_zigzag(r)}[qmode]
+    plan = batch_u8.plan(coef_dtype=A().I32, qmode=qmode, r=r)
+    out = batch_u8.empty_like_images(np.uint8, 9)
+    sse = T.zeros(len(batch_u8.images), dtype=T.int64, device="cuda")
+    psnr = T.zeros(len(batch_u8.images), dtype=T.float64, device="cuda")
+    plan.dct_compress_and_measure(batch_u8.dev, out, sse, psnr)
+    out_a = batch_u8.empty_like_images(np.uint8, 9)
+    psnr_a = T.zeros(len(batch_u8.images), dtype=T.float64, device="cuda")
+    plan.compress_and_measure(batch_u8.dev, out_a, None, None, psnr_a)
+    T.cuda.synchronize()
+    for i, (got, im) in enumerate(zip(batch_u8.unpack(out), batch_u8.images)):
+        h, w = im.shape
+        real = codec.blocks_to_image(tf.dct_inverse(np.where(keep[None], tf.dct_forward(codec.image_to_blocks(im)), 0.0)),
+                                     h, w)
+        _check_near_tie_rounding(got, real, 0, 255)
+        assert int(sse[i]) == codec.sse(im, got)
+        want_rec, want_psnr = codec.compress_dct_kept(im, keep)
+        assert _psnr_close(float(psnr[i]), codec.psnr(im, got))
+        if not math.isinf(want_psnr):
+            ape_gpu = codec.ape(float(psnr_a[i]), float(psnr[i]))
+            _, _, p_approx = codec.compress_kept(im, keep)
+            assert abs(ape_gpu - codec.ape(p_approx, want_psnr)) < 1e-3
+
+
+def test_ssim_against_oracle(batch_u8):
+    T = torch()
+    plan = batch_u8.plan(coef_dtype=A().I32, qmode=A().Q_ZIGZAG, r=20)
+    out = batch_u8.empty_like_images(np.uint8, 5)
+    plan.compress_and_measure(batch_u8.dev, out)
+    s = T.zeros(len(batch_u8.images), dtype=T.float64, device="cuda")
+    s_same = T.zeros(len(batch_u8.images), dtype=T.float64, device="cuda")
+    plan.ssim(batch_u8.dev, out, s)
+    plan.ssim(batch_u8.dev, batch_u8.dev, s_same)
+    T.cuda.synchronize()
+    for i, (got, im) in enumerate(zip(batch_u8.unpack(out), batch_u8.images)):
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            want = codec.ssim(im, got) if min(im.shape) >= 11 else float("nan")
+        if math.isnan(want):
+            assert math.isnan(float(s[i])) and math.isnan(float(s_same[i]))
+        else:
+            assert abs(float(s[i]) - want) < 1e-10, (i, float(s[i]), want)
+            assert abs(float(s_same[i]) - 1.0) < 1e-12
