@@ -35,7 +35,7 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["luma", "ragged", "residual", "rd"], default="luma")
+    ap.add_argument("--workload", choices=["luma", "ragged", "residual", "rd", "sweep"], default="luma")
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--backend", choices=["auto", "valu", "mfma"], default="auto")
     ap.add_argument("--frames", type=int, default=None)
@@ -365,6 +365,44 @@ def bench_rd(args, A, torch):
                        "rd_curve": points}}
 
 
+def bench_sweep(args, A, torch):
+    """Section 4's experiment on synthetic stand-ins for its 512x512 image
+    bank: for zig-zag retention of the first r coefficients, mean PSNR and
+    SSIM of the approximate transform and of the exact DCT-II, and the APE
+    between their PSNRs, all on the GPU."""
+    from synth import BASE_SEED, ar1_image, pack_images
+    n = args.frames or 32
+    ims = [ar1_image(BASE_SEED + 100 + k, 512, 512) for k in range(n)]
+    buf, hs, ws, ps, offs = pack_images(ims, align_elems=128, pitch_multiple=128)
+    dev = torch.from_numpy(buf).cuda()
+    out = torch.empty_like(dev)
+    psnr_a = torch.zeros(n, dtype=torch.float64, device="cuda")
+    psnr_d = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ssim_a = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ssim_d = torch.zeros(n, dtype=torch.float64, device="cuda")
+    rows = []
+    t0 = time.perf_counter()
+    for r in (1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 224, 255):
+        plan = A.Plan(hs, ws, ps, offs, in_dtype=A.U8, coef_dtype=A.I32, qmode=A.Q_ZIGZAG, r=r)
+        plan.compress_and_measure(dev, out, None, None, psnr_a)
+        plan.ssim(dev, out, ssim_a)
+        plan.dct_compress_and_measure(dev, out, None, psnr_d)
+        plan.ssim(dev, out, ssim_d)
+        pa, pd = psnr_a.cpu().numpy(), psnr_d.cpu().numpy()
+        ape = 100.0 * np.abs(pa - pd) / pd
+        fin = lambda x, nd: round(float(x), nd) if np.isfinite(x) else None  # lossless: +inf dB, no APE
+        rows.append({"r": r, "compression_pct": round(100.0 * (1 - r / 256.0), 2),
+                     "psnr_approx_db": fin(pa.mean(), 4), "psnr_dct_db": fin(pd.mean(), 4),
+                     "ssim_approx": fin(ssim_a.mean(), 5), "ssim_dct": fin(ssim_d.mean(), 5),
+                     "ape_pct": fin(ape.mean(), 4) if np.all(np.isfinite(pd)) else None})
+    wall = time.perf_counter() - t0
+    return {"metric": "Section 4 sweep: mean PSNR / SSIM / APE vs zig-zag r (approximate vs exact DCT-II)",
+            "value": rows[8]["ape_pct"], "unit": "APE % at r=16", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "u8 / f64", "data": "synthetic",
+            "config": {"workload": f"{n} AR(1) 512x512 uint8 images (rho 0.95, sigma 40), zig-zag retention",
+                       "wall_s": round(wall, 2), "rows": rows}}
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -374,7 +412,8 @@ def main():
     import torch
 
     import paper_1606_05562_amd as A
-    fn = {"luma": bench_luma, "ragged": bench_ragged, "residual": bench_residual, "rd": bench_rd}[args.workload]
+    fn = {"luma": bench_luma, "ragged": bench_ragged, "residual": bench_residual, "rd": bench_rd,
+          "sweep": bench_sweep}[args.workload]
     print(json.dumps(fn(args, A, torch)), flush=True)
 
 
