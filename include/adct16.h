@@ -159,6 +159,10 @@ typedef struct adct16_desc {
   int32_t q;
   int32_t backend;
   int32_t flags;
+  int32_t matrix;   /* ADCT16_MATRIX_APPROX (or ADCT16_MATRIX_T): the proposed transform,
+                       T with S folded into the quantiser; ADCT16_MATRIX_WHT: the same
+                       kernels with the Walsh-Hadamard matrix in natural order (S = I/4,
+                       all weights 3); ADCT16_E_MODE otherwise */
 } adct16_desc;
 
 typedef struct adct16_plan_s *adct16_plan;

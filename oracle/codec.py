@@ -88,8 +88,8 @@ def mask_zigzag(r: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 # Uniform quantiser with S folded in (float32 decision, see module notes).
 
-def uniform_multipliers(q: int) -> np.ndarray:
-    n = tf.row_norms()
+def uniform_multipliers(q: int, t: np.ndarray = tf.T) -> np.ndarray:
+    n = tf.row_norms(t)
     m = np.empty((BLK, BLK), dtype=np.float32)
     for u in range(BLK):
         for v in range(BLK):
@@ -97,9 +97,9 @@ def uniform_multipliers(q: int) -> np.ndarray:
     return m
 
 
-def quantise_uniform(z: np.ndarray, q: int) -> np.ndarray:
+def quantise_uniform(z: np.ndarray, q: int, t: np.ndarray = tf.T) -> np.ndarray:
     zf = np.asarray(z).astype(np.float32)
-    prod = (zf * uniform_multipliers(q)).astype(np.float32)
+    prod = (zf * uniform_multipliers(q, t)).astype(np.float32)
     return np.rint(prod).astype(np.int64)
 
 
@@ -257,42 +257,43 @@ def ssim(a: np.ndarray, b: np.ndarray, peak: float = 255.0) -> float:
 # ----------------------------------------------------------------------------
 # The compression experiment of Section 4, per image.
 
-def forward_image(img: np.ndarray) -> np.ndarray:
+def forward_image(img: np.ndarray, t: np.ndarray = tf.T) -> np.ndarray:
     """Integer coefficients Z of every block, (nblocks, 16, 16) int64."""
-    return tf.forward_int(image_to_blocks(img))
+    return tf.forward_int(image_to_blocks(img), t)
 
 
-def reconstruct_kept(z: np.ndarray, keep: np.ndarray, h: int, w: int, out_dtype=np.uint8) -> np.ndarray:
+def reconstruct_kept(z: np.ndarray, keep: np.ndarray, h: int, w: int, out_dtype=np.uint8,
+                     t: np.ndarray = tf.T) -> np.ndarray:
     """Zero the coefficients outside ``keep`` and invert exactly."""
     zk = np.where(keep[None, :, :], z, 0)
-    num = tf.inverse_int_numerator(zk)
+    num = tf.inverse_int_numerator(zk, t)
     rec = int_recon_u8(num) if out_dtype == np.uint8 else int_recon_i16(num)
     return blocks_to_image(rec, h, w)
 
 
 def reconstruct_uniform(levels: np.ndarray, q: int, h: int, w: int, out_dtype=np.uint8,
-                        rounded: bool = True) -> np.ndarray:
-    a = tf.inverse_real(dequantise_uniform(levels, q))
+                        rounded: bool = True, t: np.ndarray = tf.T) -> np.ndarray:
+    a = tf.inverse_real(dequantise_uniform(levels, q), t)
     if not rounded:
         return blocks_to_image(a, h, w)
     rec = round_half_up_u8(a) if out_dtype == np.uint8 else round_half_up_i16(a)
     return blocks_to_image(rec, h, w)
 
 
-def compress_kept(img: np.ndarray, keep: np.ndarray):
+def compress_kept(img: np.ndarray, keep: np.ndarray, t: np.ndarray = tf.T):
     """Forward, retain ``keep``, inverse, measure: (recon, sse, psnr)."""
     h, w = img.shape
-    rec = reconstruct_kept(forward_image(img), keep, h, w,
-                           np.uint8 if img.dtype == np.uint8 else np.int16)
+    rec = reconstruct_kept(forward_image(img, t), keep, h, w,
+                           np.uint8 if img.dtype == np.uint8 else np.int16, t)
     s = sse(img, rec)
     return rec, s, psnr_from_sse(s, h * w)
 
 
-def compress_uniform(img: np.ndarray, q: int):
+def compress_uniform(img: np.ndarray, q: int, t: np.ndarray = tf.T):
     """Forward, uniform quantiser, inverse, measure: (levels, recon, sse, psnr)."""
     h, w = img.shape
-    lv = quantise_uniform(forward_image(img), q)
-    rec = reconstruct_uniform(lv, q, h, w, np.uint8 if img.dtype == np.uint8 else np.int16)
+    lv = quantise_uniform(forward_image(img, t), q, t)
+    rec = reconstruct_uniform(lv, q, h, w, np.uint8 if img.dtype == np.uint8 else np.int16, t=t)
     s = sse(img, rec)
     return lv, rec, s, psnr_from_sse(s, h * w)
 

@@ -36,20 +36,30 @@ T = np.array([
 ], dtype=np.int64)
 
 
-def row_norms() -> np.ndarray:
+def wht() -> np.ndarray:
+    """The 16x16 Walsh-Hadamard matrix in natural (Sylvester) order,
+    H_1 = [1], H_2k = [[H_k, H_k], [H_k, -H_k]]: a comparison transform of
+    Table 2 that the kernels also accept in place of T."""
+    h = np.array([[1]], dtype=np.int64)
+    while h.shape[0] < N:
+        h = np.block([[h, h], [h, -h]])
+    return h
+
+
+def row_norms(t: np.ndarray = T) -> np.ndarray:
     """n_i = (T T^T)_ii, the squared row norms of T (Section 2: T T^T is
     diagonal, which is what makes the orthogonalisation possible)."""
-    return np.diag(T @ T.T).copy()
+    return np.diag(t @ t.T).copy()
 
 
-def s_diag() -> np.ndarray:
+def s_diag(t: np.ndarray = T) -> np.ndarray:
     """Diagonal of S = diag(1/sqrt(n_i)) in float64 (Section 2)."""
-    return 1.0 / np.sqrt(row_norms().astype(np.float64))
+    return 1.0 / np.sqrt(row_norms(t).astype(np.float64))
 
 
-def c_hat() -> np.ndarray:
+def c_hat(t: np.ndarray = T) -> np.ndarray:
     """C_hat = S T, the orthogonal approximation (Section 2), float64."""
-    return s_diag()[:, None] * T.astype(np.float64)
+    return s_diag(t)[:, None] * t.astype(np.float64)
 
 
 def dct_matrix(n: int = N) -> np.ndarray:
@@ -170,16 +180,16 @@ def additions(m: np.ndarray) -> int:
 # ----------------------------------------------------------------------------
 # Blockwise 2-D transform (Section 4: B_k = C~ A_k C~^T, A'_k = C~^T B'_k C~).
 
-def forward_int(blocks: np.ndarray) -> np.ndarray:
+def forward_int(blocks: np.ndarray, t: np.ndarray = T) -> np.ndarray:
     """Z = T A T^T for every 16x16 block (int64, exact)."""
     a = np.asarray(blocks, dtype=np.int64)
-    return T @ a @ T.T
+    return t @ a @ t.T
 
 
-def scale(z: np.ndarray) -> np.ndarray:
+def scale(z: np.ndarray, t: np.ndarray = T) -> np.ndarray:
     """B = S Z S, i.e. B_uv = s_u s_v Z_uv (float64): the orthonormal
     coefficients C_hat A C_hat^T."""
-    s = s_diag()
+    s = s_diag(t)
     return np.asarray(z, dtype=np.float64) * (s[:, None] * s[None, :])
 
 
@@ -189,27 +199,27 @@ def forward_real(blocks: np.ndarray) -> np.ndarray:
     return c @ np.asarray(blocks, dtype=np.float64) @ c.T
 
 
-def inverse_real(b: np.ndarray) -> np.ndarray:
+def inverse_real(b: np.ndarray, t: np.ndarray = T) -> np.ndarray:
     """A' = C_hat^T B' C_hat in float64 (Section 4)."""
-    c = c_hat()
+    c = c_hat(t)
     return c.T @ np.asarray(b, dtype=np.float64) @ c
 
 
-def inverse_weights() -> np.ndarray:
+def inverse_weights(t: np.ndarray = T) -> np.ndarray:
     """w_i = 48 / n_i.  Since C_hat^T S = T^T S^2 = T^T diag(1/n), the inverse
     of integer coefficients Z' (with B' = S Z' S) is
         A' = T^T diag(1/n) Z' diag(1/n) T = (T^T W Z' W T) / 2304,
     with W = diag(w) and 2304 = 48^2.  All w_i are integers (3, 4 or 6)."""
-    n = row_norms()
+    n = row_norms(t)
     assert np.all(48 % n == 0)
     return 48 // n
 
 
-def inverse_int_numerator(z_kept: np.ndarray) -> np.ndarray:
+def inverse_int_numerator(z_kept: np.ndarray, t: np.ndarray = T) -> np.ndarray:
     """Exact integer numerator N = T^T (w w^T * Z') T of A' = N / 2304."""
-    w = inverse_weights()
+    w = inverse_weights(t)
     wz = (w[:, None] * w[None, :]) * np.asarray(z_kept, dtype=np.int64)
-    return T.T @ wz @ T
+    return t.T @ wz @ t
 
 
 def dct_forward(blocks: np.ndarray) -> np.ndarray:

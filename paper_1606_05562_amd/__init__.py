@@ -66,6 +66,7 @@ class _Desc(ctypes.Structure):
         ("q", ctypes.c_int32),
         ("backend", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("matrix", ctypes.c_int32),
     ]
 
 
@@ -149,7 +150,7 @@ class Plan:
 
     def __init__(self, heights, widths, pitches, offsets, in_dtype=U8, coef_dtype=I32,
                  qcoef_dtype=None, out_dtype=None, qmode=Q_NONE, r=16, q=1,
-                 backend=BACKEND_AUTO, flags=0):
+                 backend=BACKEND_AUTO, flags=0, matrix=MATRIX_APPROX):
         n = len(heights)
         if not (len(widths) == len(pitches) == len(offsets) == n):
             raise ValueError("heights, widths, pitches and offsets must have equal lengths")
@@ -162,7 +163,7 @@ class Plan:
         if out_dtype is None:
             out_dtype = in_dtype
         d = _Desc(n, self._h, self._w, self._p, self._o, in_dtype, coef_dtype, qcoef_dtype, out_dtype,
-                  qmode, r, q, backend, flags)
+                  qmode, r, q, backend, flags, matrix)
         h = ctypes.c_void_p()
         _check(_lib.adct16_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._plan = h

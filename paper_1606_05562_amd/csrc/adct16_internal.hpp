@@ -65,8 +65,14 @@ struct Tables {
   double dctc[256];    // orthonormal DCT-II C[k][m] (comparison transform), float64
   double gauss[11];    // SSIM window: normalised 1-D Gaussian, sigma 1.5
   double pad2;
+  double sdiag[16];    // s_u = 1 / sqrt(n_u) of the plan's matrix
+  signed char tmat[256];  // the plan's integer matrix, tmat[u * 16 + k] (T or Walsh-Hadamard)
+  signed char wvec[16];   // inverse weights w_u = 48 / n_u
 };
 
+// The integer matrix of a plan: MAT_APPROX is T of the proposed transform,
+// MAT_WHT the Walsh-Hadamard matrix in natural order.
+enum MatKind { MAT_APPROX = 0, MAT_WHT = 1 };
 enum InKind { IN_U8 = 0, IN_I16 = 1 };
 enum CoefKind { CF_I32 = 0, CF_I16C = 1, CF_F32 = 2, CF_L16 = 3, CF_L32 = 4, CF_NONE = 5 };
 enum OutKind { OUT_NONE = 0, OUT_U8 = 1, OUT_I16 = 2, OUT_F32 = 3 };
@@ -96,10 +102,10 @@ struct Params {
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 hipError_t launch_psnr_finalize(const Params& P, hipStream_t s);
 hipError_t launch_task_sse_reduce(const Params& P, hipStream_t s);
-hipError_t launch_valu_forward(int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s);
-hipError_t launch_valu_fused(int in_kind, int mode, int qout_kind, int out_kind, const Params& P,
+hipError_t launch_valu_forward(int mat, int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s);
+hipError_t launch_valu_fused(int mat, int in_kind, int mode, int qout_kind, int out_kind, const Params& P,
                              int grid, hipStream_t s);
-hipError_t launch_valu_inverse(int coef_kind, int mode, int out_kind, const Params& P, int grid,
+hipError_t launch_valu_inverse(int mat, int coef_kind, int mode, int out_kind, const Params& P, int grid,
                                hipStream_t s);
 hipError_t launch_quantise(int coef_kind, int mode, int qout_kind, const Params& P, hipStream_t s);
 hipError_t launch_measure(int in_kind, int out_kind, const Params& P, int grid, hipStream_t s);

@@ -38,7 +38,26 @@ adct16_status hip_fail(hipError_t e, const char* what) {
 }
 
 // Section 2: n_i = (T T^T)_ii, the squared row norms of T; S = diag(1/sqrt(n)).
-constexpr int kNorm[16] = {16, 16, 12, 8, 8, 16, 12, 12, 16, 12, 12, 8, 8, 12, 12, 12};
+// Section 2: the matrix T (its squared row norms are 16, 16, 12, 8, 8, 16,
+// 12, 12, 16, 12, 12, 8, 8, 12, 12, 12).
+constexpr signed char kTHost[16][16] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {1, 1, 1, 1, 1, 1, 1, 1, -1, -1, -1, -1, -1, -1, -1, -1},
+    {1, 1, 1, 0, 0, -1, -1, -1, -1, -1, -1, 0, 0, 1, 1, 1},
+    {1, 1, 0, 0, 0, 0, -1, -1, 1, 1, 0, 0, 0, 0, -1, -1},
+    {1, 0, 0, -1, -1, 0, 0, 1, 1, 0, 0, -1, -1, 0, 0, 1},
+    {1, 1, -1, -1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1},
+    {1, 0, -1, -1, 1, 1, 0, -1, -1, 0, 1, 1, -1, -1, 0, 1},
+    {0, 0, -1, 1, 1, -1, -1, 1, -1, 1, 1, -1, -1, 1, 0, 0},
+    {1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1},
+    {1, -1, -1, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 1, 1, -1},
+    {1, -1, 0, 1, -1, 0, 1, -1, -1, 1, 0, -1, 1, 0, -1, 1},
+    {0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 0, 0},
+    {0, -1, 1, 0, 0, 1, -1, 0, 0, -1, 1, 0, 0, 1, -1, 0},
+    {1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1},
+    {0, -1, 1, -1, 1, -1, 1, 0, 0, 1, -1, 1, -1, 1, -1, 0},
+    {1, -1, 0, 0, -1, 1, -1, 1, -1, 1, -1, 1, 0, 0, 1, -1},
+};
 // Deadzone quantiser scales per QP mod 6 (the six steps per doubling of the
 // video-coding standards; quant_scale x dequant_scale ~ 2^20).
 constexpr int kQuantScale[6] = {26214, 23302, 20560, 18396, 16384, 14564};
@@ -92,6 +111,7 @@ struct adct16_plan_s {
   int64_t* d_ssim_tiles = nullptr;  // SSIM: first tile of each image (n_images + 1 entries)
   int64_t n_ssim_tiles = 0;
   bool lines_aligned = false;       // every pitch and image offset a multiple of 128 bytes
+  int mat = MAT_APPROX;             // integer matrix of the transform (T or Walsh-Hadamard)
   unsigned long long* d_sse_ws = nullptr;
   int grid = 0;           // persistent workgroups for the strip kernels
   int backend = ADCT16_BACKEND_VALU;   // resolved backend of the fused/forward calls
@@ -151,7 +171,7 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void*
   }
   e = launch_zero_u64(P.sse, P.n_images, s);
   if (e != hipSuccess) return hip_fail(e, "zero SSE");
-  e = launch_valu_fused(p->in_kind, p->mode, qk, ok, P, grid, s);
+  e = launch_valu_fused(p->mat, p->in_kind, p->mode, qk, ok, P, grid, s);
   if (e != hipSuccess) return hip_fail(e, "fused kernel");
   if (d_psnr) {
     e = launch_psnr_finalize(P, s);
@@ -174,7 +194,7 @@ std::mutex g_tune_mu;
 
 std::string tune_key(const adct16_plan_s* p, const char* arch) {
   std::ostringstream k;
-  k << arch << "/cu" << p->cu_count << "/b" << p->d.backend << "/in" << p->in_kind << "/m" << p->mode << "/q" << p->d.qmode
+  k << arch << "/cu" << p->cu_count << "/b" << p->d.backend << "/t" << p->mat << "/in" << p->in_kind << "/m" << p->mode << "/q" << p->d.qmode
     << "/o" << p->out_kind << "/f" << (p->d.flags & ADCT16_FLAG_EXPLICIT_COEF)
     << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips);
   return k.str();
@@ -332,6 +352,9 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   }
   if (d->backend < ADCT16_BACKEND_AUTO || d->backend > ADCT16_BACKEND_MFMA)
     return fail(ADCT16_E_MODE, "backend %d", d->backend);
+  if (!(d->matrix == ADCT16_MATRIX_APPROX || d->matrix == ADCT16_MATRIX_T || d->matrix == ADCT16_MATRIX_WHT))
+    return fail(ADCT16_E_MODE, "matrix %d: the kernels take the proposed transform or the Walsh-Hadamard matrix",
+                d->matrix);
   // geometry
   const int es = esize(d->in_dtype);
   std::vector<ImageDesc> images(d->n_images);
@@ -386,6 +409,17 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   for (const ImageDesc& g : images)
     if (((int64_t)g.pitch * es) % 128 || (g.offset * es) % 128) p->lines_aligned = false;
 
+  // the integer matrix, its squared row norms n_u and the weights 48 / n_u
+  p->mat = d->matrix == ADCT16_MATRIX_WHT ? MAT_WHT : MAT_APPROX;
+  int tmat[16][16], norm[16];
+  for (int u = 0; u < 16; ++u) {
+    norm[u] = 0;
+    for (int k = 0; k < 16; ++k) {
+      tmat[u][k] = p->mat == MAT_WHT ? ((__builtin_popcount(u & k) & 1) ? -1 : 1) : kTHost[u][k];
+      norm[u] += tmat[u][k] * tmat[u][k];
+    }
+  }
+
   // constant tables
   Tables t;
   memset(&t, 0, sizeof t);
@@ -393,8 +427,8 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   zigzag_rank(zz);
   for (int u = 0; u < 16; ++u) {
     for (int v = 0; v < 16; ++v) {
-      const int nn = kNorm[u] * kNorm[v];
-      const int wuv = (48 / kNorm[u]) * (48 / kNorm[v]);
+      const int nn = norm[u] * norm[v];
+      const int wuv = (48 / norm[u]) * (48 / norm[v]);
       bool keep = true;
       if (d->qmode == ADCT16_Q_ZONAL) keep = u < d->r && v < d->r;
       if (d->qmode == ADCT16_Q_ZIGZAG) keep = zz[u * 16 + v] < d->r;
@@ -407,9 +441,12 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
       if (deadzone)
         t.qmul[u * 16 + v] = (float)(std::ldexp((double)kQuantScale[d->q % 6] / std::sqrt((double)nn), -(14 + d->q / 6)));
     }
-    if (uniform) t.deqc[u] = (double)d->q / std::sqrt((double)kNorm[u]);
+    if (uniform) t.deqc[u] = (double)d->q / std::sqrt((double)norm[u]);
     // deadzone reconstruction step: dequant_scale[QP mod 6] 2^(QP / 6) / 64 (exact)
-    if (deadzone) t.deqc[u] = std::ldexp((double)kDequantScale[d->q % 6], d->q / 6 - 6) / std::sqrt((double)kNorm[u]);
+    if (deadzone) t.deqc[u] = std::ldexp((double)kDequantScale[d->q % 6], d->q / 6 - 6) / std::sqrt((double)norm[u]);
+    t.sdiag[u] = 1.0 / std::sqrt((double)norm[u]);
+    t.wvec[u] = (signed char)(48 / norm[u]);
+    for (int k = 0; k < 16; ++k) t.tmat[u * 16 + k] = (signed char)tmat[u][k];
   }
   t.qoff = (d->flags & ADCT16_FLAG_DEADZONE_INTER) ? (float)(1.0 / 6.0) : (float)(1.0 / 3.0);
   // comparison transform and SSIM window
@@ -526,7 +563,7 @@ adct16_status adct16_forward(adct16_plan p, const void* d_in, void* d_coef, void
     e = (p->d.flags & ADCT16_FLAG_MFMA_INT8) ? launch_mfma_forward_i8(p->coef_kind, P, p->grid, (hipStream_t)stream)
                                              : launch_mfma_forward(p->coef_kind, P, p->grid, (hipStream_t)stream);
   else
-    e = launch_valu_forward(p->in_kind, p->coef_kind, P, p->grid, (hipStream_t)stream);
+    e = launch_valu_forward(p->mat, p->in_kind, p->coef_kind, P, p->grid, (hipStream_t)stream);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "forward kernel");
 }
 
@@ -552,7 +589,7 @@ adct16_status adct16_inverse(adct16_plan p, const void* d_qcoef, void* d_out, vo
   P.qcoef = const_cast<void*>(d_qcoef);
   P.out = d_out;
   // the deadzone levels are reconstructed like uniform ones (step in the tables)
-  hipError_t e = launch_valu_inverse(p->qcoef_kind, p->mode == MODE_DEADZONE ? MODE_UNIFORM : p->mode, p->out_kind,
+  hipError_t e = launch_valu_inverse(p->mat, p->qcoef_kind, p->mode == MODE_DEADZONE ? MODE_UNIFORM : p->mode, p->out_kind,
                                      P, p->grid, (hipStream_t)stream);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "inverse kernel");
 }

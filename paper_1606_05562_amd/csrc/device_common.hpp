@@ -113,6 +113,36 @@ __device__ __forceinline__ void t_inv(T (&x)[16]) {
   }
 }
 
+// The Walsh-Hadamard transform in natural (Sylvester) order, y = H x, by
+// four radix-2 stages (64 additions); H is symmetric, so it is its own
+// inverse pass (H^T = H).
+template <class T>
+__device__ __forceinline__ void wht_fwd(T (&x)[16]) {
+#pragma unroll
+  for (int len = 1; len < 16; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < 16; i += 2 * len) {
+#pragma unroll
+      for (int j = 0; j < len; ++j) {
+        const T a = x[i + j], b = x[i + j + len];
+        x[i + j] = a + b;
+        x[i + j + len] = a - b;
+      }
+    }
+  }
+}
+
+
+template <int MAT, class T>
+__device__ __forceinline__ void m_fwd(T (&x)[16]) {
+  if constexpr (MAT == MAT_WHT) wht_fwd(x); else t_fwd(x);
+}
+
+template <int MAT, class T>
+__device__ __forceinline__ void m_inv(T (&x)[16]) {
+  if constexpr (MAT == MAT_WHT) wht_fwd(x); else t_inv(x);
+}
+
 // ---------------------------------------------------------------------------
 // Transposition buffer (Section 5.1's row-parallel transpose, in LDS).
 // Each wavefront owns 4 slots of 16 x 16 dwords, one per lane group p.

@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   __shared__ int lds_all[kWavesPerGroup * 512];
   int* lds = lds_all + (threadIdx.x >> 6) * 512;
   const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4, r = lane >> 3, c = lane & 7;
-  const MfmaConsts k = make_consts(q, g, P.tables->rsep);
+  const MfmaConsts k = make_consts(q, g, P.tables->rsep, P.tables);
   bool keepz[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) keepz[v] = P.tables->wkeep[(4 * g + v) * 16 + q] != 0;
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
 template <int CF>
 __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P) {
   const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
-  const MfmaConsts k = make_consts(q, g, 16);
+  const MfmaConsts k = make_consts(q, g, 16, P.tables);
   const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
   StripCursor c;
   if (!cursor_init(c, P)) return;
@@ -441,10 +441,10 @@ __device__ __forceinline__ unsigned pack_low_bytes(int a, int b, int c, int d) {
   return __builtin_amdgcn_perm(cd, ab, 0x05040100u);
 }
 
-__device__ __forceinline__ unsigned t_bytes(int row, int c0) {
+__device__ __forceinline__ unsigned t_bytes(const signed char* tm, int row, int c0, int scale = 1) {
   unsigned r = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) r |= (unsigned)(uint8_t)kT[row][c0 + j] << (8 * j);
+  for (int j = 0; j < 4; ++j) r |= (unsigned)(uint8_t)(scale * tm[row * 16 + c0 + j]) << (8 * j);
   return r;
 }
 
@@ -452,12 +452,10 @@ template <int CF>
 __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward_i8(Params P) {
   const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
   // stage-1 B: T[q][8g..8g+7] for g < 2 (K = image column), zero otherwise
-  const uint2 b1 = g < 2 ? make_uint2(t_bytes(q, 8 * g), t_bytes(q, 8 * g + 4)) : make_uint2(0u, 0u);
+  const signed char* tm = P.tables->tmat;
+  const uint2 b1 = g < 2 ? make_uint2(t_bytes(tm, q, 8 * g), t_bytes(tm, q, 8 * g + 4)) : make_uint2(0u, 0u);
   // stage-2 B: column u = q; slots j < 4: T[q][4g + j], slots j >= 4: 64 T[q][4g + j - 4]
-  unsigned t64 = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) t64 |= (unsigned)(uint8_t)(64 * kT[q][4 * g + j]) << (8 * j);
-  const uint2 b2 = make_uint2(t_bytes(q, 4 * g), t64);
+  const uint2 b2 = make_uint2(t_bytes(tm, q, 4 * g), t_bytes(tm, q, 4 * g, 64));
   const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
   StripCursor c;
   if (!cursor_init(c, P)) return;

@@ -119,22 +119,24 @@ __device__ __forceinline__ void fix_edges_u8(const LaneGeom& g, uint4& ra, uint4
 }
 
 // Forward transform of rows already loaded (and edge-extended).
+template <int MAT>
 __device__ __forceinline__ void forward_u8_rows(int* lds, int x, int p, const uint4& ra, const uint4& rb,
                                                 us2 (&Z)[16]) {
   pair_bytes(ra, rb, Z);
-  t_fwd(Z);                                 // row pass
+  m_fwd<MAT>(Z);                                 // row pass
   transpose_rows_to_cols(lds, p, x, Z);     // transposition buffer
-  t_fwd(Z);                                 // column pass: Z[u] = (Za[u][x], Zb[u][x])
+  m_fwd<MAT>(Z);                                 // column pass: Z[u] = (Za[u][x], Zb[u][x])
 }
 
+template <int MAT>
 __device__ __forceinline__ void forward_u8(const uint8_t* img, const LaneGeom& g, int* lds, int x,
                                            int p, uint4& ra, uint4& rb, us2 (&Z)[16]) {
   ra = load_row_u8(img, g.rowoff + g.xa, g.na);
   rb = load_row_u8(img, g.rowoff + g.xb, g.nb);
   pair_bytes(ra, rb, Z);
-  t_fwd(Z);                                 // row pass
+  m_fwd<MAT>(Z);                                 // row pass
   transpose_rows_to_cols(lds, p, x, Z);     // transposition buffer
-  t_fwd(Z);                                 // column pass: Z[u] = (Za[u][x], Zb[u][x])
+  m_fwd<MAT>(Z);                                 // column pass: Z[u] = (Za[u][x], Zb[u][x])
 }
 
 // Exact int32 coefficients from the packed 16-bit residues: AC values are
@@ -151,16 +153,17 @@ __device__ __forceinline__ void widen_u8(const us2 (&Z)[16], int x, int (&za)[16
   zb[0] = (x == 0) ? (int)(w0 >> 16) : zb[0];
 }
 
+template <int MAT>
 __device__ __forceinline__ void forward_i16(const int16_t* img, const LaneGeom& g, int* lds, int x,
                                             int p, int (&za)[16], int (&zb)[16]) {
   load_row_i16(img, g.rowoff + g.xa, g.na, za);
   load_row_i16(img, g.rowoff + g.xb, g.nb, zb);
-  t_fwd(za);
-  t_fwd(zb);
+  m_fwd<MAT>(za);
+  m_fwd<MAT>(zb);
   transpose_rows_to_cols(lds, p, x, za);
   transpose_rows_to_cols(lds, p, x, zb);
-  t_fwd(za);
-  t_fwd(zb);
+  m_fwd<MAT>(za);
+  m_fwd<MAT>(zb);
 }
 
 // ---------------------------------------------------------------------------
@@ -169,23 +172,25 @@ __device__ __forceinline__ void forward_i16(const int16_t* img, const LaneGeom& 
 // Mask modes: t = T^T (W .* Z) T + 1152 exactly in int32 (W = w w^T .* keep
 // already applied by the caller).  `rnd` adds 1152 at (0,0), which adds 1152
 // to every output because row 0 of T is all ones.
+template <int MAT>
 __device__ __forceinline__ void inverse_int(int* lds, int x, int p, int (&a)[16], int (&b)[16], bool rnd) {
   if (rnd && x == 0) { a[0] += 1152; b[0] += 1152; }
-  t_inv(a);
-  t_inv(b);
+  m_inv<MAT>(a);
+  m_inv<MAT>(b);
   transpose_cols_to_rows(lds, p, x, a);
   transpose_cols_to_rows(lds, p, x, b);
-  t_inv(a);
-  t_inv(b);
+  m_inv<MAT>(a);
+  m_inv<MAT>(b);
 }
 
+template <int MAT>
 __device__ __forceinline__ void inverse_f64(int* lds, int x, int p, double (&a)[16], double (&b)[16]) {
-  t_inv(a);
-  t_inv(b);
+  m_inv<MAT>(a);
+  m_inv<MAT>(b);
   transpose_cols_to_rows_f64(lds, p, x, a);
   transpose_cols_to_rows_f64(lds, p, x, b);
-  t_inv(a);
-  t_inv(b);
+  m_inv<MAT>(a);
+  m_inv<MAT>(b);
 }
 
 // floor((N + 1152) / 2304) clamped to [0, 255], given t = N + 1152: for
@@ -287,7 +292,7 @@ __device__ __forceinline__ void load_col(const void* buf, int64_t blk, int x, bo
 // ---------------------------------------------------------------------------
 // Kernels.
 
-template <int IN, int CF>
+template <int MAT, int IN, int CF>
 __global__ __launch_bounds__(kGroupThreads) void k_forward(Params P) {
   __shared__ int lds_all[kWavesPerGroup * kWaveLds];
   int* lds = lds_all + (threadIdx.x >> 6) * kWaveLds;
@@ -305,7 +310,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_forward(Params P) {
     if constexpr (IN == IN_U8) {
       uint4 ra, rb;
       us2 Z[16];
-      forward_u8(reinterpret_cast<const uint8_t*>(P.in), g, lds, x, p, ra, rb, Z);
+      forward_u8<MAT>(reinterpret_cast<const uint8_t*>(P.in), g, lds, x, p, ra, rb, Z);
       if constexpr (CF == CF_I16C) {
         // Residues are the int16 bit patterns of the centred coefficients,
         // except DC: flipping bit 15 subtracts 32768 modulo 2^16.
@@ -321,7 +326,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_forward(Params P) {
       }
       widen_u8(Z, x, za, zb);
     } else {
-      forward_i16(reinterpret_cast<const int16_t*>(P.in), g, lds, x, p, za, zb);
+      forward_i16<MAT>(reinterpret_cast<const int16_t*>(P.in), g, lds, x, p, za, zb);
     }
     if constexpr (CF == CF_I32) {
       if (g.na > 0) store_col<CF_I32>(P.coef, g.blka, x, za);
@@ -356,7 +361,7 @@ __device__ __forceinline__ int level_of(int z, float m, float f) {
 // Retention / quantiser of the column-layout coefficients of one lane.
 // Mask modes multiply by W = w_u w_v keep(u, v) (the inverse weights); the
 // masked coefficients themselves are kept for an optional qcoef output.
-template <int MODE, int QOUT, int OUT>
+template <int MAT, int MODE, int QOUT, int OUT>
 __device__ __forceinline__ void quant_and_inverse(const Params& P, const LaneGeom& g, int* lds, int x,
                                                   int p, const int (&W)[16], const float (&Mq)[16],
                                                   double Dc, int (&za)[16], int (&zb)[16],
@@ -378,7 +383,7 @@ __device__ __forceinline__ void quant_and_inverse(const Params& P, const LaneGeo
       za[u] = __mul24(za[u], W[u]);
       zb[u] = __mul24(zb[u], W[u]);
     }
-    inverse_int(lds, x, p, za, zb, OUT != OUT_F32);
+    inverse_int<MAT>(lds, x, p, za, zb, OUT != OUT_F32);
 #pragma unroll
     for (int k = 0; k < 16; ++k) { oa[k] = za[k]; ob[k] = zb[k]; }
   } else {
@@ -394,10 +399,10 @@ __device__ __forceinline__ void quant_and_inverse(const Params& P, const LaneGeo
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      fa[u] = ((double)la[u] * Dc) * s_of(u);
-      fb[u] = ((double)lb[u] * Dc) * s_of(u);
+      fa[u] = ((double)la[u] * Dc) * P.tables->sdiag[u];
+      fb[u] = ((double)lb[u] * Dc) * P.tables->sdiag[u];
     }
-    inverse_f64(lds, x, p, fa, fb);
+    inverse_f64<MAT>(lds, x, p, fa, fb);
   }
 }
 
@@ -428,7 +433,7 @@ __device__ __forceinline__ void recon_i16(const int (&t)[16], const double (&f)[
   }
 }
 
-template <int IN, int MODE, int QOUT, int OUT>
+template <int MAT, int IN, int MODE, int QOUT, int OUT>
 __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Params P) {
   __shared__ int lds_all[kWavesPerGroup * kWaveLds];
   int* lds = lds_all + (threadIdx.x >> 6) * kWaveLds;
@@ -467,14 +472,14 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
     if constexpr (IN == IN_U8) {
       us2 Z[16];
       fix_edges_u8(g, ra, rb);
-      forward_u8_rows(lds, x, p, ra, rb, Z);
+      forward_u8_rows<MAT>(lds, x, p, ra, rb, Z);
       widen_u8(Z, x, za, zb);
     } else {
-      forward_i16(reinterpret_cast<const int16_t*>(P.in), g, lds, x, p, za, zb);
+      forward_i16<MAT>(reinterpret_cast<const int16_t*>(P.in), g, lds, x, p, za, zb);
     }
     int ta[16], tb[16];
     double fa[16], fb[16];
-    quant_and_inverse<MODE, QOUT, OUT>(P, g, lds, x, p, W, Mq, Dc, za, zb, ta, tb, fa, fb);
+    quant_and_inverse<MAT, MODE, QOUT, OUT>(P, g, lds, x, p, W, Mq, Dc, za, zb, ta, tb, fa, fb);
     if constexpr (IN == IN_U8) {
       unsigned pa[16], pb[16];
       recon_u8<MODE, OUT>(ta, fa, pa);
@@ -521,7 +526,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
 }
 
 // Inverse of block-major coefficients or levels.
-template <int CFIN, int MODE, int OUT>
+template <int MAT, int CFIN, int MODE, int OUT>
 __global__ __launch_bounds__(kGroupThreads) void k_inverse(Params P) {
   __shared__ int lds_all[kWavesPerGroup * kWaveLds];
   int* lds = lds_all + (threadIdx.x >> 6) * kWaveLds;
@@ -549,16 +554,16 @@ __global__ __launch_bounds__(kGroupThreads) void k_inverse(Params P) {
         za[u] = __mul24(za[u], W[u]);
         zb[u] = __mul24(zb[u], W[u]);
       }
-      inverse_int(lds, x, p, za, zb, OUT != OUT_F32);
+      inverse_int<MAT>(lds, x, p, za, zb, OUT != OUT_F32);
 #pragma unroll
       for (int k = 0; k < 16; ++k) { ta[k] = za[k]; tb[k] = zb[k]; }
     } else {
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        fa[u] = ((double)za[u] * Dc) * s_of(u);
-        fb[u] = ((double)zb[u] * Dc) * s_of(u);
+        fa[u] = ((double)za[u] * Dc) * P.tables->sdiag[u];
+        fb[u] = ((double)zb[u] * Dc) * P.tables->sdiag[u];
       }
-      inverse_f64(lds, x, p, fa, fb);
+      inverse_f64<MAT>(lds, x, p, fa, fb);
     }
     if (!g.rowok) continue;
     if constexpr (OUT == OUT_U8) {
@@ -773,74 +778,90 @@ hipError_t launch_psnr_finalize(const Params& P, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_valu_forward(int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s) {
+template <int MAT>
+static hipError_t valu_forward_m(int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s) {
   if (in_kind == IN_U8) {
     switch (coef_kind) {
-      case CF_I32: ADCT16_LAUNCH((k_forward<IN_U8, CF_I32>), grid, s, P);
-      case CF_I16C: ADCT16_LAUNCH((k_forward<IN_U8, CF_I16C>), grid, s, P);
-      case CF_F32: ADCT16_LAUNCH((k_forward<IN_U8, CF_F32>), grid, s, P);
+      case CF_I32: ADCT16_LAUNCH((k_forward<MAT, IN_U8, CF_I32>), grid, s, P);
+      case CF_I16C: ADCT16_LAUNCH((k_forward<MAT, IN_U8, CF_I16C>), grid, s, P);
+      case CF_F32: ADCT16_LAUNCH((k_forward<MAT, IN_U8, CF_F32>), grid, s, P);
     }
   } else {
     switch (coef_kind) {
-      case CF_I32: ADCT16_LAUNCH((k_forward<IN_I16, CF_I32>), grid, s, P);
-      case CF_F32: ADCT16_LAUNCH((k_forward<IN_I16, CF_F32>), grid, s, P);
+      case CF_I32: ADCT16_LAUNCH((k_forward<MAT, IN_I16, CF_I32>), grid, s, P);
+      case CF_F32: ADCT16_LAUNCH((k_forward<MAT, IN_I16, CF_F32>), grid, s, P);
     }
   }
   return hipErrorInvalidValue;
 }
 
-template <int IN, int MODE, int QOUT>
+hipError_t launch_valu_forward(int mat, int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s) {
+  return mat == MAT_WHT ? valu_forward_m<MAT_WHT>(in_kind, coef_kind, P, grid, s)
+                        : valu_forward_m<MAT_APPROX>(in_kind, coef_kind, P, grid, s);
+}
+
+template <int MAT, int IN, int MODE, int QOUT>
 static hipError_t fused_out(int out_kind, const Params& P, int grid, hipStream_t s) {
   constexpr int OUTK = IN == IN_U8 ? OUT_U8 : OUT_I16;
-  if (out_kind == OUT_NONE) ADCT16_LAUNCH((k_fused<IN, MODE, QOUT, OUT_NONE>), grid, s, P);
-  if (out_kind == OUTK) ADCT16_LAUNCH((k_fused<IN, MODE, QOUT, OUTK>), grid, s, P);
+  if (out_kind == OUT_NONE) ADCT16_LAUNCH((k_fused<MAT, IN, MODE, QOUT, OUT_NONE>), grid, s, P);
+  if (out_kind == OUTK) ADCT16_LAUNCH((k_fused<MAT, IN, MODE, QOUT, OUTK>), grid, s, P);
   return hipErrorInvalidValue;
 }
 
-template <int IN>
+template <int MAT, int IN>
 static hipError_t fused_in(int mode, int qout, int out_kind, const Params& P, int grid, hipStream_t s) {
   if (mode == MODE_MASK) {
-    if (qout == CF_NONE) return fused_out<IN, MODE_MASK, CF_NONE>(out_kind, P, grid, s);
-    if (qout == CF_I32) return fused_out<IN, MODE_MASK, CF_I32>(out_kind, P, grid, s);
-    if (IN == IN_U8 && qout == CF_I16C) return fused_out<IN, MODE_MASK, CF_I16C>(out_kind, P, grid, s);
+    if (qout == CF_NONE) return fused_out<MAT, IN, MODE_MASK, CF_NONE>(out_kind, P, grid, s);
+    if (qout == CF_I32) return fused_out<MAT, IN, MODE_MASK, CF_I32>(out_kind, P, grid, s);
+    if (IN == IN_U8 && qout == CF_I16C) return fused_out<MAT, IN, MODE_MASK, CF_I16C>(out_kind, P, grid, s);
   } else if (mode == MODE_UNIFORM) {
-    if (qout == CF_NONE) return fused_out<IN, MODE_UNIFORM, CF_NONE>(out_kind, P, grid, s);
-    if (qout == CF_L16) return fused_out<IN, MODE_UNIFORM, CF_L16>(out_kind, P, grid, s);
-    if (qout == CF_L32) return fused_out<IN, MODE_UNIFORM, CF_L32>(out_kind, P, grid, s);
+    if (qout == CF_NONE) return fused_out<MAT, IN, MODE_UNIFORM, CF_NONE>(out_kind, P, grid, s);
+    if (qout == CF_L16) return fused_out<MAT, IN, MODE_UNIFORM, CF_L16>(out_kind, P, grid, s);
+    if (qout == CF_L32) return fused_out<MAT, IN, MODE_UNIFORM, CF_L32>(out_kind, P, grid, s);
   } else {
-    if (qout == CF_NONE) return fused_out<IN, MODE_DEADZONE, CF_NONE>(out_kind, P, grid, s);
-    if (qout == CF_L16) return fused_out<IN, MODE_DEADZONE, CF_L16>(out_kind, P, grid, s);
-    if (qout == CF_L32) return fused_out<IN, MODE_DEADZONE, CF_L32>(out_kind, P, grid, s);
+    if (qout == CF_NONE) return fused_out<MAT, IN, MODE_DEADZONE, CF_NONE>(out_kind, P, grid, s);
+    if (qout == CF_L16) return fused_out<MAT, IN, MODE_DEADZONE, CF_L16>(out_kind, P, grid, s);
+    if (qout == CF_L32) return fused_out<MAT, IN, MODE_DEADZONE, CF_L32>(out_kind, P, grid, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_valu_fused(int in_kind, int mode, int qout_kind, int out_kind, const Params& P,
+hipError_t launch_valu_fused(int mat, int in_kind, int mode, int qout_kind, int out_kind, const Params& P,
                              int grid, hipStream_t s) {
-  if (in_kind == IN_U8) return fused_in<IN_U8>(mode, qout_kind, out_kind, P, grid, s);
-  return fused_in<IN_I16>(mode, qout_kind, out_kind, P, grid, s);
+  if (mat == MAT_WHT) {
+    if (in_kind == IN_U8) return fused_in<MAT_WHT, IN_U8>(mode, qout_kind, out_kind, P, grid, s);
+    return fused_in<MAT_WHT, IN_I16>(mode, qout_kind, out_kind, P, grid, s);
+  }
+  if (in_kind == IN_U8) return fused_in<MAT_APPROX, IN_U8>(mode, qout_kind, out_kind, P, grid, s);
+  return fused_in<MAT_APPROX, IN_I16>(mode, qout_kind, out_kind, P, grid, s);
 }
 
-template <int CFIN, int MODE>
+template <int MAT, int CFIN, int MODE>
 static hipError_t inverse_out(int out_kind, const Params& P, int grid, hipStream_t s) {
   switch (out_kind) {
-    case OUT_U8: ADCT16_LAUNCH((k_inverse<CFIN, MODE, OUT_U8>), grid, s, P);
-    case OUT_I16: ADCT16_LAUNCH((k_inverse<CFIN, MODE, OUT_I16>), grid, s, P);
-    case OUT_F32: ADCT16_LAUNCH((k_inverse<CFIN, MODE, OUT_F32>), grid, s, P);
+    case OUT_U8: ADCT16_LAUNCH((k_inverse<MAT, CFIN, MODE, OUT_U8>), grid, s, P);
+    case OUT_I16: ADCT16_LAUNCH((k_inverse<MAT, CFIN, MODE, OUT_I16>), grid, s, P);
+    case OUT_F32: ADCT16_LAUNCH((k_inverse<MAT, CFIN, MODE, OUT_F32>), grid, s, P);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_valu_inverse(int coef_kind, int mode, int out_kind, const Params& P, int grid,
-                               hipStream_t s) {
+template <int MAT>
+static hipError_t valu_inverse_m(int coef_kind, int mode, int out_kind, const Params& P, int grid, hipStream_t s) {
   if (mode == MODE_MASK) {
-    if (coef_kind == CF_I32) return inverse_out<CF_I32, MODE_MASK>(out_kind, P, grid, s);
-    if (coef_kind == CF_I16C) return inverse_out<CF_I16C, MODE_MASK>(out_kind, P, grid, s);
+    if (coef_kind == CF_I32) return inverse_out<MAT, CF_I32, MODE_MASK>(out_kind, P, grid, s);
+    if (coef_kind == CF_I16C) return inverse_out<MAT, CF_I16C, MODE_MASK>(out_kind, P, grid, s);
   } else {
-    if (coef_kind == CF_L32) return inverse_out<CF_L32, MODE_UNIFORM>(out_kind, P, grid, s);
-    if (coef_kind == CF_L16) return inverse_out<CF_L16, MODE_UNIFORM>(out_kind, P, grid, s);
+    if (coef_kind == CF_L32) return inverse_out<MAT, CF_L32, MODE_UNIFORM>(out_kind, P, grid, s);
+    if (coef_kind == CF_L16) return inverse_out<MAT, CF_L16, MODE_UNIFORM>(out_kind, P, grid, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_valu_inverse(int mat, int coef_kind, int mode, int out_kind, const Params& P, int grid,
+                               hipStream_t s) {
+  return mat == MAT_WHT ? valu_inverse_m<MAT_WHT>(coef_kind, mode, out_kind, P, grid, s)
+                        : valu_inverse_m<MAT_APPROX>(coef_kind, mode, out_kind, P, grid, s);
 }
 
 hipError_t launch_quantise(int coef_kind, int mode, int qout_kind, const Params& P, hipStream_t s) {

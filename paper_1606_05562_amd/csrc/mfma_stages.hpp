@@ -12,27 +12,9 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
 
-// Section 2: the matrix T.
-__constant__ signed char kT[16][16] = {
-    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
-    {1, 1, 1, 1, 1, 1, 1, 1, -1, -1, -1, -1, -1, -1, -1, -1},
-    {1, 1, 1, 0, 0, -1, -1, -1, -1, -1, -1, 0, 0, 1, 1, 1},
-    {1, 1, 0, 0, 0, 0, -1, -1, 1, 1, 0, 0, 0, 0, -1, -1},
-    {1, 0, 0, -1, -1, 0, 0, 1, 1, 0, 0, -1, -1, 0, 0, 1},
-    {1, 1, -1, -1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1},
-    {1, 0, -1, -1, 1, 1, 0, -1, -1, 0, 1, 1, -1, -1, 0, 1},
-    {0, 0, -1, 1, 1, -1, -1, 1, -1, 1, 1, -1, -1, 1, 0, 0},
-    {1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1},
-    {1, -1, -1, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 1, 1, -1},
-    {1, -1, 0, 1, -1, 0, 1, -1, -1, 1, 0, -1, 1, 0, -1, 1},
-    {0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 0, 0},
-    {0, -1, 1, 0, 0, 1, -1, 0, 0, -1, 1, 0, 0, 1, -1, 0},
-    {1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1},
-    {0, -1, 1, -1, 1, -1, 1, 0, 0, 1, -1, 1, -1, 1, -1, 0},
-    {1, -1, 0, 0, -1, 1, -1, 1, -1, 1, -1, 1, 0, 0, 1, -1},
-};
-// w_u = 48 / n_u with n = diag(T T^T).
-__constant__ signed char kW[16] = {3, 3, 4, 6, 6, 3, 4, 4, 3, 4, 4, 6, 6, 4, 4, 4};
+// The integer matrix (T of Section 2, or the Walsh-Hadamard matrix) and the
+// inverse weights w_u = 48 / n_u come from the plan's tables (Tables::tmat,
+// Tables::wvec), read once per lane when the constant operands are built.
 
 __device__ __forceinline__ unsigned h2bits(float lo, float hi) {
   return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(lo, hi));
@@ -67,16 +49,19 @@ struct MfmaConsts {
   uint2 gq;      // collapsed stages 2-3: G[q][4g..4g+3] 2^-11, G = T^T diag(w m) T
 };
 
-__device__ __forceinline__ MfmaConsts make_consts(int q, int g, int r_sep) {
+__device__ __forceinline__ MfmaConsts make_consts(int q, int g, int r_sep, const Tables* tb) {
+  const signed char* tm = tb->tmat;  // tm[u * 16 + k] = T[u][k]
+  const signed char* kW = tb->wvec;
+  auto kT = [tm](int u, int kk) { return (int)tm[u * 16 + kk]; };
   MfmaConsts k;
   const bool keep_q = q < r_sep;
   float t[4], w3[4], w4[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int kk = 4 * g + m;
-    t[m] = keep_q ? (float)kT[q][kk] : 0.0f;
-    w3[m] = (float)(kW[kk] * kT[kk][q]) * (1.0f / 2048.0f);
-    w4[m] = (float)(kW[kk] * kT[kk][q]);
+    t[m] = keep_q ? (float)kT(q, kk) : 0.0f;
+    w3[m] = (float)(kW[kk] * kT(kk, q)) * (1.0f / 2048.0f);
+    w4[m] = (float)(kW[kk] * kT(kk, q));
   }
   k.tq = make_uint2(pack_h(t[0], t[1]), pack_h(t[2], t[3]));
   k.c1 = (q == 0) ? -18432.0f : 0.0f;
@@ -84,13 +69,14 @@ __device__ __forceinline__ MfmaConsts make_consts(int q, int g, int r_sep) {
   k.w3 = make_uint4(w30, w31, w30, w31);
   k.w4 = make_uint2(pack_h(w4[0], w4[1]), pack_h(w4[2], w4[3]));
   // G = T^T diag(w m) T (m: retained rows / columns of a separable mask) is
-  // symmetric with |G| <= 68; G 2^-11 is exact in fp16.
+  // a symmetric integer matrix with |G| <= 68 (48 for the Walsh-Hadamard
+  // matrix); G 2^-11 is exact in fp16.
   float gv[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int kk = 4 * g + m;
     int acc = 0;
-    for (int u = 0; u < r_sep; ++u) acc += kW[u] * kT[u][q] * kT[u][kk];
+    for (int u = 0; u < r_sep; ++u) acc += kW[u] * kT(u, q) * kT(u, kk);
     gv[m] = (float)acc * (1.0f / 2048.0f);
   }
   k.gq = make_uint2(pack_h(gv[0], gv[1]), pack_h(gv[2], gv[3]));
@@ -98,7 +84,7 @@ __device__ __forceinline__ MfmaConsts make_consts(int q, int g, int r_sep) {
   for (int v = 0; v < 4; ++v) {
     const int j = 4 * g + v;
     int s = 0;
-    for (int f = 0; f < 16; ++f) s += kW[f] * kT[f][j];
+    for (int f = 0; f < 16; ++f) s += kW[f] * kT(f, j);
     k.c4[v] = -1536.0f * (float)s;
   }
   return k;

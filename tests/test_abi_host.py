@@ -80,6 +80,8 @@ def test_validation_errors():
     assert _plan_status(qmode=A.Q_DEADZONE, q=30, qcoef_dtype=A.U8) == A.E_DTYPE
     assert _plan_status(qmode=7) == A.E_MODE
     assert _plan_status(backend=5) == A.E_MODE
+    assert _plan_status(matrix=A.MATRIX_DCT) == A.E_MODE
+    assert _plan_status(matrix=9) == A.E_MODE
 
 
 def test_valid_desc_reaches_device_check():

@@ -562,3 +562,57 @@ def test_ssim_against_oracle(batch_u8):
         else:
             assert abs(float(s[i]) - want) < 1e-10, (i, float(s[i]), want)
             assert abs(float(s_same[i]) - 1.0) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# The same kernels with the Walsh-Hadamard matrix (a comparison transform of
+# Table 2) in place of T
+
+@pytest.mark.parametrize("backend", ["valu", "mfma"])
+@pytest.mark.parametrize("qmode,r", [(0, 16), (1, 4), (2, 50)])
+def test_wht_fused_u8(batch_u8, backend, qmode, r):
+    T = torch()
+    be = A().BACKEND_VALU if backend == "valu" else A().BACKEND_MFMA
+    plan = batch_u8.plan(coef_dtype=A().I32, qmode=qmode, r=r, backend=be, matrix=A().MATRIX_WHT)
+    out = batch_u8.empty_like_images(np.uint8, 7)
+    sse = T.zeros(len(batch_u8.images), dtype=T.int64, device="cuda")
+    plan.compress_and_measure(batch_u8.dev, out, None, sse)
+    T.cuda.synchronize()
+    keep = {0: codec.mask_none(), 1: codec.mask_zonal(r), 2: codec.mask_zigzag(r)}[qmode]
+    for i, (got, im) in enumerate(zip(batch_u8.unpack(out), batch_u8.images)):
+        want, s, _ = codec.compress_kept(im, keep, tf.wht())
+        assert np.array_equal(got, want), f"image {i}"
+        assert int(sse[i]) == s
+        if qmode == 0:
+            assert np.array_equal(got, im)
+
+
+@pytest.mark.parametrize("backend,int8", [("valu", False), ("mfma", False), ("mfma", True)])
+def test_wht_forward(batch_u8, backend, int8):
+    T = torch()
+    be = A().BACKEND_VALU if backend == "valu" else A().BACKEND_MFMA
+    plan = batch_u8.plan(coef_dtype=A().I32, backend=be, matrix=A().MATRIX_WHT,
+                         flags=A().FLAG_MFMA_INT8 if int8 else 0)
+    coef = batch_u8.coef_tensor(T.int32)
+    plan.forward(batch_u8.dev, coef)
+    T.cuda.synchronize()
+    for got, im in zip(batch_u8.split_coef(coef), batch_u8.images):
+        assert np.array_equal(got.astype(np.int64), codec.forward_image(im, tf.wht()))
+
+
+def test_wht_uniform_residual(batch_i16):
+    T = torch()
+    q = 16
+    plan = batch_i16.plan(coef_dtype=A().I32, qmode=A().Q_UNIFORM, q=q, qcoef_dtype=A().I16, out_dtype=A().I16,
+                          matrix=A().MATRIX_WHT)
+    out = batch_i16.empty_like_images(np.int16)
+    lv = batch_i16.coef_tensor(T.int16)
+    plan.compress_and_measure(batch_i16.dev, out, lv)
+    T.cuda.synchronize()
+    h16 = tf.wht()
+    for got, lvl, im in zip(batch_i16.unpack(out), batch_i16.split_coef(lv), batch_i16.images):
+        h, w = im.shape
+        want_lv = codec.quantise_uniform(codec.forward_image(im, h16), q, h16)
+        assert np.array_equal(lvl.astype(np.int64), want_lv)
+        real = codec.reconstruct_uniform(want_lv, q, h, w, rounded=False, t=h16)
+        _check_near_tie_rounding(got, real)

@@ -16,9 +16,14 @@ def _box_max(K, lo=-128, hi=127):
     return float(np.maximum(np.abs(mx), np.abs(mn)).max())
 
 
-def test_intermediate_ranges_all_masks():
-    T = tf.T.astype(np.float64)
-    w = tf.inverse_weights().astype(np.float64)
+import pytest
+
+
+@pytest.mark.parametrize("name,mat,umax_want,nmax_want", [("T", tf.T, 212544, 1648452),
+                                                       ("WHT", tf.wht(), 208464, 1327662)])
+def test_intermediate_ranges_all_masks(name, mat, umax_want, nmax_want):
+    T = mat.astype(np.float64)
+    w = tf.inverse_weights(mat).astype(np.float64)
     KP = np.einsum("fb,ia->ifab", T, np.eye(16))           # P = Xc T^T
     KZ = np.einsum("ua,vb->uvab", T, T)                    # Z = T Xc T^T
     assert _box_max(KP) <= 2048                            # fp16-exact
@@ -36,7 +41,14 @@ def test_intermediate_ranges_all_masks():
     # N 2^-11 (with the stage-4 partial sums) must stay below 1024 so that a
     # multiple of 2^-11 is exact in float32; N itself far below 2^24.
     assert nmax / 2048 + 96 < 1024 and nmax < 2**24
-    assert umax == 212544 and nmax == 1648452
+    assert umax == umax_want and nmax == nmax_want
+    # the final rounding below is proven for |N| <= 1648452
+    assert nmax <= 1648452
+    # collapsed products: G = T^T diag(w m) T is integer with |G| <= 68, so
+    # G 2^-11 is exact in fp16
+    for r in range(1, 17):
+        g = T.T @ np.diag(w * (np.arange(16) < r)) @ T
+        assert np.abs(g).max() <= 68 and np.array_equal(g, np.rint(g))
 
 
 def test_final_rounding_is_exact():

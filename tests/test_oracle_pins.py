@@ -163,6 +163,25 @@ def test_table2_wht_row():
         assert abs(got[k] - float(txt)) <= 0.5 * 10.0 ** (-dec) + 1e-12, k
 
 
+def test_wht_matrix_and_round_trip():
+    # Natural (Sylvester) order equals scipy's Hadamard; H H^T = 16 I, so
+    # S = I / 4 and every inverse weight is 3 (A' = 9 H^T Z H / 2304).
+    from scipy.linalg import hadamard
+    h = tf.wht()
+    assert np.array_equal(h, hadamard(16))
+    assert np.array_equal(h @ h.T, 16 * np.eye(16, dtype=np.int64))
+    assert np.array_equal(tf.inverse_weights(h), np.full(16, 3))
+    rng = np.random.default_rng(9)
+    a = rng.integers(0, 256, size=(32, 16, 16))
+    z = tf.forward_int(a, h)
+    assert np.array_equal(tf.inverse_int_numerator(z, h), 2304 * a)   # lossless
+    # the natural-order WHT coefficient (u, v) of a block is the sum of the
+    # pixels weighted by (-1)^(popcount(u & i) + popcount(v & j))
+    for u, v in ((0, 0), (3, 5), (15, 9)):
+        sgn = np.array([[(-1) ** (bin(u & i).count("1") + bin(v & j).count("1")) for j in range(16)] for i in range(16)])
+        assert np.array_equal(z[:, u, v], np.einsum("bij,ij->b", a, sgn))
+
+
 def test_dct_matrix_against_library():
     from scipy.fft import dct
     c = tf.dct_matrix()
