@@ -47,15 +47,18 @@ def _parse():
     return ap.parse_args()
 
 
-# Device-side sources of the fused kernels (host API code excluded).
-KERNEL_SOURCES = ["adct16_internal.hpp", "device_common.hpp", "kernels_mfma.hip", "kernels_valu.hip",
-                  "mfma_stages.hpp"]
+# Device-side sources each fused kernel is compiled from (host API code
+# excluded): counters taken on one kernel stay valid while these are unchanged.
+KERNEL_SOURCES = {
+    "k_mfma_fused": ["adct16_internal.hpp", "device_common.hpp", "kernels_mfma.hip", "mfma_stages.hpp"],
+    "k_fused": ["adct16_internal.hpp", "device_common.hpp", "kernels_valu.hip"],
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kernel_name: str) -> str:
     csrc = os.path.join(ROOT, "paper_1606_05562_amd", "csrc")
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel_name.split("<")[0]]:
         h.update(f.encode())
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
@@ -84,7 +87,7 @@ def _traffic(kernel_name: str):
             c = json.load(f)
     except OSError:
         return None
-    if c.get("source_sha256") != kernel_source_hash() or c.get("kernel") != kernel_name:
+    if c.get("source_sha256") != kernel_source_hash(kernel_name) or c.get("kernel") != kernel_name:
         return None
     copy_kib = c["copy_bytes"] / 1024.0
     fetch = c["fetch_kib"] * copy_kib / c["copy_fetch_kib"]
@@ -110,7 +113,8 @@ def _cpu_baseline(frames, keep_r, n):
 
 def _fused_kernel_name(plan_info):
     if plan_info["backend"] == "mfma":
-        return "k_mfma_fused<false, true, 1>"
+        nt = "true" if plan_info.get("rows_line_aligned") else "false"
+        return f"k_mfma_fused<false, true, 1, {nt}>"
     return "k_fused<0, 0, 5, 1>"
 
 
