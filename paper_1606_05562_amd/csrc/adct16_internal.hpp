@@ -100,6 +100,7 @@ struct Params {
 // Launchers (return hipSuccess or the launch error).  `grid` is the number
 // of workgroups of kGroupThreads threads for the persistent strip kernels.
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+hipError_t launch_fill_noise(void* p, int64_t bytes, bool i16, hipStream_t s);
 hipError_t launch_psnr_finalize(const Params& P, hipStream_t s);
 hipError_t launch_task_sse_reduce(const Params& P, hipStream_t s);
 hipError_t launch_valu_forward(int mat, int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s);

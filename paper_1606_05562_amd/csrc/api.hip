@@ -116,6 +116,10 @@ struct adct16_plan_s {
   int grid = 0;           // persistent workgroups for the strip kernels
   int backend = ADCT16_BACKEND_VALU;   // resolved backend of the fused/forward calls
   std::string tuned;      // how the choice was made
+  // Fused calls that also write the retained coefficients or levels run
+  // the vector kernel with its own launch shape.
+  int grid_lv = 0;
+  std::string tuned_lv;
 };
 
 struct adct16_graph_s {
@@ -187,15 +191,16 @@ bool mfma_supported(const adct16_plan_s* p) {
 }
 
 // Autotuning: time the fused call for each candidate (backend, workgroups
-// per CU) on a scratch batch of the plan's own geometry, keep the fastest.
+// per CU) on a scratch batch of the plan's own geometry filled with noise,
+// keep the fastest.
 // Results are cached per process and, if ADCT16_TUNE_CACHE names a file,
 // across processes (key: device arch, CU count, call shape, mask kind).
 std::mutex g_tune_mu;
 
-std::string tune_key(const adct16_plan_s* p, const char* arch) {
+std::string tune_key(const adct16_plan_s* p, const char* arch, bool levels) {
   std::ostringstream k;
   k << arch << "/cu" << p->cu_count << "/b" << p->d.backend << "/t" << p->mat << "/in" << p->in_kind << "/m" << p->mode << "/q" << p->d.qmode
-    << "/o" << p->out_kind << "/f" << (p->d.flags & ADCT16_FLAG_EXPLICIT_COEF)
+    << "/o" << p->out_kind << "/f" << (p->d.flags & ADCT16_FLAG_EXPLICIT_COEF) << "/lv" << (levels ? p->qcoef_kind : -1)
     << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips);
   return k.str();
 }
@@ -219,14 +224,19 @@ void tune_cache_put(const std::string& key, int backend, int wgpc) {
   f << key << " " << backend << " " << wgpc << "\n";
 }
 
-adct16_status autotune(adct16_plan_s* p, const char* arch) {
-  std::lock_guard<std::mutex> lock(g_tune_mu);
-  const std::string key = tune_key(p, arch);
-  int best_b = ADCT16_BACKEND_VALU, best_w = 2;
+int grid_for(const adct16_plan_s* p, int wgpc) {
+  return (int)std::min<int64_t>((int64_t)p->cu_count * wgpc, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup);
+}
+
+// Tunes one call shape: without (levels = false) or with the coefficient /
+// level output, whose stores change the kernel's best occupancy.
+adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& best_b, int& best_w,
+                         std::string& how) {
+  const std::string key = tune_key(p, arch, levels);
+  best_b = ADCT16_BACKEND_VALU;
+  best_w = 2;
   if (tune_cache_get(key, best_b, best_w)) {
-    p->backend = best_b;
-    p->grid = (int)std::min<int64_t>(p->cu_count * best_w, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup);
-    p->tuned = "cache";
+    how = "cache";
     return ADCT16_OK;
   }
   // Scratch input / output covering the packed batch extent.
@@ -234,9 +244,12 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
   for (size_t i = 0; i < p->images.size(); ++i)
     in_elems = std::max<int64_t>(in_elems, p->images[i].offset + (int64_t)p->images[i].h * p->images[i].pitch);
   const size_t bytes = (size_t)in_elems * esize(p->d.in_dtype);
+  const size_t qbytes = levels ? (size_t)p->n_blocks * 256 *
+                                     ((p->qcoef_kind == CF_I16C || p->qcoef_kind == CF_L16) ? 2 : 4)
+                               : 0;
   // Resources released on every exit.
   struct Scratch {
-    void *din = nullptr, *dout = nullptr;
+    void *din = nullptr, *dout = nullptr, *dq = nullptr;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ~Scratch() {
@@ -245,12 +258,14 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
       if (s) (void)hipStreamDestroy(s);
       if (din) (void)hipFree(din);
       if (dout) (void)hipFree(dout);
+      if (dq) (void)hipFree(dq);
     }
   } w;
-  if (hipMalloc(&w.din, bytes + 64) != hipSuccess || hipMalloc(&w.dout, bytes + 64) != hipSuccess)
+  if (hipMalloc(&w.din, bytes + 64) != hipSuccess || hipMalloc(&w.dout, bytes + 64) != hipSuccess ||
+      (levels && hipMalloc(&w.dq, qbytes) != hipSuccess))
     return fail(ADCT16_E_NOMEM, "autotune scratch");
-  hipError_t e = hipMemset(w.din, 0x5a, bytes);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking);
+  hipError_t e = hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = launch_fill_noise(w.din, (int64_t)bytes, p->in_kind == IN_I16, w.s);
   if (e == hipSuccess) e = hipEventCreate(&w.e0);
   if (e == hipSuccess) e = hipEventCreate(&w.e1);
   if (e != hipSuccess) return hip_fail(e, "autotune set-up");
@@ -260,21 +275,20 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
   struct Cand { int backend, wgpc, grid; float best; };
   std::vector<Cand> cands;
   std::vector<int> backends;
-  if (p->d.backend != ADCT16_BACKEND_MFMA) backends.push_back(ADCT16_BACKEND_VALU);
-  if (p->d.backend != ADCT16_BACKEND_VALU && mfma_supported(p)) backends.push_back(ADCT16_BACKEND_MFMA);
+  if (p->d.backend != ADCT16_BACKEND_MFMA || levels) backends.push_back(ADCT16_BACKEND_VALU);
+  if (!levels && p->d.backend != ADCT16_BACKEND_VALU && mfma_supported(p)) backends.push_back(ADCT16_BACKEND_MFMA);
   for (int b : backends)
-    for (int wg : {1, 2, 3, 4, 6, 8, 12})
-      cands.push_back({b, wg, (int)std::min<int64_t>(p->cu_count * wg, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup), 1e30f});
+    for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({b, wg, grid_for(p, wg), 1e30f});
   void* const tout = p->out_kind == OUT_F32 ? nullptr : w.dout;
   for (const Cand& c : cands) {  // warm-up (code objects, clocks)
-    adct16_status st = compress_impl(p, c.backend, c.grid, w.din, tout, nullptr, nullptr, nullptr, w.s);
+    adct16_status st = compress_impl(p, c.backend, c.grid, w.din, tout, w.dq, nullptr, nullptr, w.s);
     if (st != ADCT16_OK) return st;
   }
   for (int round = 0; round < 4; ++round) {
     for (Cand& c : cands) {
       e = hipEventRecord(w.e0, w.s);
       if (e != hipSuccess) return hip_fail(e, "autotune event");
-      adct16_status st = compress_impl(p, c.backend, c.grid, w.din, tout, nullptr, nullptr, nullptr, w.s);
+      adct16_status st = compress_impl(p, c.backend, c.grid, w.din, tout, w.dq, nullptr, nullptr, w.s);
       if (st != ADCT16_OK) return st;
       e = hipEventRecord(w.e1, w.s);
       if (e == hipSuccess) e = hipEventSynchronize(w.e1);
@@ -287,12 +301,23 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
   float best = 1e30f;
   for (const Cand& c : cands)
     if (c.best < best) { best = c.best; best_b = c.backend; best_w = c.wgpc; }
-  p->backend = best_b;
-  p->grid = (int)std::min<int64_t>(p->cu_count * best_w, (p->n_strips + kWavesPerGroup - 1) / kWavesPerGroup);
   std::ostringstream t;
   t << "timed:" << best_w << "wg/cu";
-  p->tuned = t.str();
+  how = t.str();
   tune_cache_put(key, best_b, best_w);
+  return ADCT16_OK;
+}
+
+adct16_status autotune(adct16_plan_s* p, const char* arch) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  int b, wg;
+  adct16_status st = tune_shape(p, arch, false, b, wg, p->tuned);
+  if (st != ADCT16_OK) return st;
+  p->backend = b;
+  p->grid = grid_for(p, wg);
+  st = tune_shape(p, arch, true, b, wg, p->tuned_lv);
+  if (st != ADCT16_OK) return st;
+  p->grid_lv = grid_for(p, wg);
   return ADCT16_OK;
 }
 
@@ -499,6 +524,8 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
     adct16_plan_destroy(p);
     return fail(ADCT16_E_MODE, "MFMA backend supports U8 input, retention modes and U8 output");
   }
+  p->grid_lv = p->grid;
+  p->tuned_lv = "default";
   if (d->flags & ADCT16_FLAG_AUTOTUNE) {
     // a requested backend restricts the search to its launch shapes
     adct16_status st = autotune(p, prop.gcnArchName);
@@ -544,7 +571,8 @@ adct16_status adct16_plan_info(adct16_plan p, char* buf, int32_t len) {
   o << "{\"backend\": \"" << (p->backend == ADCT16_BACKEND_MFMA ? "mfma" : "valu") << "\", \"grid\": " << p->grid
     << ", \"threads\": " << kGroupThreads << ", \"strips\": " << p->n_strips << ", \"blocks\": " << p->n_blocks
     << ", \"cus\": " << p->cu_count << ", \"rows_line_aligned\": " << (p->lines_aligned ? "true" : "false")
-    << ", \"choice\": \"" << p->tuned << "\"}";
+    << ", \"choice\": \"" << p->tuned << "\", \"levels_grid\": " << p->grid_lv
+    << ", \"levels_choice\": \"" << p->tuned_lv << "\"}";
   const std::string s = o.str();
   if ((int32_t)s.size() + 1 > len) return fail(ADCT16_E_SHAPE, "buffer too small (%d needed)", (int)s.size() + 1);
   memcpy(buf, s.c_str(), s.size() + 1);
@@ -663,6 +691,8 @@ adct16_status adct16_compress_and_measure(adct16_plan p, const void* d_in, void*
     return fail(ADCT16_E_ALIGN, "buffers must be 16-byte aligned");
   if (d_out && p->out_kind == OUT_F32)
     return fail(ADCT16_E_STATE, "the fused call writes rounded reconstructions (out_dtype U8 or I16)");
+  if (d_qcoef)
+    return compress_impl(p, ADCT16_BACKEND_VALU, p->grid_lv, d_in, d_out, d_qcoef, d_sse, d_psnr, (hipStream_t)stream);
   return compress_impl(p, p->backend, p->grid, d_in, d_out, d_qcoef, d_sse, d_psnr, (hipStream_t)stream);
 }
 
