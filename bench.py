@@ -35,7 +35,7 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["luma", "ragged", "residual", "rd", "sweep"], default="luma")
+    ap.add_argument("--workload", choices=["luma", "ragged", "residual", "rd", "sweep", "vector"], default="luma")
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--backend", choices=["auto", "valu", "mfma"], default="auto")
     ap.add_argument("--frames", type=int, default=None)
@@ -191,6 +191,14 @@ def bench_luma(args, A, torch):
                 f()
                 vms = _events_ms(f, max(3, args.steps // 2), stream)
                 v[f"fused_{name}_r{r}_gpix_s"] = round(npx / (vms * 1e-3) / 1e9, 4)
+        # the Walsh-Hadamard matrix through the same fused kernels
+        for name, be in (("valu", A.BACKEND_VALU), ("mfma", A.BACKEND_MFMA)):
+            p2 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32, qmode=A.Q_ZONAL,
+                        r=args.r, backend=be, flags=A.FLAG_AUTOTUNE, matrix=A.MATRIX_WHT)
+            f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)
+            f()
+            vms = _events_ms(f, max(3, args.steps // 2), stream)
+            v[f"fused_wht_{name}_r{args.r}_gpix_s"] = round(npx / (vms * 1e-3) / 1e9, 4)
         # Unfused pipeline through HBM: forward (int16 centred Z) -> retention
         # in place -> inverse -> measure.
         p3 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I16, qmode=A.Q_ZONAL,
@@ -407,6 +415,35 @@ def bench_sweep(args, A, torch):
                        "wall_s": round(wall, 2), "rows": rows}}
 
 
+def bench_vector(args, A, torch):
+    """The 1-D API: y = T x and y = T^T x over int32 vectors of 16 in device
+    memory (64 bytes read and 64 written per vector)."""
+    n = (args.frames or 32) << 20  # vectors
+    g = torch.Generator(device="cpu").manual_seed(2016)
+    x = torch.randint(-(1 << 20), 1 << 20, (n, 16), dtype=torch.int32, generator=g).cuda()
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, fn in (("forward", A.forward_1d), ("inverse", A.inverse_1d)):
+        f = lambda: fn(x, y)
+        for _ in range(args.warmup):
+            f()
+        ms = _events_ms(f, args.steps, stream)
+        out[name] = {"ms": round(ms, 4), "gvec_s": round(n / (ms * 1e-3) / 1e9, 4),
+                     "gbs": round(128 * n / (ms * 1e-3) / 1e9, 1)}
+    cms = _events_ms(lambda: y.copy_(x), args.steps, stream)
+    copy_gbs = 128 * n / (cms * 1e-3) / 1e9
+    fw = out["forward"]["gbs"]
+    return {"metric": "GB/s 1-D 16-point T x over int32 vectors (forward; inverse in config)",
+            "value": fw, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": out["forward"]["ms"], "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": f"{n} int32 vectors of 16 (uniform in [-2^20, 2^20)), {n * 64 / 2**30:.1f} GiB in",
+                       "vectors": n, "per_direction": out},
+            "roofline": {"bound": "hbm", "achieved": fw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(fw / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes": 128 * n,
+                         "copy_same_bytes_gbs": round(copy_gbs, 1), "frac_of_copy": round(fw / copy_gbs, 4)}}
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -417,7 +454,7 @@ def main():
 
     import paper_1606_05562_amd as A
     fn = {"luma": bench_luma, "ragged": bench_ragged, "residual": bench_residual, "rd": bench_rd,
-          "sweep": bench_sweep}[args.workload]
+          "sweep": bench_sweep, "vector": bench_vector}[args.workload]
     print(json.dumps(fn(args, A, torch)), flush=True)
 
 

@@ -844,20 +844,62 @@ __global__ __launch_bounds__(64) void k_task_sse_reduce(Params P) {
   }
 }
 
+// 1-D transforms of int32 vectors of 16.  A wavefront moves 64 vectors
+// (4 KB) per step: each load or store instruction covers 1 KB of
+// consecutive bytes (lane l, instruction m: bytes 1024 m + 16 l), and the
+// LDS regroups them so that each lane holds one whole vector (rows of 80
+// bytes, 16 of them padding, keep the accesses free of bank conflicts).
+// The data is streamed once, so the accesses are non-temporal.  Vectors
+// past the last whole group of 64 are taken one per lane by wavefront 0.
+typedef int v4i __attribute__((ext_vector_type(4)));
+
 template <bool INV>
-__global__ void k_1d(const int32_t* x, int32_t* y, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+__device__ __forceinline__ void t_1d(int (&v)[16]) {
+  if constexpr (INV) t_inv(v); else t_fwd(v);
+}
+
+template <bool INV>
+__global__ __launch_bounds__(256) void k_1d(const int32_t* __restrict__ x, int32_t* __restrict__ y, int64_t n) {
+  __shared__ v4i lds_all[kWavesPerGroup][64 * 5];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  v4i* L = lds_all[w];
+  const int64_t groups = n / 64;
+  for (int64_t c = (int64_t)blockIdx.x * kWavesPerGroup + w; c < groups; c += (int64_t)gridDim.x * kWavesPerGroup) {
+    const v4i* src = reinterpret_cast<const v4i*>(x) + c * 256;
+    v4i q[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) q[m] = __builtin_nontemporal_load(src + m * 64 + l);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) L[(m * 16 + (l >> 2)) * 5 + (l & 3)] = q[m];
+    wave_lds_sync();
     int v[16];
-    const int4* s = reinterpret_cast<const int4*>(x + i * 16);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const v4i t = L[l * 5 + k];
+      v[4 * k] = t.x; v[4 * k + 1] = t.y; v[4 * k + 2] = t.z; v[4 * k + 3] = t.w;
+    }
+    t_1d<INV>(v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L[l * 5 + k] = v4i{v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]};
+    wave_lds_sync();
+    v4i* dst = reinterpret_cast<v4i*>(y) + c * 256;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) __builtin_nontemporal_store(L[(m * 16 + (l >> 2)) * 5 + (l & 3)], dst + m * 64 + l);
+    wave_lds_sync();
+  }
+  const int64_t i = groups * 64 + l;
+  if (blockIdx.x == 0 && w == 0 && i < n) {
+    int v[16];
+    const int4* src = reinterpret_cast<const int4*>(x + i * 16);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const int4 q = s[m];
+      const int4 q = src[m];
       v[4 * m] = q.x; v[4 * m + 1] = q.y; v[4 * m + 2] = q.z; v[4 * m + 3] = q.w;
     }
-    if constexpr (INV) t_inv(v); else t_fwd(v);
-    int4* d = reinterpret_cast<int4*>(y + i * 16);
+    t_1d<INV>(v);
+    int4* dst = reinterpret_cast<int4*>(y + i * 16);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) d[m] = make_int4(v[4 * m], v[4 * m + 1], v[4 * m + 2], v[4 * m + 3]);
+    for (int m = 0; m < 4; ++m) dst[m] = make_int4(v[4 * m], v[4 * m + 1], v[4 * m + 2], v[4 * m + 3]);
   }
 }
 
@@ -1070,7 +1112,8 @@ hipError_t launch_rate(int level_kind, const Params& P, unsigned long long* bits
 }
 
 hipError_t launch_1d(bool inverse, const int32_t* x, int32_t* y, int64_t n, hipStream_t s) {
-  const int grid = (int)std::min<int64_t>((n + 255) / 256, 1 << 16);
+  const int64_t groups = n / 64;  // whole 64-vector groups, one per wavefront step
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kWavesPerGroup - 1) / kWavesPerGroup, 1 << 16));
   if (inverse) hipLaunchKernelGGL(k_1d<true>, dim3(grid), dim3(256), 0, s, x, y, n);
   else hipLaunchKernelGGL(k_1d<false>, dim3(grid), dim3(256), 0, s, x, y, n);
   return hipGetLastError();

@@ -390,10 +390,13 @@ def test_graph_replays_match_eager(batch_u8):
     g.close()
 
 
-def test_one_d_api():
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 10000])
+def test_one_d_api(n):
+    """Whole 64-vector groups go through the LDS-regrouped path, the rest
+    one per lane; both directions against the oracle's T."""
     T = torch()
-    rng = np.random.default_rng(3)
-    x = rng.integers(-100000, 100000, size=(10000, 16)).astype(np.int32)
+    rng = np.random.default_rng(3 + n)
+    x = rng.integers(-100000, 100000, size=(n, 16)).astype(np.int32)
     xd = T.from_numpy(x).cuda()
     y = T.empty_like(xd)
     A().forward_1d(xd, y)
@@ -403,6 +406,24 @@ def test_one_d_api():
     assert np.array_equal(y.cpu().numpy().astype(np.int64), x.astype(np.int64) @ tf.T.T)
     assert np.array_equal(yi.cpu().numpy().astype(np.int64), x.astype(np.int64) @ tf.T)
     A().forward_1d(xd[:0], y[:0])  # empty input is a no-op
+
+
+def test_one_d_api_large():
+    """More groups than the launch has wavefronts (each wavefront loops),
+    plus a ragged tail; sampled rows against the oracle's T."""
+    T = torch()
+    n = 64 * (4 << 16) + 64 * 3 + 5
+    g = T.Generator(device="cpu").manual_seed(77)
+    xd = T.randint(-(1 << 20), 1 << 20, (n, 16), dtype=T.int32, generator=g).cuda()
+    y = T.empty_like(xd)
+    A().forward_1d(xd, y)
+    T.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([np.arange(64), np.arange(n - 200, n), rng.integers(0, n, 20000)]))
+    idx = T.from_numpy(rows).cuda()
+    xs = xd[idx].cpu().numpy().astype(np.int64)
+    ys = y[idx].cpu().numpy().astype(np.int64)
+    assert np.array_equal(ys, xs @ tf.T.T)
 
 
 def test_random_blocks_worst_case():
