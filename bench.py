@@ -199,10 +199,10 @@ def bench_luma(args, A, torch):
             f()
             vms = _events_ms(f, max(3, args.steps // 2), stream)
             v[f"fused_wht_{name}_r{args.r}_gpix_s"] = round(npx / (vms * 1e-3) / 1e9, 4)
-        # Unfused pipeline through HBM: forward (int16 centred Z) -> retention
-        # in place -> inverse -> measure.
+        # Unfused pipeline through HBM: forward (int16 centred Z, matrix
+        # cores) -> retention in place -> inverse -> measure.
         p3 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I16, qmode=A.Q_ZONAL,
-                    r=args.r, backend=A.BACKEND_VALU)
+                    r=args.r, backend=A.BACKEND_MFMA)
         coef = torch.empty(p3.num_blocks * 256, dtype=torch.int16, device="cuda")
         stages = {"forward_u8_to_i16": (lambda: p3.forward(dev, coef), 3),
                   "quantise_i16_inplace": (lambda: p3.quantise(coef, coef), 4),

@@ -587,10 +587,13 @@ adct16_status adct16_forward(adct16_plan p, const void* d_in, void* d_coef, void
   P.in = d_in;
   P.coef = d_coef;
   hipError_t e;
-  if (p->backend == ADCT16_BACKEND_MFMA && p->coef_kind != CF_F32)
-    e = (p->d.flags & ADCT16_FLAG_MFMA_INT8) ? launch_mfma_forward_i8(p->coef_kind, P, p->grid, (hipStream_t)stream)
-                                             : launch_mfma_forward(p->coef_kind, P, p->grid, (hipStream_t)stream);
-  else
+  if (p->backend == ADCT16_BACKEND_MFMA && p->coef_kind != CF_F32) {
+    // whole-cache-line rows and block-aligned coefficients: streaming accesses
+    const bool nt = p->lines_aligned && (reinterpret_cast<uintptr_t>(d_in) & 127) == 0 &&
+                    (reinterpret_cast<uintptr_t>(d_coef) & 127) == 0;
+    e = (p->d.flags & ADCT16_FLAG_MFMA_INT8) ? launch_mfma_forward_i8(p->coef_kind, nt, P, p->grid, (hipStream_t)stream)
+                                             : launch_mfma_forward(p->coef_kind, nt, P, p->grid, (hipStream_t)stream);
+  } else
     e = launch_valu_forward(p->mat, p->in_kind, p->coef_kind, P, p->grid, (hipStream_t)stream);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "forward kernel");
 }

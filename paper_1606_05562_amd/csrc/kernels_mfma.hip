@@ -147,6 +147,7 @@ __device__ __forceinline__ void st_row16(uint8_t* p, const uint4& v) {
 struct ImgGeom {
   int64_t offset;
   int32_t h, w, pitch, bx, sx;
+  int64_t block_begin;
 };
 
 // One dword of block row q (columns 4g..4g+3), edge-extended.
@@ -197,13 +198,13 @@ __device__ __forceinline__ void edge_strip(const ImgGeom& d, int sy, int sxi, co
 // with one set of vector loads; the task in use is read back with readlane.
 // The table latency is paid once per 64 tasks instead of once per task.
 struct TaskRegs {
-  int sy, sx0, off_lo, off_hi, h, w, pitch, bx, sx;
+  int sy, sx0, off_lo, off_hi, h, w, pitch, bx, sx, bb_lo, bb_hi;
 };
 
 __device__ __forceinline__ TaskRegs gather_tasks(const ImageDesc* __restrict__ images,
                                                  const RowTask* __restrict__ rows, int64_t t0, int64_t W,
                                                  int64_t n, int lane) {
-  TaskRegs tr = {0, 0, 0, 0, 1, 1, 0, 0, 1};
+  TaskRegs tr = {0, 0, 0, 0, 1, 1, 0, 0, 1, 0, 0};
   const int64_t tk = t0 + (int64_t)lane * W;
   if (tk < n) {
     const RowTask e = rows[tk];
@@ -218,6 +219,9 @@ __device__ __forceinline__ TaskRegs gather_tasks(const ImageDesc* __restrict__ i
     tr.pitch = d->pitch;
     tr.bx = d->bx;
     tr.sx = d->sx;
+    const int64_t bb = d->block_begin;
+    tr.bb_lo = (int)(uint32_t)bb;
+    tr.bb_hi = (int)(bb >> 32);
   }
   // complete the gather here, so that reading a task (every few strips)
   // never waits on memory; vmcnt(0), other counters unchanged
@@ -234,6 +238,8 @@ __device__ __forceinline__ ImgGeom task_geom(const TaskRegs& tr, int k) {
   m.pitch = __builtin_amdgcn_readlane(tr.pitch, k);
   m.bx = __builtin_amdgcn_readlane(tr.bx, k);
   m.sx = __builtin_amdgcn_readlane(tr.sx, k);
+  m.block_begin = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(tr.bb_hi, k) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane(tr.bb_lo, k));
   return m;
 }
 
@@ -367,50 +373,6 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   }
 }
 
-// Forward only: Z (int32) or the centred int16 form, block-major.  Stage 2
-// runs transposed (Z^T = P^T T^T) so that each lane ends with four
-// consecutive coefficients of one row: Z[q][4g..4g+3].
-template <int CF>
-__global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P) {
-  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
-  const MfmaConsts k = make_consts(q, g, 16, P.tables);
-  const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
-  StripCursor c;
-  if (!cursor_init(c, P)) return;
-  do {
-    const int y = min(c.sy * 16 + q, c.d.h - 1);
-    const int b0 = c.sxi * kStripBlocks;
-    const int nb = min(kStripBlocks, c.d.bx - b0);
-    const int64_t rowblk = c.d.block_begin + (int64_t)c.sy * c.d.bx + b0;
-    unsigned x[kStripBlocks];
-#pragma unroll
-    for (int b = 0; b < kStripBlocks; ++b)
-      x[b] = b < nb ? load_dword_u8(in, c.d, y, (b0 + b) * 16 + 4 * g) : 0u;
-#pragma unroll
-    for (int b = 0; b < kStripBlocks; ++b) {
-      if (b < nb) {
-        const f4 c1 = {k.c1, k.c1, k.c1, k.c1};
-        const f4 p = mma16(bytes_to_h4(x[b]), k.tq, c1);
-        const uint2 ph = make_uint2(pack_h(p[0], p[1]), pack_h(p[2], p[3]));
-        const f4 zero = {0, 0, 0, 0};
-        const f4 zt = mma16(ph, k.tq, zero);  // Z_c[q][4g+v]
-        int z[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) z[v] = (int)zt[v];
-        const int64_t base = (rowblk + b) * 256 + q * 16 + 4 * g;
-        if constexpr (CF == CF_I32) {
-          if (q == 0 && g == 0) z[0] += 32768;  // undo the centring at (0, 0)
-          *reinterpret_cast<int4*>(reinterpret_cast<int*>(P.coef) + base) = make_int4(z[0], z[1], z[2], z[3]);
-        } else {
-          const unsigned lo = ((unsigned)z[0] & 0xffffu) | ((unsigned)z[1] << 16);
-          const unsigned hi = ((unsigned)z[2] & 0xffffu) | ((unsigned)z[3] << 16);
-          *reinterpret_cast<uint2*>(reinterpret_cast<int16_t*>(P.coef) + base) = make_uint2(lo, hi);
-        }
-      }
-    }
-  } while (cursor_next(c, P), c.s < c.s_end);
-}
-
 // ---------------------------------------------------------------------------
 // Forward transform as int8 products with int32 accumulation (exact: every
 // operand is a small integer and int32 sums do not round).
@@ -448,53 +410,205 @@ __device__ __forceinline__ unsigned t_bytes(const signed char* tm, int row, int 
   return r;
 }
 
-template <int CF>
-__global__ __launch_bounds__(kGroupThreads) void k_mfma_forward_i8(Params P) {
-  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
-  // stage-1 B: T[q][8g..8g+7] for g < 2 (K = image column), zero otherwise
-  const signed char* tm = P.tables->tmat;
-  const uint2 b1 = g < 2 ? make_uint2(t_bytes(tm, q, 8 * g), t_bytes(tm, q, 8 * g + 4)) : make_uint2(0u, 0u);
-  // stage-2 B: column u = q; slots j < 4: T[q][4g + j], slots j >= 4: 64 T[q][4g + j - 4]
-  const uint2 b2 = make_uint2(t_bytes(tm, q, 4 * g), t_bytes(tm, q, 4 * g, 64));
-  const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
-  StripCursor c;
-  if (!cursor_init(c, P)) return;
-  do {
-    const int y = min(c.sy * 16 + q, c.d.h - 1);
-    const int b0 = c.sxi * kStripBlocks;
-    const int nb = min(kStripBlocks, c.d.bx - b0);
-    const int64_t rowblk = c.d.block_begin + (int64_t)c.sy * c.d.bx + b0;
-    uint2 x[kStripBlocks];
+// ---------------------------------------------------------------------------
+// Forward only: Z (int32) or the centred int16 form, block-major, in the
+// FP16 form (stages 1 and 2 above, stage 2 transposed: Z^T = P^T T^T) or
+// the int8 form.  Either way lane 16g + q ends with Z[q][4g..4g+3] of each
+// block, so one store instruction writes a whole block (1 KB of int32 or
+// 512 B of int16) contiguously.  Strips are read and scheduled as in the
+// fused kernel: 8 rows x 128 bytes per load instruction, regrouped through
+// LDS, tasks dealt out cyclically, rows loaded a strip ahead.
+enum FwdForm { FWD_F16 = 0, FWD_I8 = 1 };
+
+// Int8 operands: lanes 16g + q with g < 2 take dwords 2g and 2g + 1 of row
+// q of every block (8 bytes of the K = 32 slots), the others zero.
+__device__ __forceinline__ void rows_to_operands_i8(int* lds, int r, int c, int g, int q, const uint4 (&rows)[2],
+                                                    uint2 (&x)[kStripBlocks]) {
 #pragma unroll
-    for (int b = 0; b < kStripBlocks; ++b) {
-      x[b] = make_uint2(0u, 0u);
-      if (g < 2 && b < nb) {
-        const int x0 = (b0 + b) * 16 + 8 * g;
-        x[b] = make_uint2(load_dword_u8(in, c.d, y, x0) ^ 0x80808080u, load_dword_u8(in, c.d, y, x0 + 4) ^ 0x80808080u);
+  for (int h = 0; h < 2; ++h) {
+    const int o = (8 * h + r) * kStripBlocks + c;
+    lds[o] = (int)rows[h].x;
+    lds[128 + o] = (int)rows[h].y;
+    lds[256 + o] = (int)rows[h].z;
+    lds[384 + o] = (int)rows[h].w;
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int b = 0; b < kStripBlocks; ++b) x[b] = make_uint2(0u, 0u);
+  if (g < 2) {
+    const int4* p0 = reinterpret_cast<const int4*>(lds + (2 * g) * 128 + q * kStripBlocks);
+    const int4* p1 = reinterpret_cast<const int4*>(lds + (2 * g + 1) * 128 + q * kStripBlocks);
+    const int4 a0 = p0[0], a1 = p0[1], c0 = p1[0], c1 = p1[1];
+    const int lo[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+    const int hi[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+#pragma unroll
+    for (int b = 0; b < kStripBlocks; ++b) x[b] = make_uint2((unsigned)lo[b], (unsigned)hi[b]);
+  }
+  wave_lds_sync();
+}
+
+struct FwdConsts {
+  MfmaConsts k;  // FP16 form
+  uint2 b1, b2;  // int8 form: stage-1 and stage-2 B operands
+};
+
+template <int FORM>
+__device__ __forceinline__ FwdConsts fwd_consts(int q, int g, const Tables* tb) {
+  FwdConsts f;
+  if constexpr (FORM == FWD_F16) {
+    f.k = make_consts(q, g, 16, tb);
+  } else {
+    // stage-1 B: T[q][8g..8g+7] for g < 2 (K = image column), zero otherwise;
+    // stage-2 B: column u = q; slots j < 4: T[q][4g + j], slots j >= 4: 64 T[q][4g + j - 4]
+    const signed char* tm = tb->tmat;
+    f.b1 = g < 2 ? make_uint2(t_bytes(tm, q, 8 * g), t_bytes(tm, q, 8 * g + 4)) : make_uint2(0u, 0u);
+    f.b2 = make_uint2(t_bytes(tm, q, 4 * g), t_bytes(tm, q, 4 * g, 64));
+  }
+  return f;
+}
+
+// Z[q][4g..4g+3] of one block from its operand (FP16 form: dword g of row q;
+// int8 form: the raw bytes, centred here).
+template <int FORM, int CF>
+__device__ __forceinline__ int4 fwd_z(unsigned x, uint2 xi, const FwdConsts& f, int q, int g) {
+  if constexpr (FORM == FWD_F16) {
+    const f4 c1 = {f.k.c1, f.k.c1, f.k.c1, f.k.c1};
+    const f4 p = mma16(bytes_to_h4(x), f.k.tq, c1);  // P_c[4g+v][q]
+    const uint2 ph = make_uint2(pack_h(p[0], p[1]), pack_h(p[2], p[3]));
+    const f4 zero = {0, 0, 0, 0};
+    const f4 zt = mma16(ph, f.k.tq, zero);  // Z_c[q][4g+v]
+    int4 z = make_int4((int)zt[0], (int)zt[1], (int)zt[2], (int)zt[3]);
+    if (CF == CF_I32 && q == 0 && g == 0) z.x += 32768;  // undo the centring at (0, 0)
+    return z;
+  } else {
+    const uint2 xc = g < 2 ? make_uint2(xi.x ^ 0x80808080u, xi.y ^ 0x80808080u) : make_uint2(0u, 0u);
+    const i4v zero = {0, 0, 0, 0};
+    const i4v p = mma_i8(xc, f.b1, zero);  // P[4g+v][q]
+    const uint2 digits = make_uint2(pack_low_bytes(p[0], p[1], p[2], p[3]) & 0x3f3f3f3fu,
+                                    pack_low_bytes(p[0] >> 6, p[1] >> 6, p[2] >> 6, p[3] >> 6));
+    i4v init = {0, 0, 0, 0};
+    if (CF == CF_I32 && q == 0 && g == 0) init[0] = 32768;
+    const i4v z = mma_i8(digits, f.b2, init);  // Z[q][4g+v]
+    return make_int4(z[0], z[1], z[2], z[3]);
+  }
+}
+
+template <int CF, bool NT>
+__device__ __forceinline__ void store_z(void* coef, int64_t blk, int q, int g, int4 z) {
+  const int64_t base = blk * 256 + q * 16 + 4 * g;
+  if constexpr (CF == CF_I32) {
+    v4u* p = reinterpret_cast<v4u*>(reinterpret_cast<int*>(coef) + base);
+    const v4u v = {(unsigned)z.x, (unsigned)z.y, (unsigned)z.z, (unsigned)z.w};
+    if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+  } else {
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    v2u* p = reinterpret_cast<v2u*>(reinterpret_cast<int16_t*>(coef) + base);
+    const v2u v = {((unsigned)z.x & 0xffffu) | ((unsigned)z.y << 16), ((unsigned)z.z & 0xffffu) | ((unsigned)z.w << 16)};
+    if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+  }
+}
+
+template <int FORM, int CF, bool NT>
+__global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P, const ImageDesc* __restrict__ images,
+                                                                const RowTask* __restrict__ rows) {
+  __shared__ int lds_all[kWavesPerGroup * 512];
+  int* lds = lds_all + (threadIdx.x >> 6) * 512;
+  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4, r = lane >> 3, c = lane & 7;
+  const FwdConsts f = fwd_consts<FORM>(q, g, P.tables);
+  const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
+  const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
+  int64_t t0 = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
+  if (t0 >= P.n_rows) return;
+  TaskRegs tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
+  int kk = 0;
+  int sy = __builtin_amdgcn_readlane(tr.sy, 0);
+  int sxi = __builtin_amdgcn_readlane(tr.sx0, 0);
+  ImgGeom d = task_geom(tr, 0);
+  int sxe = min(sxi + kTaskStrips, d.sx);
+  auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
+    return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
+  };
+  auto lane_off = [&](const ImgGeom& dd, int ssy, int ssxi) {
+    return dd.offset + (int64_t)(ssy * 16 + r) * dd.pitch + ssxi * (16 * kStripBlocks) + 16 * c;
+  };
+  uint4 nr[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+  if (interior(d, sy, sxi)) {
+    const int64_t o = lane_off(d, sy, sxi);
+    nr[0] = ld_row16<NT>(in + o);
+    nr[1] = ld_row16<NT>(in + o + 8 * (int64_t)d.pitch);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters unchanged
+  }
+  for (;;) {
+    const bool task_end = sxi + 1 == sxe;
+    int nsy = sy, nsxi = sxi + 1, nsxe = sxe;
+    ImgGeom nd = d;
+    bool more = true;
+    if (task_end) {
+      if (++kk == 64) {
+        kk = 0;
+        t0 += 64 * W;
+        tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
+      }
+      more = t0 + kk * W < P.n_rows;
+      if (more) {
+        nsy = __builtin_amdgcn_readlane(tr.sy, kk);
+        nsxi = __builtin_amdgcn_readlane(tr.sx0, kk);
+        nd = task_geom(tr, kk);
+        nsxe = min(nsxi + kTaskStrips, nd.sx);
       }
     }
+    const uint4 cr[2] = {nr[0], nr[1]};
+    auto prefetch = [&]() {
+      if (more && interior(nd, nsy, nsxi)) {
+        const int64_t o = lane_off(nd, nsy, nsxi);
+        nr[0] = ld_row16<NT>(in + o);
+        nr[1] = ld_row16<NT>(in + o + 8 * (int64_t)nd.pitch);
+      }
+    };
+    const int64_t rowblk = d.block_begin + (int64_t)sy * d.bx + sxi * kStripBlocks;
+    if (interior(d, sy, sxi)) {
+      prefetch();
+      unsigned x[kStripBlocks] = {};
+      uint2 xi[kStripBlocks] = {};
+      if constexpr (FORM == FWD_F16) rows_to_operands(lds, r, c, g, q, cr, x);
+      else rows_to_operands_i8(lds, r, c, g, q, cr, xi);
 #pragma unroll
-    for (int b = 0; b < kStripBlocks; ++b) {
-      if (b < nb) {
-        const i4v zero = {0, 0, 0, 0};
-        const i4v p = mma_i8(x[b], b1, zero);  // P[4g+v][q]
-        const uint2 digits = make_uint2(pack_low_bytes(p[0], p[1], p[2], p[3]) & 0x3f3f3f3fu,
-                                        pack_low_bytes(p[0] >> 6, p[1] >> 6, p[2] >> 6, p[3] >> 6));
-        i4v init = {0, 0, 0, 0};
-        if constexpr (CF == CF_I32)
-          if (q == 0 && g == 0) init[0] = 32768;
-        const i4v z = mma_i8(digits, b2, init);  // Z[q][4g+v]
-        const int64_t base = (rowblk + b) * 256 + q * 16 + 4 * g;
-        if constexpr (CF == CF_I32) {
-          *reinterpret_cast<int4*>(reinterpret_cast<int*>(P.coef) + base) = make_int4(z[0], z[1], z[2], z[3]);
-        } else {
-          const unsigned lo = ((unsigned)z[0] & 0xffffu) | ((unsigned)z[1] << 16);
-          const unsigned hi = ((unsigned)z[2] & 0xffffu) | ((unsigned)z[3] << 16);
-          *reinterpret_cast<uint2*>(reinterpret_cast<int16_t*>(P.coef) + base) = make_uint2(lo, hi);
+      for (int b = 0; b < kStripBlocks; ++b) store_z<CF, NT>(P.coef, rowblk + b, q, g, fwd_z<FORM, CF>(x[b], xi[b], f, q, g));
+      // the prefetched rows were issued before the 8 stores: wait for
+      // everything but the stores (vmcnt(8))
+      __builtin_amdgcn_s_waitcnt(0x0F78);
+    } else {
+      prefetch();
+      // edge strip: dword loads, the last column / row repeated
+      const int y = min(sy * 16 + q, d.h - 1);
+      const int b0 = sxi * kStripBlocks;
+      const int nb = min(kStripBlocks, d.bx - b0);
+      unsigned x[kStripBlocks];
+      uint2 xi[kStripBlocks];
+#pragma unroll
+      for (int b = 0; b < kStripBlocks; ++b) {
+        x[b] = 0u;
+        xi[b] = make_uint2(0u, 0u);
+        if (b < nb) {
+          if constexpr (FORM == FWD_F16) {
+            x[b] = load_dword_edge(in, d, y, (b0 + b) * 16 + 4 * g);
+          } else if (g < 2) {
+            const int x0 = (b0 + b) * 16 + 8 * g;
+            xi[b] = make_uint2(load_dword_edge(in, d, y, x0), load_dword_edge(in, d, y, x0 + 4));
+          }
         }
       }
+#pragma unroll
+      for (int b = 0; b < kStripBlocks; ++b)
+        if (b < nb) store_z<CF, false>(P.coef, rowblk + b, q, g, fwd_z<FORM, CF>(x[b], xi[b], f, q, g));
+      __builtin_amdgcn_s_waitcnt(0x0F70);
     }
-  } while (cursor_next(c, P), c.s < c.s_end);
+    if (!more) break;
+    sy = nsy;
+    sxi = nsxi;
+    sxe = nsxe;
+    d = nd;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -567,16 +681,21 @@ __global__ __launch_bounds__(kGroupThreads) void k_dct(Params P, float* Y) {
     return hipGetLastError();                                                          \
   } while (0)
 
-hipError_t launch_mfma_forward_i8(int coef_kind, const Params& P, int grid, hipStream_t s) {
-  if (coef_kind == CF_I32) ADCT16_MLAUNCH((k_mfma_forward_i8<CF_I32>), grid, s, P);
-  if (coef_kind == CF_I16C) ADCT16_MLAUNCH((k_mfma_forward_i8<CF_I16C>), grid, s, P);
+template <int FORM, bool NT>
+static hipError_t launch_mfma_forward_form(int coef_kind, const Params& P, int grid, hipStream_t s) {
+  if (coef_kind == CF_I32) ADCT16_MLAUNCH((k_mfma_forward<FORM, CF_I32, NT>), grid, s, P, P.images, P.rows);
+  if (coef_kind == CF_I16C) ADCT16_MLAUNCH((k_mfma_forward<FORM, CF_I16C, NT>), grid, s, P, P.images, P.rows);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma_forward(int coef_kind, const Params& P, int grid, hipStream_t s) {
-  if (coef_kind == CF_I32) ADCT16_MLAUNCH((k_mfma_forward<CF_I32>), grid, s, P);
-  if (coef_kind == CF_I16C) ADCT16_MLAUNCH((k_mfma_forward<CF_I16C>), grid, s, P);
-  return hipErrorInvalidValue;
+hipError_t launch_mfma_forward_i8(int coef_kind, bool nt, const Params& P, int grid, hipStream_t s) {
+  return nt ? launch_mfma_forward_form<FWD_I8, true>(coef_kind, P, grid, s)
+            : launch_mfma_forward_form<FWD_I8, false>(coef_kind, P, grid, s);
+}
+
+hipError_t launch_mfma_forward(int coef_kind, bool nt, const Params& P, int grid, hipStream_t s) {
+  return nt ? launch_mfma_forward_form<FWD_F16, true>(coef_kind, P, grid, s)
+            : launch_mfma_forward_form<FWD_F16, false>(coef_kind, P, grid, s);
 }
 
 template <bool NT>
