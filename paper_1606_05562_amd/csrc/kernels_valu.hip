@@ -283,49 +283,89 @@ __device__ __forceinline__ void store_row_i16(int16_t* img, int64_t off, int n, 
 }
 
 // ---------------------------------------------------------------------------
-// Coefficient stores / loads in the column layout (block-major buffers).
+// Block-major coefficient buffers (256 values per block, [u][v]) to and
+// from the column layout, through the transposition buffer: lane group p
+// puts its column-layout values of one block into slot p, and each global
+// access instruction then moves one whole block from row chunks (lane l:
+// row l / 4, columns 4 (l % 4) .. + 3), 1 KB of 32-bit or 512 B of 16-bit
+// values contiguously.  `first` is the block held by lane group 0 and `nb`
+// how many of the four (consecutive) blocks exist; both are the same for
+// the whole wavefront.  32-bit kinds: CF_I32, CF_L32 and CF_F32 (float
+// bits); 16-bit: CF_I16C (DC centred by -32768) and CF_L16 (saturated).
 template <int CF>
-__device__ __forceinline__ void store_col(void* buf, int64_t blk, int x, const int (&z)[16]) {
-  if constexpr (CF == CF_I32 || CF == CF_L32) {
-    int* d = reinterpret_cast<int*>(buf) + blk * 256 + x;
+__device__ __forceinline__ void store_blocks(void* buf, int* lds, int p, int x, int lane, int64_t first, int nb,
+                                             const int (&z)[16]) {
+  lds_put_col(lds, p, x, z);
+  wave_lds_sync();
+  const int u = lane >> 2, j = lane & 3;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) d[u * 16] = z[u];
-  } else if constexpr (CF == CF_I16C) {
-    int16_t* d = reinterpret_cast<int16_t*>(buf) + blk * 256 + x;
+  for (int m = 0; m < 4; ++m) {
+    if (m < nb) {
+      int4 v = *reinterpret_cast<const int4*>(lds + m * kSlot + u * kRow + 4 * j);
+      const int64_t off = (first + m) * 256 + u * 16 + 4 * j;
+      if constexpr (CF == CF_I32 || CF == CF_L32 || CF == CF_F32) {
+        *reinterpret_cast<int4*>(reinterpret_cast<int*>(buf) + off) = v;
+      } else {
+        if constexpr (CF == CF_I16C) {
+          if (lane == 0) v.x -= 32768;
+        } else {
+          v = make_int4(sat16(v.x), sat16(v.y), sat16(v.z), sat16(v.w));
+        }
+        *reinterpret_cast<uint2*>(reinterpret_cast<int16_t*>(buf) + off) =
+            make_uint2(((unsigned)v.x & 0xffffu) | ((unsigned)v.y << 16), ((unsigned)v.z & 0xffffu) | ((unsigned)v.w << 16));
+      }
+    }
+  }
+  wave_lds_sync();
+}
+
+// The converse, in two steps so that the loads of the next strip can be in
+// flight while this one is computed: fetch_blocks issues the loads (zeros
+// where a block does not exist), blocks_to_cols regroups them into column
+// x of the lane group's block.
+// The loads are unconditional (a missing block reads block `safe`, which
+// exists, and is zeroed afterwards): loads under a branch would each be
+// waited for before the branch joins.
+template <int CF>
+__device__ __forceinline__ void fetch_blocks(const void* buf, int lane, int64_t first, int nb, int64_t safe,
+                                             int4 (&v)[4]) {
+  const int u = lane >> 2, j = lane & 3;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) d[u * 16] = (int16_t)((u == 0 && x == 0) ? z[u] - 32768 : z[u]);
-  } else if constexpr (CF == CF_L16) {
-    int16_t* d = reinterpret_cast<int16_t*>(buf) + blk * 256 + x;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) d[u * 16] = (int16_t)sat16(z[u]);
+  for (int m = 0; m < 4; ++m) {
+    const int64_t off = (m < nb ? first + m : safe) * 256 + u * 16 + 4 * j;
+    int4 t;
+    if constexpr (CF == CF_I32 || CF == CF_L32) {
+      t = *reinterpret_cast<const int4*>(reinterpret_cast<const int*>(buf) + off);
+    } else {
+      const uint2 w = *reinterpret_cast<const uint2*>(reinterpret_cast<const int16_t*>(buf) + off);
+      t = make_int4((int)(short)(w.x & 0xffffu), ((int)w.x) >> 16, (int)(short)(w.y & 0xffffu), ((int)w.y) >> 16);
+      if constexpr (CF == CF_I16C) {
+        if (lane == 0) t.x += 32768;
+      }
+    }
+    v[m] = m < nb ? t : make_int4(0, 0, 0, 0);
   }
 }
 
-template <int CF>
-__device__ __forceinline__ void load_col(const void* buf, int64_t blk, int x, bool ok, int (&z)[16]) {
-  if (!ok) {
+__device__ __forceinline__ void blocks_to_cols(int* lds, int p, int x, int lane, const int4 (&v)[4], int (&z)[16]) {
+  const int u = lane >> 2, j = lane & 3;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) z[u] = 0;
-    return;
-  }
-  if constexpr (CF == CF_I32 || CF == CF_L32) {
-    const int* s = reinterpret_cast<const int*>(buf) + blk * 256 + x;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) z[u] = s[u * 16];
-  } else {
-    const int16_t* s = reinterpret_cast<const int16_t*>(buf) + blk * 256 + x;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) z[u] = s[u * 16];
-    if constexpr (CF == CF_I16C) z[0] += (x == 0) ? 32768 : 0;
-  }
+  for (int m = 0; m < 4; ++m) *reinterpret_cast<int4*>(lds + m * kSlot + u * kRow + 4 * j) = v[m];
+  wave_lds_sync();
+  lds_get_col(lds, p, x, z);
+  wave_lds_sync();
 }
+
+// Blocks of the strip's lane-group halves: a = blocks 0..3, b = 4..7.
+__device__ __forceinline__ int blocks_a(const StripCursor& c) { return min(4, max(0, c.d.bx - c.sxi * kStripBlocks)); }
+__device__ __forceinline__ int blocks_b(const StripCursor& c) { return min(4, max(0, c.d.bx - c.sxi * kStripBlocks - 4)); }
 
 // ---------------------------------------------------------------------------
 // Kernels.
 
 template <int MAT, int IN, int CF>
 __global__ __launch_bounds__(kGroupThreads) void k_forward(Params P) {
-  __shared__ int lds_all[kWavesPerGroup * kWaveLds];
+  __shared__ __attribute__((aligned(16))) int lds_all[kWavesPerGroup * kWaveLds];
   int* lds = lds_all + (threadIdx.x >> 6) * kWaveLds;
   const int lane = threadIdx.x & 63, x = lane & 15, p = lane >> 4;
   float ysc[16];
@@ -342,34 +382,19 @@ __global__ __launch_bounds__(kGroupThreads) void k_forward(Params P) {
       uint4 ra, rb;
       us2 Z[16];
       forward_u8<MAT>(reinterpret_cast<const uint8_t*>(P.in), g, lds, x, p, ra, rb, Z);
-      if constexpr (CF == CF_I16C) {
-        // Residues are the int16 bit patterns of the centred coefficients,
-        // except DC: flipping bit 15 subtracts 32768 modulo 2^16.
-        int16_t* d = reinterpret_cast<int16_t*>(P.coef);
-        if (x == 0) Z[0] = as_us2(as_u32(Z[0]) ^ 0x80008000u);
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const unsigned w = as_u32(Z[u]);
-          if (g.na > 0) d[g.blka * 256 + u * 16 + x] = (int16_t)(w & 0xffffu);
-          if (g.nb > 0) d[g.blkb * 256 + u * 16 + x] = (int16_t)(w >> 16);
-        }
-        continue;
-      }
       widen_u8(Z, x, za, zb);
     } else {
       forward_i16<MAT>(reinterpret_cast<const int16_t*>(P.in), g, lds, x, p, za, zb);
     }
-    if constexpr (CF == CF_I32) {
-      if (g.na > 0) store_col<CF_I32>(P.coef, g.blka, x, za);
-      if (g.nb > 0) store_col<CF_I32>(P.coef, g.blkb, x, zb);
-    } else if constexpr (CF == CF_F32) {
-      float* d = reinterpret_cast<float*>(P.coef);
+    if constexpr (CF == CF_F32) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        if (g.na > 0) d[g.blka * 256 + u * 16 + x] = (float)za[u] * ysc[u];
-        if (g.nb > 0) d[g.blkb * 256 + u * 16 + x] = (float)zb[u] * ysc[u];
+        za[u] = __float_as_int((float)za[u] * ysc[u]);
+        zb[u] = __float_as_int((float)zb[u] * ysc[u]);
       }
     }
+    store_blocks<CF>(P.coef, lds, p, x, lane, g.blka - p, blocks_a(c), za);
+    store_blocks<CF>(P.coef, lds, p, x, lane, g.blkb - p, blocks_b(c), zb);
   } while (cursor_next(c, P), c.s < c.s_end);
 }
 
@@ -449,8 +474,8 @@ __device__ __forceinline__ void dequant_inverse_block(int* lds, int x, int p, co
 // return the rounded reconstruction pixels.  |A'| stays far inside the
 // int32 range (within 8 q of the 16-bit input), so the conversion is exact.
 template <int MAT, int IN, int MODE, int QOUT, int OUT>
-__device__ __forceinline__ void quant_and_inverse(const Params& P, const LaneGeom& g, int* lds, int x,
-                                                  int p, const int (&W)[16], const QuantLane& ql,
+__device__ __forceinline__ void quant_and_inverse(const Params& P, const LaneGeom& g, int nba, int nbb, int* lds,
+                                                  int x, int p, int lane, const int (&W)[16], const QuantLane& ql,
                                                   int (&za)[16], int (&zb)[16], int (&oa)[16],
                                                   int (&ob)[16]) {
   if constexpr (MODE == MODE_MASK) {
@@ -461,8 +486,8 @@ __device__ __forceinline__ void quant_and_inverse(const Params& P, const LaneGeo
         ka[u] = W[u] ? za[u] : 0;
         kb[u] = W[u] ? zb[u] : 0;
       }
-      if (g.na > 0) store_col<QOUT>(P.qcoef, g.blka, x, ka);
-      if (g.nb > 0) store_col<QOUT>(P.qcoef, g.blkb, x, kb);
+      store_blocks<QOUT>(P.qcoef, lds, p, x, lane, g.blka - p, nba, ka);
+      store_blocks<QOUT>(P.qcoef, lds, p, x, lane, g.blkb - p, nbb, kb);
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -480,8 +505,8 @@ __device__ __forceinline__ void quant_and_inverse(const Params& P, const LaneGeo
       zb[u] = level_of<MODE>(zb[u], ql.m[norm_class<MAT>(u)], f);
     }
     if constexpr (QOUT != CF_NONE) {
-      if (g.na > 0) store_col<QOUT>(P.qcoef, g.blka, x, za);
-      if (g.nb > 0) store_col<QOUT>(P.qcoef, g.blkb, x, zb);
+      store_blocks<QOUT>(P.qcoef, lds, p, x, lane, g.blka - p, nba, za);
+      store_blocks<QOUT>(P.qcoef, lds, p, x, lane, g.blkb - p, nbb, zb);
     }
     // one block at a time: half the float64 registers live
     dequant_inverse_block<MAT, IN>(lds, x, p, ql, za, oa);
@@ -518,7 +543,7 @@ __device__ __forceinline__ void recon_i16(const int (&t)[16], const double (&f)[
 
 template <int MAT, int IN, int MODE, int QOUT, int OUT>
 __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Params P) {
-  __shared__ int lds_all[kWavesPerGroup * kWaveLds];
+  __shared__ __attribute__((aligned(16))) int lds_all[kWavesPerGroup * kWaveLds];
   int* lds = lds_all + (threadIdx.x >> 6) * kWaveLds;
   const int lane = threadIdx.x & 63, x = lane & 15, p = lane >> 4;
   int W[16];
@@ -542,6 +567,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
   else nr = load_rows_i16(in16, gn);
   for (;;) {
     const LaneGeom g = gn;
+    const int nba = blocks_a(c), nbb = blocks_b(c);
     int za[16], zb[16];
     uint4 ra = na, rb = nb;
     const RawI16 rr = nr;
@@ -562,7 +588,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
       forward_i16_rows<MAT>(rr, g, lds, x, p, za, zb);
     }
     int ta[16], tb[16];
-    quant_and_inverse<MAT, IN, MODE, QOUT, OUT>(P, g, lds, x, p, W, ql, za, zb, ta, tb);
+    quant_and_inverse<MAT, IN, MODE, QOUT, OUT>(P, g, nba, nbb, lds, x, p, lane, W, ql, za, zb, ta, tb);
     if constexpr (IN == IN_U8) {
       unsigned pa[16], pb[16];
 #pragma unroll
@@ -618,7 +644,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
 // Inverse of block-major coefficients or levels.
 template <int MAT, int CFIN, int MODE, int OUT>
 __global__ __launch_bounds__(kGroupThreads) void k_inverse(Params P) {
-  __shared__ int lds_all[kWavesPerGroup * kWaveLds];
+  __shared__ __attribute__((aligned(16))) int lds_all[kWavesPerGroup * kWaveLds];
   int* lds = lds_all + (threadIdx.x >> 6) * kWaveLds;
   const int lane = threadIdx.x & 63, x = lane & 15, p = lane >> 4;
   int W[16];
@@ -631,11 +657,23 @@ __global__ __launch_bounds__(kGroupThreads) void k_inverse(Params P) {
   }
   StripCursor c;
   if (!cursor_init(c, P)) return;
-  do {
-    const LaneGeom g = lane_geom(c, x, p);
+  LaneGeom gn = lane_geom(c, x, p);
+  int4 va[4], vb[4];
+  fetch_blocks<CFIN>(P.qcoef, lane, gn.blka - p, blocks_a(c), gn.blka - p, va);
+  fetch_blocks<CFIN>(P.qcoef, lane, gn.blkb - p, blocks_b(c), gn.blka - p, vb);
+  for (;;) {
+    const LaneGeom g = gn;
+    const int4 ca[4] = {va[0], va[1], va[2], va[3]}, cb[4] = {vb[0], vb[1], vb[2], vb[3]};
+    cursor_next(c, P);
+    const bool more = c.s < c.s_end;
+    // the next strip's coefficients, loaded unconditionally: past the last
+    // strip the cursor still describes the current one, read again
+    gn = lane_geom(c, x, p);
+    fetch_blocks<CFIN>(P.qcoef, lane, gn.blka - p, blocks_a(c), gn.blka - p, va);
+    fetch_blocks<CFIN>(P.qcoef, lane, gn.blkb - p, blocks_b(c), gn.blka - p, vb);
     int za[16], zb[16];
-    load_col<CFIN>(P.qcoef, g.blka, x, g.na > 0, za);
-    load_col<CFIN>(P.qcoef, g.blkb, x, g.nb > 0, zb);
+    blocks_to_cols(lds, p, x, lane, ca, za);
+    blocks_to_cols(lds, p, x, lane, cb, zb);
     int ta[16], tb[16];
     double fa[16], fb[16];
     if constexpr (MODE == MODE_MASK) {
@@ -655,8 +693,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_inverse(Params P) {
       }
       inverse_f64<MAT>(lds, x, p, fa, fb);
     }
-    if (!g.rowok) continue;
-    if constexpr (OUT == OUT_U8) {
+    if (!g.rowok) {
+      // rows past the image height: nothing to store
+    } else if constexpr (OUT == OUT_U8) {
       unsigned pa[16], pb[16];
       recon_u8<MODE, OUT>(ta, fa, pa);
       recon_u8<MODE, OUT>(tb, fb, pb);
@@ -674,19 +713,20 @@ __global__ __launch_bounds__(kGroupThreads) void k_inverse(Params P) {
       float* o = reinterpret_cast<float*>(P.out);
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        float va, vb;
+        float fva, fvb;
         if constexpr (MODE == MODE_MASK) {
-          va = (float)((double)ta[k] / 2304.0);
-          vb = (float)((double)tb[k] / 2304.0);
+          fva = (float)((double)ta[k] / 2304.0);
+          fvb = (float)((double)tb[k] / 2304.0);
         } else {
-          va = (float)fa[k];
-          vb = (float)fb[k];
+          fva = (float)fa[k];
+          fvb = (float)fb[k];
         }
-        if (k < g.na) o[g.rowoff + g.xa + k] = va;
-        if (k < g.nb) o[g.rowoff + g.xb + k] = vb;
+        if (k < g.na) o[g.rowoff + g.xa + k] = fva;
+        if (k < g.nb) o[g.rowoff + g.xb + k] = fvb;
       }
     }
-  } while (cursor_next(c, P), c.s < c.s_end);
+    if (!more) break;
+  }
 }
 
 // Retention or uniform quantisation of block-major coefficients: thread t
