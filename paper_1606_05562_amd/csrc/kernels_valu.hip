@@ -95,17 +95,27 @@ __device__ __forceinline__ void load_row_i16(const int16_t* img, int64_t off, in
 
 // Raw rows of blocks a and b (32 bytes each; zero for absent blocks), so
 // that the next strip's loads can be in flight while this one is computed.
+// Block rows are 16-byte aligned (validated pitches, offsets and buffers).
+// The loads are unconditional, an absent block reading column 0 of the
+// same row: loads under a branch would each be waited for at its join.
 struct RawI16 { uint4 a0, a1, b0, b1; };
+
+__device__ __forceinline__ const uint4* row_ptr16(const void* row, int64_t byte_off) {
+  return reinterpret_cast<const uint4*>(
+      __builtin_assume_aligned(reinterpret_cast<const uint8_t*>(row) + byte_off, 16));
+}
 
 __device__ __forceinline__ RawI16 load_rows_i16(const int16_t* img, const LaneGeom& g) {
   const uint4 z = make_uint4(0, 0, 0, 0);
-  const uint4* pa = reinterpret_cast<const uint4*>(img + g.rowoff + g.xa);
-  const uint4* pb = reinterpret_cast<const uint4*>(img + g.rowoff + g.xb);
+  const int16_t* row = img + g.rowoff;
+  const uint4* pa = row_ptr16(row, 2 * (int64_t)(g.na > 0 ? g.xa : 0));
+  const uint4* pb = row_ptr16(row, 2 * (int64_t)(g.nb > 0 ? g.xb : 0));
+  const uint4 a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
   RawI16 r;
-  r.a0 = g.na > 0 ? pa[0] : z;
-  r.a1 = g.na > 0 ? pa[1] : z;
-  r.b0 = g.nb > 0 ? pb[0] : z;
-  r.b1 = g.nb > 0 ? pb[1] : z;
+  r.a0 = g.na > 0 ? a0 : z;
+  r.a1 = g.na > 0 ? a1 : z;
+  r.b0 = g.nb > 0 ? b0 : z;
+  r.b1 = g.nb > 0 ? b1 : z;
   return r;
 }
 
@@ -130,8 +140,10 @@ struct ColsI32 { int a[16], b[16]; };
 // edge extension is applied where the rows are consumed, so that loads for
 // the next strip can be in flight while the current one is computed.
 __device__ __forceinline__ void load_rows_u8(const uint8_t* img, const LaneGeom& g, uint4& ra, uint4& rb) {
-  ra = g.na > 0 ? *reinterpret_cast<const uint4*>(img + g.rowoff + g.xa) : make_uint4(0, 0, 0, 0);
-  rb = g.nb > 0 ? *reinterpret_cast<const uint4*>(img + g.rowoff + g.xb) : make_uint4(0, 0, 0, 0);
+  const uint8_t* row = img + g.rowoff;
+  const uint4 a = *row_ptr16(row, g.na > 0 ? g.xa : 0), b = *row_ptr16(row, g.nb > 0 ? g.xb : 0);
+  ra = g.na > 0 ? a : make_uint4(0, 0, 0, 0);
+  rb = g.nb > 0 ? b : make_uint4(0, 0, 0, 0);
 }
 
 __device__ __forceinline__ void fix_edges_u8(const LaneGeom& g, uint4& ra, uint4& rb) {
@@ -574,11 +586,11 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
     const int img = c.img;
     const bool changed = cursor_next(c, P);
     const bool done = c.s >= c.s_end;
-    if (!done) {  // prefetch the next strip
-      gn = lane_geom(c, x, p);
-      if constexpr (IN == IN_U8) load_rows_u8(in8, gn, na, nb);
-      else nr = load_rows_i16(in16, gn);
-    }
+    // prefetch the next strip, unconditionally: past the last strip the
+    // cursor still describes the current one, which is read again
+    gn = lane_geom(c, x, p);
+    if constexpr (IN == IN_U8) load_rows_u8(in8, gn, na, nb);
+    else nr = load_rows_i16(in16, gn);
     if constexpr (IN == IN_U8) {
       us2 Z[16];
       fix_edges_u8(g, ra, rb);
@@ -616,8 +628,9 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
         // the error against the input rows, read again (cache-resident;
         // holding them across the inverse costs more in occupancy)
         int ia[16], ib[16];
-        load_row_i16(in16, g.rowoff + g.xa, g.na > 0 ? 16 : 0, ia);
-        load_row_i16(in16, g.rowoff + g.xb, g.nb > 0 ? 16 : 0, ib);
+        const RawI16 er = load_rows_i16(in16, g);
+        unpack_i16(er.a0, er.a1, 16, ia);
+        unpack_i16(er.b0, er.b1, 16, ib);
         if constexpr (OUT == OUT_I16) {
           int16_t* o = reinterpret_cast<int16_t*>(P.out);
           if (g.na > 0) store_row_i16(o, g.rowoff + g.xa, g.na, pa);
