@@ -81,7 +81,7 @@ enum ModeKind { MODE_MASK = 0, MODE_UNIFORM = 1, MODE_DEADZONE = 2 };
 struct Params {
   const ImageDesc* images;
   int32_t n_images;
-  int32_t pad0;
+  int32_t sse_slots;    // per-image SSE accumulators (vector kernels): sse[img * sse_slots + slot]
   int64_t n_strips;
   int64_t n_blocks;
   const Tables* tables;
@@ -101,7 +101,7 @@ struct Params {
 // of workgroups of kGroupThreads threads for the persistent strip kernels.
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 hipError_t launch_fill_noise(void* p, int64_t bytes, bool i16, hipStream_t s);
-hipError_t launch_psnr_finalize(const Params& P, hipStream_t s);
+hipError_t launch_sse_finalize(const Params& P, unsigned long long* sse, hipStream_t s);
 hipError_t launch_task_sse_reduce(const Params& P, hipStream_t s);
 hipError_t launch_valu_forward(int mat, int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s);
 hipError_t launch_valu_fused(int mat, int in_kind, int mode, int qout_kind, int out_kind, const Params& P,

@@ -112,7 +112,8 @@ struct adct16_plan_s {
   int64_t n_ssim_tiles = 0;
   bool lines_aligned = false;       // every pitch and image offset a multiple of 128 bytes
   int mat = MAT_APPROX;             // integer matrix of the transform (T or Walsh-Hadamard)
-  unsigned long long* d_sse_ws = nullptr;
+  unsigned long long* d_sse_ws = nullptr;  // n_images x sse_slots accumulators
+  int sse_slots = 1;
   int grid = 0;           // persistent workgroups for the strip kernels
   int backend = ADCT16_BACKEND_VALU;   // resolved backend of the fused/forward calls
   std::string tuned;      // how the choice was made
@@ -139,6 +140,7 @@ Params base_params(const adct16_plan_s* p) {
   P.rows = p->d_rows;
   P.n_rows = p->n_rows;
   P.task_sse = p->d_task_sse;
+  P.sse_slots = p->sse_slots;
   return P;
 }
 
@@ -153,8 +155,8 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void*
   P.in = d_in;
   P.out = d_out;
   P.qcoef = d_qcoef;
-  P.sse = d_sse ? reinterpret_cast<unsigned long long*>(d_sse) : p->d_sse_ws;
   P.psnr = d_psnr;
+  unsigned long long* const out_sse = reinterpret_cast<unsigned long long*>(d_sse);
   const int qk = d_qcoef ? p->qcoef_kind : CF_NONE;
   const int ok = d_out ? p->out_kind : OUT_NONE;
   hipError_t e;
@@ -163,6 +165,7 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void*
   // that also asks for the retained coefficients runs the vector kernel,
   // which accumulates per image directly.
   if (backend == ADCT16_BACKEND_MFMA && qk == CF_NONE) {
+    P.sse = out_sse ? out_sse : p->d_sse_ws;  // the reduce writes final sums
     // whole-cache-line rows: streaming (non-temporal) accesses pay off
     const bool nt = p->lines_aligned && (reinterpret_cast<uintptr_t>(d_in) & 127) == 0 &&
                     (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 127) == 0);
@@ -173,13 +176,14 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void*
     if (e != hipSuccess) return hip_fail(e, "SSE reduction kernel");
     return ADCT16_OK;
   }
-  e = launch_zero_u64(P.sse, P.n_images, s);
+  P.sse = p->d_sse_ws;  // accumulator slots
+  e = launch_zero_u64(P.sse, P.n_images * P.sse_slots, s);
   if (e != hipSuccess) return hip_fail(e, "zero SSE");
   e = launch_valu_fused(p->mat, p->in_kind, p->mode, qk, ok, P, grid, s);
   if (e != hipSuccess) return hip_fail(e, "fused kernel");
-  if (d_psnr) {
-    e = launch_psnr_finalize(P, s);
-    if (e != hipSuccess) return hip_fail(e, "PSNR kernel");
+  if (out_sse || d_psnr) {
+    e = launch_sse_finalize(P, out_sse, s);
+    if (e != hipSuccess) return hip_fail(e, "SSE / PSNR kernel");
   }
   return ADCT16_OK;
 }
@@ -498,12 +502,15 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
         rows.push_back(RowTask{(int32_t)i, (int16_t)sy, (int16_t)sx0});
   }
   p->n_rows = (int64_t)rows.size();
+  // SSE accumulator slots per image: fewer images are each worked on by
+  // more wavefronts at once (at most 2^20 accumulators in all)
+  p->sse_slots = images.size() <= 1024 ? 64 : images.size() <= 16384 ? 8 : 1;
   bool ok = hipMalloc(&p->d_images, sizeof(ImageDesc) * images.size()) == hipSuccess &&
             hipMalloc(&p->d_tables, sizeof(Tables)) == hipSuccess &&
             hipMalloc(&p->d_rows, sizeof(RowTask) * rows.size()) == hipSuccess &&
             hipMalloc(&p->d_task_sse, sizeof(uint32_t) * rows.size()) == hipSuccess &&
             hipMalloc(&p->d_ssim_tiles, sizeof(int64_t) * ssim_tiles.size()) == hipSuccess &&
-            hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size()) == hipSuccess;
+            hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size() * p->sse_slots) == hipSuccess;
   ok = ok && hipMemcpy(p->d_images, images.data(), sizeof(ImageDesc) * images.size(), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_tables, &t, sizeof t, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_rows, rows.data(), sizeof(RowTask) * rows.size(), hipMemcpyHostToDevice) == hipSuccess &&
@@ -635,12 +642,13 @@ adct16_status adct16_dct_compress_and_measure(adct16_plan p, const void* d_in, v
   Params P = base_params(p);
   P.in = d_in;
   P.out = d_out;
-  P.sse = d_sse ? reinterpret_cast<unsigned long long*>(d_sse) : p->d_sse_ws;
+  P.sse = p->d_sse_ws;
   P.psnr = d_psnr;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_zero_u64(P.sse, P.n_images, s);
+  hipError_t e = launch_zero_u64(P.sse, P.n_images * P.sse_slots, s);
   if (e == hipSuccess) e = launch_dct_roundtrip(P, p->grid, s);
-  if (e == hipSuccess && d_psnr) e = launch_psnr_finalize(P, s);
+  if (e == hipSuccess && (d_sse || d_psnr))
+    e = launch_sse_finalize(P, reinterpret_cast<unsigned long long*>(d_sse), s);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "DCT-II round trip");
 }
 
@@ -677,12 +685,12 @@ adct16_status adct16_measure(adct16_plan p, const void* d_a, const void* d_b, in
   Params P = base_params(p);
   P.in = d_a;
   P.in2 = d_b;
-  P.sse = reinterpret_cast<unsigned long long*>(d_sse);
+  P.sse = p->d_sse_ws;
   P.psnr = d_psnr;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_zero_u64(P.sse, P.n_images, s);
+  hipError_t e = launch_zero_u64(P.sse, P.n_images * P.sse_slots, s);
   if (e == hipSuccess) e = launch_measure(p->in_kind, p->out_kind, P, p->grid, s);
-  if (e == hipSuccess && d_psnr) e = launch_psnr_finalize(P, s);
+  if (e == hipSuccess) e = launch_sse_finalize(P, reinterpret_cast<unsigned long long*>(d_sse), s);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "measure kernels");
 }
 

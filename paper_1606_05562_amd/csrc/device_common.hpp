@@ -353,11 +353,19 @@ __device__ __forceinline__ uint4 keep_bytes(uint4 q, int n) {
 
 // ---------------------------------------------------------------------------
 // SSE accumulation per wavefront, flushed with one 64-bit atomic per image.
+// Per-image SSE of the vector kernels: each wavefront adds its (nonzero)
+// sums atomically into one of P.sse_slots accumulators of the image, chosen
+// by the wavefront's index, so that the wavefronts working on one image do
+// not all contend for one address; a finishing kernel sums the slots.
 struct SseAcc {
   unsigned long long lane = 0;
-  __device__ __forceinline__ void flush(unsigned long long* sse, int img) {
+  int slot = 0;
+  __device__ __forceinline__ void init(const Params& P) {
+    slot = uniform_int((int)((blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6)) % (unsigned)P.sse_slots));
+  }
+  __device__ __forceinline__ void flush(const Params& P, int img) {
     const unsigned long long t = wave_sum_u64(lane);
-    if ((threadIdx.x & 63) == 0 && t) atomicAdd(sse + img, t);
+    if ((threadIdx.x & 63) == 0 && t) atomicAdd(P.sse + (int64_t)img * P.sse_slots + slot, t);
     lane = 0;
   }
 };

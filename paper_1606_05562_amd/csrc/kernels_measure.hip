@@ -27,6 +27,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_dct_roundtrip(Params P) {
   StripCursor c;
   if (!cursor_init(c, P)) return;
   SseAcc acc;
+  acc.init(P);
   int img = c.img;
   for (;;) {
     const int y0 = c.sy * 16;
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_dct_roundtrip(Params P) {
     const bool changed = cursor_next(c, P);
     const bool done = c.s >= c.s_end;
     if (changed || done) {
-      acc.flush(P.sse, img);
+      acc.flush(P, img);
       img = c.img;
     }
     if (done) break;

@@ -569,6 +569,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
   StripCursor c;
   if (!cursor_init(c, P)) return;
   SseAcc acc;
+  acc.init(P);
   int since_flush = 0;
   const uint8_t* in8 = reinterpret_cast<const uint8_t*>(P.in);
   const int16_t* in16 = reinterpret_cast<const int16_t*>(P.in);
@@ -647,7 +648,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
       }
     }
     if (changed || done || ++since_flush == 1024) {
-      acc.flush(P.sse, img);
+      acc.flush(P, img);
       since_flush = 0;
     }
     if (done) break;
@@ -803,6 +804,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_measure(Params P) {
   StripCursor c;
   if (!cursor_init(c, P)) return;
   SseAcc acc;
+  acc.init(P);
   int since_flush = 0;
   for (;;) {
     const LaneGeom g = lane_geom(c, x, p);
@@ -842,7 +844,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_measure(Params P) {
     const bool changed = cursor_next(c, P);
     const bool done = c.s >= c.s_end;
     if (changed || done || ++since_flush == 1024) {
-      acc.flush(P.sse, img);
+      acc.flush(P, img);
       since_flush = 0;
     }
     if (done) break;
@@ -869,13 +871,17 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-// PSNR = 10 log10(255^2 h w / SSE), +inf for SSE = 0 (Section 4).
-__global__ void k_psnr(Params P) {
+// Per-image SSE from the accumulator slots (written to `sse` when given)
+// and PSNR = 10 log10(255^2 h w / SSE), +inf for SSE = 0 (Section 4).
+__global__ void k_sse_finalize(Params P, unsigned long long* sse) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P.n_images; i += gridDim.x * blockDim.x) {
-    const unsigned long long s = P.sse[i];
-    const ImageDesc d = P.images[i];
-    P.psnr[i] = s == 0 ? __builtin_huge_val()
-                       : 10.0 * log10(65025.0 * (double)d.h * (double)d.w / (double)s);
+    unsigned long long s = 0;
+    for (int k = 0; k < P.sse_slots; ++k) s += P.sse[(int64_t)i * P.sse_slots + k];
+    if (sse) sse[i] = s;
+    if (P.psnr) {
+      const ImageDesc d = P.images[i];
+      P.psnr[i] = s == 0 ? __builtin_huge_val() : 10.0 * log10(65025.0 * (double)d.h * (double)d.w / (double)s);
+    }
   }
 }
 
@@ -981,8 +987,8 @@ hipError_t launch_task_sse_reduce(const Params& P, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_psnr_finalize(const Params& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_psnr, dim3((P.n_images + 255) / 256), dim3(256), 0, s, P);
+hipError_t launch_sse_finalize(const Params& P, unsigned long long* sse, hipStream_t s) {
+  hipLaunchKernelGGL(k_sse_finalize, dim3((P.n_images + 255) / 256), dim3(256), 0, s, P, sse);
   return hipGetLastError();
 }
 
