@@ -401,11 +401,12 @@ def bench_sweep(args, A, torch):
         plan.dct_compress_and_measure(dev, out, None, psnr_d)
         plan.ssim(dev, out, ssim_d)
         pa, pd = psnr_a.cpu().numpy(), psnr_d.cpu().numpy()
+        sa, sd = ssim_a.cpu().numpy(), ssim_d.cpu().numpy()
         ape = 100.0 * np.abs(pa - pd) / pd
         fin = lambda x, nd: round(float(x), nd) if np.isfinite(x) else None  # lossless: +inf dB, no APE
         rows.append({"r": r, "compression_pct": round(100.0 * (1 - r / 256.0), 2),
                      "psnr_approx_db": fin(pa.mean(), 4), "psnr_dct_db": fin(pd.mean(), 4),
-                     "ssim_approx": fin(ssim_a.mean(), 5), "ssim_dct": fin(ssim_d.mean(), 5),
+                     "ssim_approx": fin(sa.mean(), 5), "ssim_dct": fin(sd.mean(), 5),
                      "ape_pct": fin(ape.mean(), 4) if np.all(np.isfinite(pd)) else None})
     wall = time.perf_counter() - t0
     return {"metric": "Section 4 sweep: mean PSNR / SSIM / APE vs zig-zag r (approximate vs exact DCT-II)",
