@@ -1,0 +1,87 @@
+"""Every bench.py workload at a tiny size: the JSON line keeps its contract
+(metric, value, unit, roofline where the workload reports one) and is
+serialisable.  Throughput values are not checked, only that they are
+positive and finite."""
+import argparse
+import json
+import math
+
+import pytest
+
+import bench
+
+pytestmark = pytest.mark.gpu
+
+
+def _args(workload, frames, **kw):
+    a = dict(gpus=1, steps=2, warmup=1, workload=workload, r=8, backend="auto", frames=frames,
+             no_cpu_baseline=True, no_variants=False, cpu_frames=1, calibrate_copy=False)
+    a.update(kw)
+    return argparse.Namespace(**a)
+
+
+def _run(workload, frames, **kw):
+    import torch
+
+    import paper_1606_05562_amd as A
+    fn = {"luma": bench.bench_luma, "ragged": bench.bench_ragged, "residual": bench.bench_residual,
+          "rd": bench.bench_rd, "sweep": bench.bench_sweep, "vector": bench.bench_vector}[workload]
+    res = fn(_args(workload, frames, **kw), A, torch)
+    line = json.loads(json.dumps(res))  # plain JSON types only
+    for key in ("metric", "value", "unit", "n_gpus", "config", "higher_is_better"):
+        assert key in line, key
+    assert line["n_gpus"] == 1
+    return line
+
+
+def _positive(v):
+    return isinstance(v, (int, float)) and math.isfinite(v) and v > 0
+
+
+def test_bench_luma_small():
+    line = _run("luma", 2, no_cpu_baseline=False)
+    assert _positive(line["value"])
+    r = line["roofline"]
+    for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert key in r, key
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
+    cb = line["cpu_baseline"]
+    assert cb["kind"] == "oracle" and _positive(cb["value"]) and cb["cores"] >= 1
+    assert all(_positive(v) for v in line["variants"].values())
+
+
+def test_bench_ragged_small():
+    line = _run("ragged", 4)
+    assert _positive(line["value"]) and line["roofline"]["bound"] == "hbm"
+
+
+def test_bench_residual_small():
+    line = _run("residual", 1)
+    per_q = line["config"]["per_q"]
+    assert all(_positive(per_q[f"q{q}_gsample_s"]) and _positive(per_q[f"q{q}_one_launch_gsample_s"])
+               for q in (8, 16, 32))
+
+
+def test_bench_rd_small():
+    line = _run("rd", 1)
+    pts = line["config"]["rd_curve"]
+    assert [p["qp"] for p in pts] == [22, 27, 32, 37]
+    # coarser steps never cost more bits
+    bits = [p["bits_per_sample"] for p in pts]
+    assert all(a >= b for a, b in zip(bits, bits[1:]))
+
+
+def test_bench_sweep_small():
+    line = _run("sweep", 2)
+    rows = line["config"]["rows"]
+    assert rows[0]["r"] == 1 and rows[-1]["r"] == 255
+    # retaining more coefficients never lowers the mean PSNR of either transform
+    pa = [r["psnr_approx_db"] for r in rows if r["psnr_approx_db"] is not None]
+    assert all(a <= b + 1e-9 for a, b in zip(pa, pa[1:]))
+
+
+def test_bench_vector_small():
+    line = _run("vector", 1)
+    assert _positive(line["value"]) and line["roofline"]["bound"] == "hbm"
+    assert set(line["config"]["per_direction"]) == {"forward", "inverse"}
