@@ -28,6 +28,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 N_FRAMES, H, W = 256, 1088, 1920
 COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_hbm_counters.json")
+SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_sq_counters.json")
+# Issue capacity of the chip's 256 CUs x 4 SIMDs at 2.4 GHz: a wave64 VALU
+# instruction occupies its 16-lane SIMD for 4 cycles, and each SIMD's matrix
+# core has 2.4e9 busy cycles per second.
+CUS, SIMDS_PER_CU, CLOCK_HZ = 256, 4, 2.4e9
+VALU_ISSUE_PEAK = CUS * SIMDS_PER_CU * CLOCK_HZ / 4  # wave instructions / s
+MFMA_CYCLES_PEAK = CUS * SIMDS_PER_CU * CLOCK_HZ     # matrix-core busy cycles / s
 
 
 def _parse():
@@ -93,6 +100,28 @@ def _traffic(kernel_name: str):
     fetch = c["fetch_kib"] * copy_kib / c["copy_fetch_kib"]
     write = c["write_kib"] * copy_kib / c["copy_write_kib"]
     return (fetch + write) * 1024.0
+
+
+def _compute(kernel_name: str, kernel_s: float):
+    """Vector-ALU issue and matrix-core occupancy of one launch of the fused
+    kernel: the instruction and busy-cycle counts of the committed SQ
+    counter run (fixed by the code and the workload) over the live launch
+    duration, against the chip's issue capacity; None if the kernel sources
+    changed since the counters were taken."""
+    try:
+        with open(SQ_COUNTERS) as f:
+            c = json.load(f)
+    except OSError:
+        return None
+    if c.get("source_sha256") != kernel_source_hash(kernel_name) or c.get("kernel") != kernel_name:
+        return None
+    valu = c["sq_insts_valu"] / kernel_s
+    mfma = c["sq_valu_mfma_busy_cycles"] / kernel_s
+    return {"valu_instr_per_strip": round(c["sq_insts_valu"] / c["strips"], 2),
+            "mfma_instr_per_strip": round(c["sq_insts_mfma"] / c["strips"], 2),
+            "valu_issue_gwave_instr_s": round(valu / 1e9, 1), "valu_issue_peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+            "valu_issue_frac": round(valu / VALU_ISSUE_PEAK, 4),
+            "mfma_busy_frac": round(mfma / MFMA_CYCLES_PEAK, 4)}
 
 
 def _cpu_baseline(frames, keep_r, n):
@@ -178,7 +207,8 @@ def bench_luma(args, A, torch):
                      "traffic": round(traffic / 1e9, 4) if traffic else None,
                      "traffic_unit": "GB per launch", "algorithmic_bytes": alg_bytes,
                      "kernel": kname, "kernel_ms": round(kms, 4),
-                     "copy_same_bytes_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
+                     "copy_same_bytes_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                     "compute": _compute(kname, kms * 1e-3)},
         "psnr_mean_db": round(float(psnr[torch.isfinite(psnr)].mean()), 4),
     }
     if not args.no_variants:
