@@ -35,17 +35,16 @@ struct ImageDesc {
   int32_t h, w, pitch;  // true size and row pitch (elements)
   int32_t bx, by;       // blocks across / down
   int32_t sx;           // strips across = ceil(bx / 8)
-  int64_t task_begin;   // index of the image's first task in the task table
+  int64_t pad;
 };
 static_assert(sizeof(ImageDesc) == 56, "ImageDesc layout");
 
-// Up to kTaskStrips consecutive strips of one block row of one image: the
-// unit of work that the matrix-core fused kernel deals out to wavefronts
-// cyclically (strips sx0 .. min(sx0 + kTaskStrips, sx) - 1 of block row sy).
-#ifndef ADCT16_TASK_STRIPS
-#define ADCT16_TASK_STRIPS 4
-#endif
-constexpr int kTaskStrips = ADCT16_TASK_STRIPS;
+// Up to P.task_strips (at most 16) consecutive strips of one block row of
+// one image: the unit of work that the matrix-core kernels deal out to
+// wavefronts cyclically (strips sx0 .. min(sx0 + task_strips, sx) - 1 of
+// block row sy).  Plans hold task tables for 4-strip tasks and for 16-strip
+// tasks (whole rows of images up to 2048 pixels wide); the autotuner picks.
+constexpr int kTaskStripsShort = 4, kTaskStripsLong = 16;
 struct RowTask {
   int32_t img;
   int16_t sy, sx0;
@@ -95,6 +94,9 @@ struct Params {
   const RowTask* rows;  // the batch's strips in tasks, image by image, row by row
   int64_t n_rows;
   uint32_t* task_sse;   // per-task SSE partials (matrix-core fused kernel)
+  const int64_t* task_first;  // index of each image's first task (n_images + 1 entries)
+  int32_t task_strips;  // strips per task (4 or 16)
+  int32_t pad1;
 };
 
 // Launchers (return hipSuccess or the launch error).  `grid` is the number

@@ -105,8 +105,14 @@ struct adct16_plan_s {
   int64_t n_blocks = 0, n_strips = 0;
   ImageDesc* d_images = nullptr;
   Tables* d_tables = nullptr;
-  RowTask* d_rows = nullptr;
-  int64_t n_rows = 0;
+  // Task tables of the matrix-core kernels: [0] 4-strip tasks, [1] 16-strip tasks.
+  struct TaskTable {
+    RowTask* d_rows = nullptr;
+    int64_t* d_first = nullptr;  // each image's first task, n_images + 1 entries
+    int64_t n_rows = 0;
+    int strips = 0;
+  } tasks[2];
+  int task_sel = 0;  // table of the calls without level output
   uint32_t* d_task_sse = nullptr;  // per-task SSE partials of the matrix-core fused kernel
   int64_t* d_ssim_tiles = nullptr;  // SSIM: first tile of each image (n_images + 1 entries)
   int64_t n_ssim_tiles = 0;
@@ -137,8 +143,11 @@ Params base_params(const adct16_plan_s* p) {
   P.n_strips = p->n_strips;
   P.n_blocks = p->n_blocks;
   P.tables = p->d_tables;
-  P.rows = p->d_rows;
-  P.n_rows = p->n_rows;
+  const auto& tt = p->tasks[p->task_sel];
+  P.rows = tt.d_rows;
+  P.n_rows = tt.n_rows;
+  P.task_first = tt.d_first;
+  P.task_strips = tt.strips;
   P.task_sse = p->d_task_sse;
   P.sse_slots = p->sse_slots;
   return P;
@@ -149,9 +158,13 @@ adct16_status check_plan(adct16_plan p) {
   return ADCT16_OK;
 }
 
-adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, const void* d_in, void* d_out,
+adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, const void* d_in, void* d_out,
                             void* d_qcoef, int64_t* d_sse, double* d_psnr, hipStream_t s) {
   Params P = base_params(p);
+  P.rows = p->tasks[tsel].d_rows;
+  P.n_rows = p->tasks[tsel].n_rows;
+  P.task_first = p->tasks[tsel].d_first;
+  P.task_strips = p->tasks[tsel].strips;
   P.in = d_in;
   P.out = d_out;
   P.qcoef = d_qcoef;
@@ -205,27 +218,35 @@ std::string tune_key(const adct16_plan_s* p, const char* arch, bool levels) {
   std::ostringstream k;
   k << arch << "/cu" << p->cu_count << "/b" << p->d.backend << "/t" << p->mat << "/in" << p->in_kind << "/m" << p->mode << "/q" << p->d.qmode
     << "/o" << p->out_kind << "/f" << (p->d.flags & ADCT16_FLAG_EXPLICIT_COEF) << "/lv" << (levels ? p->qcoef_kind : -1)
-    << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips);
+    << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips) << "/v2";
   return k.str();
 }
 
-bool tune_cache_get(const std::string& key, int& backend, int& wgpc) {
+bool tune_cache_get(const std::string& key, int& backend, int& wgpc, int& tsel) {
   const char* path = getenv("ADCT16_TUNE_CACHE");
   if (!path) return false;
   std::ifstream f(path);
-  std::string k;
-  int b, w;
+  std::string line;
   bool found = false;
-  while (f >> k >> b >> w)
-    if (k == key) { backend = b; wgpc = w; found = true; }
+  while (std::getline(f, line)) {
+    std::istringstream in(line);
+    std::string k;
+    int b, w, t;
+    if ((in >> k >> b >> w >> t) && k == key) {
+      backend = b;
+      wgpc = w;
+      tsel = t;
+      found = true;
+    }
+  }
   return found;
 }
 
-void tune_cache_put(const std::string& key, int backend, int wgpc) {
+void tune_cache_put(const std::string& key, int backend, int wgpc, int tsel) {
   const char* path = getenv("ADCT16_TUNE_CACHE");
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << " " << backend << " " << wgpc << "\n";
+  f << key << " " << backend << " " << wgpc << " " << tsel << "\n";
 }
 
 int grid_for(const adct16_plan_s* p, int wgpc) {
@@ -234,12 +255,13 @@ int grid_for(const adct16_plan_s* p, int wgpc) {
 
 // Tunes one call shape: without (levels = false) or with the coefficient /
 // level output, whose stores change the kernel's best occupancy.
-adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& best_b, int& best_w,
+adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& best_b, int& best_w, int& best_t,
                          std::string& how) {
   const std::string key = tune_key(p, arch, levels);
   best_b = ADCT16_BACKEND_VALU;
   best_w = 2;
-  if (tune_cache_get(key, best_b, best_w)) {
+  best_t = 0;
+  if (tune_cache_get(key, best_b, best_w, best_t)) {
     how = "cache";
     return ADCT16_OK;
   }
@@ -276,23 +298,24 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
   // Candidates are timed round-robin, one launch at a time, and each keeps
   // its fastest launch: clocks drift over a few milliseconds of sustained
   // load, and a sequential sweep would favour whichever ran first.
-  struct Cand { int backend, wgpc, grid; float best; };
+  // (matrix-core candidates also choose the task size)
+  struct Cand { int backend, wgpc, grid, tsel; float best; };
   std::vector<Cand> cands;
-  std::vector<int> backends;
-  if (p->d.backend != ADCT16_BACKEND_MFMA || levels) backends.push_back(ADCT16_BACKEND_VALU);
-  if (!levels && p->d.backend != ADCT16_BACKEND_VALU && mfma_supported(p)) backends.push_back(ADCT16_BACKEND_MFMA);
-  for (int b : backends)
-    for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({b, wg, grid_for(p, wg), 1e30f});
+  if (p->d.backend != ADCT16_BACKEND_MFMA || levels)
+    for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_VALU, wg, grid_for(p, wg), 0, 1e30f});
+  if (!levels && p->d.backend != ADCT16_BACKEND_VALU && mfma_supported(p))
+    for (int ts = 0; ts < 2; ++ts)
+      for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_MFMA, wg, grid_for(p, wg), ts, 1e30f});
   void* const tout = p->out_kind == OUT_F32 ? nullptr : w.dout;
   for (const Cand& c : cands) {  // warm-up (code objects, clocks)
-    adct16_status st = compress_impl(p, c.backend, c.grid, w.din, tout, w.dq, nullptr, nullptr, w.s);
+    adct16_status st = compress_impl(p, c.backend, c.grid, c.tsel, w.din, tout, w.dq, nullptr, nullptr, w.s);
     if (st != ADCT16_OK) return st;
   }
   for (int round = 0; round < 4; ++round) {
     for (Cand& c : cands) {
       e = hipEventRecord(w.e0, w.s);
       if (e != hipSuccess) return hip_fail(e, "autotune event");
-      adct16_status st = compress_impl(p, c.backend, c.grid, w.din, tout, w.dq, nullptr, nullptr, w.s);
+      adct16_status st = compress_impl(p, c.backend, c.grid, c.tsel, w.din, tout, w.dq, nullptr, nullptr, w.s);
       if (st != ADCT16_OK) return st;
       e = hipEventRecord(w.e1, w.s);
       if (e == hipSuccess) e = hipEventSynchronize(w.e1);
@@ -304,22 +327,23 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
   }
   float best = 1e30f;
   for (const Cand& c : cands)
-    if (c.best < best) { best = c.best; best_b = c.backend; best_w = c.wgpc; }
+    if (c.best < best) { best = c.best; best_b = c.backend; best_w = c.wgpc; best_t = c.tsel; }
   std::ostringstream t;
   t << "timed:" << best_w << "wg/cu";
   how = t.str();
-  tune_cache_put(key, best_b, best_w);
+  tune_cache_put(key, best_b, best_w, best_t);
   return ADCT16_OK;
 }
 
 adct16_status autotune(adct16_plan_s* p, const char* arch) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  int b, wg;
-  adct16_status st = tune_shape(p, arch, false, b, wg, p->tuned);
+  int b, wg, ts;
+  adct16_status st = tune_shape(p, arch, false, b, wg, ts, p->tuned);
   if (st != ADCT16_OK) return st;
   p->backend = b;
   p->grid = grid_for(p, wg);
-  st = tune_shape(p, arch, true, b, wg, p->tuned_lv);
+  p->task_sel = ts;
+  st = tune_shape(p, arch, true, b, wg, ts, p->tuned_lv);
   if (st != ADCT16_OK) return st;
   p->grid_lv = grid_for(p, wg);
   return ADCT16_OK;
@@ -494,26 +518,37 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   }
   p->n_ssim_tiles = ssim_tiles.back();
   t.rsep = d->qmode == ADCT16_Q_ZONAL ? d->r : 16;
-  std::vector<RowTask> rows;
-  for (size_t i = 0; i < images.size(); ++i) {
-    images[i].task_begin = (int64_t)rows.size();
-    for (int sy = 0; sy < images[i].by; ++sy)
-      for (int sx0 = 0; sx0 < images[i].sx; sx0 += kTaskStrips)
-        rows.push_back(RowTask{(int32_t)i, (int16_t)sy, (int16_t)sx0});
+  std::vector<RowTask> rows[2];
+  std::vector<int64_t> first[2];
+  for (int ts = 0; ts < 2; ++ts) {
+    const int n = ts == 0 ? kTaskStripsShort : kTaskStripsLong;
+    p->tasks[ts].strips = n;
+    for (size_t i = 0; i < images.size(); ++i) {
+      first[ts].push_back((int64_t)rows[ts].size());
+      for (int sy = 0; sy < images[i].by; ++sy)
+        for (int sx0 = 0; sx0 < images[i].sx; sx0 += n) rows[ts].push_back(RowTask{(int32_t)i, (int16_t)sy, (int16_t)sx0});
+    }
+    first[ts].push_back((int64_t)rows[ts].size());
+    p->tasks[ts].n_rows = (int64_t)rows[ts].size();
   }
-  p->n_rows = (int64_t)rows.size();
   // SSE accumulator slots per image: fewer images are each worked on by
   // more wavefronts at once (at most 2^20 accumulators in all)
   p->sse_slots = images.size() <= 1024 ? 64 : images.size() <= 16384 ? 8 : 1;
   bool ok = hipMalloc(&p->d_images, sizeof(ImageDesc) * images.size()) == hipSuccess &&
             hipMalloc(&p->d_tables, sizeof(Tables)) == hipSuccess &&
-            hipMalloc(&p->d_rows, sizeof(RowTask) * rows.size()) == hipSuccess &&
-            hipMalloc(&p->d_task_sse, sizeof(uint32_t) * rows.size()) == hipSuccess &&
+            hipMalloc(&p->tasks[0].d_rows, sizeof(RowTask) * rows[0].size()) == hipSuccess &&
+            hipMalloc(&p->tasks[1].d_rows, sizeof(RowTask) * rows[1].size()) == hipSuccess &&
+            hipMalloc(&p->tasks[0].d_first, sizeof(int64_t) * first[0].size()) == hipSuccess &&
+            hipMalloc(&p->tasks[1].d_first, sizeof(int64_t) * first[1].size()) == hipSuccess &&
+            hipMalloc(&p->d_task_sse, sizeof(uint32_t) * rows[0].size()) == hipSuccess &&
             hipMalloc(&p->d_ssim_tiles, sizeof(int64_t) * ssim_tiles.size()) == hipSuccess &&
             hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size() * p->sse_slots) == hipSuccess;
   ok = ok && hipMemcpy(p->d_images, images.data(), sizeof(ImageDesc) * images.size(), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_tables, &t, sizeof t, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->d_rows, rows.data(), sizeof(RowTask) * rows.size(), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p->tasks[0].d_rows, rows[0].data(), sizeof(RowTask) * rows[0].size(), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p->tasks[1].d_rows, rows[1].data(), sizeof(RowTask) * rows[1].size(), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p->tasks[0].d_first, first[0].data(), sizeof(int64_t) * first[0].size(), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p->tasks[1].d_first, first[1].data(), sizeof(int64_t) * first[1].size(), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_ssim_tiles, ssim_tiles.data(), sizeof(int64_t) * ssim_tiles.size(), hipMemcpyHostToDevice) ==
            hipSuccess;
   if (!ok) {
@@ -556,7 +591,10 @@ adct16_status adct16_plan_destroy(adct16_plan p) {
   // nothing useful can be done about a failed free on teardown
   if (p->d_images) (void)hipFree(p->d_images);
   if (p->d_tables) (void)hipFree(p->d_tables);
-  if (p->d_rows) (void)hipFree(p->d_rows);
+  for (auto& tt : p->tasks) {
+    if (tt.d_rows) (void)hipFree(tt.d_rows);
+    if (tt.d_first) (void)hipFree(tt.d_first);
+  }
   if (p->d_task_sse) (void)hipFree(p->d_task_sse);
   if (p->d_ssim_tiles) (void)hipFree(p->d_ssim_tiles);
   if (p->d_sse_ws) (void)hipFree(p->d_sse_ws);
@@ -578,6 +616,7 @@ adct16_status adct16_plan_info(adct16_plan p, char* buf, int32_t len) {
   o << "{\"backend\": \"" << (p->backend == ADCT16_BACKEND_MFMA ? "mfma" : "valu") << "\", \"grid\": " << p->grid
     << ", \"threads\": " << kGroupThreads << ", \"strips\": " << p->n_strips << ", \"blocks\": " << p->n_blocks
     << ", \"cus\": " << p->cu_count << ", \"rows_line_aligned\": " << (p->lines_aligned ? "true" : "false")
+    << ", \"task_strips\": " << p->tasks[p->task_sel].strips
     << ", \"choice\": \"" << p->tuned << "\", \"levels_grid\": " << p->grid_lv
     << ", \"levels_choice\": \"" << p->tuned_lv << "\"}";
   const std::string s = o.str();
@@ -703,8 +742,9 @@ adct16_status adct16_compress_and_measure(adct16_plan p, const void* d_in, void*
   if (d_out && p->out_kind == OUT_F32)
     return fail(ADCT16_E_STATE, "the fused call writes rounded reconstructions (out_dtype U8 or I16)");
   if (d_qcoef)
-    return compress_impl(p, ADCT16_BACKEND_VALU, p->grid_lv, d_in, d_out, d_qcoef, d_sse, d_psnr, (hipStream_t)stream);
-  return compress_impl(p, p->backend, p->grid, d_in, d_out, d_qcoef, d_sse, d_psnr, (hipStream_t)stream);
+    return compress_impl(p, ADCT16_BACKEND_VALU, p->grid_lv, p->task_sel, d_in, d_out, d_qcoef, d_sse, d_psnr,
+                         (hipStream_t)stream);
+  return compress_impl(p, p->backend, p->grid, p->task_sel, d_in, d_out, d_qcoef, d_sse, d_psnr, (hipStream_t)stream);
 }
 
 adct16_status adct16_dct_forward(adct16_plan p, const void* d_in, float* d_y, int32_t precision, void* stream) {

@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   int sy = __builtin_amdgcn_readlane(tr.sy, 0);
   int sxi = __builtin_amdgcn_readlane(tr.sx0, 0);
   ImgGeom d = task_geom(tr, 0);
-  int sxe = min(sxi + kTaskStrips, d.sx);  // end of the current task
+  int sxe = min(sxi + P.task_strips, d.sx);  // end of the current task
   auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
     return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
   };
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   // strips x 2048 pixels x 255^2 < 2^32); a second kernel sums the partials
   // of each image.  No atomics: tasks of one image run on many wavefronts at
   // once, and contended atomics would serialise them.
-  static_assert(kTaskStrips <= 16, "per-task SSE must fit 32 bits");
+  // (tasks hold at most 16 strips)
   unsigned lane_sse = 0, sum_aa = 0, sum_rr = 0, sum_ar = 0;
   int64_t tcur = t0;  // index of the current task
   for (;;) {
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
         nsy = __builtin_amdgcn_readlane(tr.sy, kk);
         nsxi = __builtin_amdgcn_readlane(tr.sx0, kk);
         nd = task_geom(tr, kk);
-        nsxe = min(nsxi + kTaskStrips, nd.sx);
+        nsxe = min(nsxi + P.task_strips, nd.sx);
       }
     }
     const uint4 cr[2] = {nr[0], nr[1]};
@@ -524,7 +524,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P, const 
   int sy = __builtin_amdgcn_readlane(tr.sy, 0);
   int sxi = __builtin_amdgcn_readlane(tr.sx0, 0);
   ImgGeom d = task_geom(tr, 0);
-  int sxe = min(sxi + kTaskStrips, d.sx);
+  int sxe = min(sxi + P.task_strips, d.sx);
   auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
     return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
   };
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P, const 
         nsy = __builtin_amdgcn_readlane(tr.sy, kk);
         nsxi = __builtin_amdgcn_readlane(tr.sx0, kk);
         nd = task_geom(tr, kk);
-        nsxe = min(nsxi + kTaskStrips, nd.sx);
+        nsxe = min(nsxi + P.task_strips, nd.sx);
       }
     }
     const uint4 cr[2] = {nr[0], nr[1]};

@@ -889,8 +889,7 @@ __global__ void k_sse_finalize(Params P, unsigned long long* sse) {
 // (one wavefront per image; an image's tasks are contiguous), and PSNR.
 __global__ __launch_bounds__(64) void k_task_sse_reduce(Params P) {
   const int i = blockIdx.x;
-  const int64_t b = P.images[i].task_begin;
-  const int64_t e = i + 1 < P.n_images ? P.images[i + 1].task_begin : P.n_rows;
+  const int64_t b = P.task_first[i], e = P.task_first[i + 1];
   unsigned long long v = 0;
   for (int64_t t = b + threadIdx.x; t < e; t += 64) v += P.task_sse[t];
   v = wave_sum_u64(v);
