@@ -24,6 +24,10 @@
  *   is enqueued asynchronously; errors the host can detect are returned
  *   before anything is enqueued, and a failed launch returns
  *   ADCT16_E_LAUNCH.  No compute call allocates memory.
+ * - A plan owns workspace (per-image SSE accumulators, task partials) that
+ *   its measuring calls use; calls on one plan must not overlap (use one
+ *   stream per plan, or one plan per stream).  Every call leaves the
+ *   workspace ready for the next, so graph replays need no reset.
  * - Images of a batch live in one packed device buffer.  Image k has
  *   height[k] x width[k] pixels; its row y starts at element
  *   offset[k] + y * pitch[k].  Requirements: pitch >= width rounded up to

@@ -118,7 +118,10 @@ struct adct16_plan_s {
   int64_t n_ssim_tiles = 0;
   bool lines_aligned = false;       // every pitch and image offset a multiple of 128 bytes
   int mat = MAT_APPROX;             // integer matrix of the transform (T or Walsh-Hadamard)
-  unsigned long long* d_sse_ws = nullptr;  // n_images x sse_slots accumulators
+  // n_images x sse_slots accumulators of the vector kernels, zero between
+  // calls (cleared at creation, and by the finishing kernel of every call)
+  unsigned long long* d_sse_ws = nullptr;
+  unsigned long long* d_sse_out = nullptr;  // per-image SSE when the caller passes none
   int sse_slots = 1;
   int grid = 0;           // persistent workgroups for the strip kernels
   int backend = ADCT16_BACKEND_VALU;   // resolved backend of the fused/forward calls
@@ -178,7 +181,7 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, c
   // that also asks for the retained coefficients runs the vector kernel,
   // which accumulates per image directly.
   if (backend == ADCT16_BACKEND_MFMA && qk == CF_NONE) {
-    P.sse = out_sse ? out_sse : p->d_sse_ws;  // the reduce writes final sums
+    P.sse = out_sse ? out_sse : p->d_sse_out;  // the reduce writes final sums
     // whole-cache-line rows: streaming (non-temporal) accesses pay off
     const bool nt = p->lines_aligned && (reinterpret_cast<uintptr_t>(d_in) & 127) == 0 &&
                     (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 127) == 0);
@@ -189,15 +192,11 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, c
     if (e != hipSuccess) return hip_fail(e, "SSE reduction kernel");
     return ADCT16_OK;
   }
-  P.sse = p->d_sse_ws;  // accumulator slots
-  e = launch_zero_u64(P.sse, P.n_images * P.sse_slots, s);
-  if (e != hipSuccess) return hip_fail(e, "zero SSE");
+  P.sse = p->d_sse_ws;  // accumulator slots (zero on entry)
   e = launch_valu_fused(p->mat, p->in_kind, p->mode, qk, ok, P, grid, s);
   if (e != hipSuccess) return hip_fail(e, "fused kernel");
-  if (out_sse || d_psnr) {
-    e = launch_sse_finalize(P, out_sse, s);
-    if (e != hipSuccess) return hip_fail(e, "SSE / PSNR kernel");
-  }
+  e = launch_sse_finalize(P, out_sse, s);  // also clears the slots
+  if (e != hipSuccess) return hip_fail(e, "SSE / PSNR kernel");
   return ADCT16_OK;
 }
 
@@ -542,7 +541,9 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
             hipMalloc(&p->tasks[1].d_first, sizeof(int64_t) * first[1].size()) == hipSuccess &&
             hipMalloc(&p->d_task_sse, sizeof(uint32_t) * rows[0].size()) == hipSuccess &&
             hipMalloc(&p->d_ssim_tiles, sizeof(int64_t) * ssim_tiles.size()) == hipSuccess &&
-            hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size() * p->sse_slots) == hipSuccess;
+            hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size() * p->sse_slots) == hipSuccess &&
+            hipMalloc(&p->d_sse_out, sizeof(unsigned long long) * images.size()) == hipSuccess;
+  ok = ok && hipMemset(p->d_sse_ws, 0, sizeof(unsigned long long) * images.size() * p->sse_slots) == hipSuccess;
   ok = ok && hipMemcpy(p->d_images, images.data(), sizeof(ImageDesc) * images.size(), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_tables, &t, sizeof t, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->tasks[0].d_rows, rows[0].data(), sizeof(RowTask) * rows[0].size(), hipMemcpyHostToDevice) == hipSuccess &&
@@ -598,6 +599,7 @@ adct16_status adct16_plan_destroy(adct16_plan p) {
   if (p->d_task_sse) (void)hipFree(p->d_task_sse);
   if (p->d_ssim_tiles) (void)hipFree(p->d_ssim_tiles);
   if (p->d_sse_ws) (void)hipFree(p->d_sse_ws);
+  if (p->d_sse_out) (void)hipFree(p->d_sse_out);
   delete p;
   return ADCT16_OK;
 }
@@ -684,10 +686,8 @@ adct16_status adct16_dct_compress_and_measure(adct16_plan p, const void* d_in, v
   P.sse = p->d_sse_ws;
   P.psnr = d_psnr;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_zero_u64(P.sse, P.n_images * P.sse_slots, s);
-  if (e == hipSuccess) e = launch_dct_roundtrip(P, p->grid, s);
-  if (e == hipSuccess && (d_sse || d_psnr))
-    e = launch_sse_finalize(P, reinterpret_cast<unsigned long long*>(d_sse), s);
+  hipError_t e = launch_dct_roundtrip(P, p->grid, s);
+  if (e == hipSuccess) e = launch_sse_finalize(P, reinterpret_cast<unsigned long long*>(d_sse), s);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "DCT-II round trip");
 }
 
@@ -727,8 +727,7 @@ adct16_status adct16_measure(adct16_plan p, const void* d_a, const void* d_b, in
   P.sse = p->d_sse_ws;
   P.psnr = d_psnr;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_zero_u64(P.sse, P.n_images * P.sse_slots, s);
-  if (e == hipSuccess) e = launch_measure(p->in_kind, p->out_kind, P, p->grid, s);
+  hipError_t e = launch_measure(p->in_kind, p->out_kind, P, p->grid, s);
   if (e == hipSuccess) e = launch_sse_finalize(P, reinterpret_cast<unsigned long long*>(d_sse), s);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "measure kernels");
 }

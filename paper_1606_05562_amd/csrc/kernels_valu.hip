@@ -872,15 +872,23 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 }
 
 // Per-image SSE from the accumulator slots (written to `sse` when given)
-// and PSNR = 10 log10(255^2 h w / SSE), +inf for SSE = 0 (Section 4).
-__global__ void k_sse_finalize(Params P, unsigned long long* sse) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P.n_images; i += gridDim.x * blockDim.x) {
-    unsigned long long s = 0;
-    for (int k = 0; k < P.sse_slots; ++k) s += P.sse[(int64_t)i * P.sse_slots + k];
-    if (sse) sse[i] = s;
+// and PSNR = 10 log10(255^2 h w / SSE), +inf for SSE = 0 (Section 4).  One
+// wavefront per image, a lane per slot; the slots are cleared after they
+// are read, so that every call leaves them at zero for the next one.
+__global__ __launch_bounds__(64) void k_sse_finalize(Params P, unsigned long long* sse) {
+  const int i = blockIdx.x, l = threadIdx.x;
+  unsigned long long* slots = P.sse + (int64_t)i * P.sse_slots;
+  unsigned long long v = 0;
+  for (int k = l; k < P.sse_slots; k += 64) {
+    v += slots[k];
+    slots[k] = 0;
+  }
+  v = wave_sum_u64(v);
+  if (l == 0) {
+    if (sse) sse[i] = v;
     if (P.psnr) {
-      const ImageDesc d = P.images[i];
-      P.psnr[i] = s == 0 ? __builtin_huge_val() : 10.0 * log10(65025.0 * (double)d.h * (double)d.w / (double)s);
+      const ImageDesc& d = P.images[i];
+      P.psnr[i] = v == 0 ? __builtin_huge_val() : 10.0 * log10(65025.0 * (double)d.h * (double)d.w / (double)v);
     }
   }
 }
@@ -987,7 +995,7 @@ hipError_t launch_task_sse_reduce(const Params& P, hipStream_t s) {
 }
 
 hipError_t launch_sse_finalize(const Params& P, unsigned long long* sse, hipStream_t s) {
-  hipLaunchKernelGGL(k_sse_finalize, dim3((P.n_images + 255) / 256), dim3(256), 0, s, P, sse);
+  hipLaunchKernelGGL(k_sse_finalize, dim3(P.n_images), dim3(64), 0, s, P, sse);
   return hipGetLastError();
 }
 
