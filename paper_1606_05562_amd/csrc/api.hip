@@ -563,6 +563,9 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   int wgpc = 4;
   if (const char* env = getenv("ADCT16_WG_PER_CU")) wgpc = std::max(1, std::min(64, atoi(env)));
   p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)p->cu_count * wgpc, max_groups));
+  // task size of the matrix-core kernels (ADCT16_TASK_STRIPS = 4 or 16 overrides the default 4; the
+  // autotuner may replace it)
+  if (const char* env = getenv("ADCT16_TASK_STRIPS")) p->task_sel = atoi(env) >= kTaskStripsLong ? 1 : 0;
   if (d->backend == ADCT16_BACKEND_MFMA && !mfma_supported(p)) {
     adct16_plan_destroy(p);
     return fail(ADCT16_E_MODE, "MFMA backend supports U8 input, retention modes and U8 output");

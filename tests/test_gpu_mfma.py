@@ -129,6 +129,32 @@ def test_mfma_ragged(align):
         assert np.array_equal(got, want) and sse[i] == s
 
 
+@pytest.mark.parametrize("strips", [4, 16])
+def test_mfma_task_sizes(monkeypatch, strips):
+    """Both task tables (tasks of up to 4 or 16 strips of a block row), on
+    images whose block rows hold fewer and more strips than a task, through
+    the fused kernel and both forward forms."""
+    monkeypatch.setenv("ADCT16_TASK_STRIPS", str(strips))
+    T = torch()
+    sizes = [(48, 16), (40, 130), (33, 2050), (20, 4000), (272, 384), (70, 1920), (16, 2048)]
+    ims = [mixed_image(BASE_SEED + 6, k, h, w) for k, (h, w) in enumerate(sizes)]
+    b = Batch(ims, 128)
+    plan = b.plan(coef_dtype=A().I32, qmode=A().Q_ZONAL, r=6, backend=A().BACKEND_MFMA)
+    import json
+    assert json.loads(plan.info())["task_strips"] == strips
+    recs, sse, _ = _fused(b, A().BACKEND_MFMA, A().Q_ZONAL, 6)
+    for i, (got, im) in enumerate(zip(recs, ims)):
+        want, s, _ = codec.compress_kept(im, codec.mask_zonal(6))
+        assert np.array_equal(got, want) and sse[i] == s, f"image {i} {sizes[i]}"
+    for int8 in (False, True):
+        p = b.plan(coef_dtype=A().I32, backend=A().BACKEND_MFMA, flags=A().FLAG_MFMA_INT8 if int8 else 0)
+        coef = b.coef_tensor(T.int32)
+        p.forward(b.dev, coef)
+        T.cuda.synchronize()
+        for i, (got, im) in enumerate(zip(b.split_coef(coef), ims)):
+            assert np.array_equal(got.astype(np.int64), codec.forward_image(im)), f"int8={int8} image {i}"
+
+
 def test_mfma_full_size_sampled():
     T = torch()
     mod = A()
