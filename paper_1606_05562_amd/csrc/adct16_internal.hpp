@@ -120,6 +120,7 @@ hipError_t launch_ssim(const Params& P, const int64_t* tile_begin, int64_t n_til
 
 hipError_t launch_mfma_forward(int coef_kind, bool nt, const Params& P, int grid, hipStream_t s);
 hipError_t launch_mfma_forward_i8(int coef_kind, bool nt, const Params& P, int grid, hipStream_t s);
+hipError_t launch_mfma_forward_i16(bool nt, const Params& P, int grid, hipStream_t s);
 hipError_t launch_mfma_fused(bool zigzag, bool collapse, int out_kind, bool nt, const Params& P, int grid,
                              hipStream_t s);
 hipError_t launch_dct_mfma(int in_kind, int precision, const Params& P, float* y, int grid,

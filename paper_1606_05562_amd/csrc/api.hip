@@ -161,6 +161,8 @@ adct16_status check_plan(adct16_plan p) {
   return ADCT16_OK;
 }
 
+bool mfma_supported(const adct16_plan_s* p);
+
 adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, const void* d_in, void* d_out,
                             void* d_qcoef, int64_t* d_sse, double* d_psnr, hipStream_t s) {
   Params P = base_params(p);
@@ -180,7 +182,7 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, c
   // partials, which a second kernel sums per image (SSE and PSNR); a call
   // that also asks for the retained coefficients runs the vector kernel,
   // which accumulates per image directly.
-  if (backend == ADCT16_BACKEND_MFMA && qk == CF_NONE) {
+  if (backend == ADCT16_BACKEND_MFMA && qk == CF_NONE && mfma_supported(p)) {
     P.sse = out_sse ? out_sse : p->d_sse_out;  // the reduce writes final sums
     // whole-cache-line rows: streaming (non-temporal) accesses pay off
     const bool nt = p->lines_aligned && (reinterpret_cast<uintptr_t>(d_in) & 127) == 0 &&
@@ -200,10 +202,15 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, c
   return ADCT16_OK;
 }
 
-// The matrix-core kernels cover 8-bit input with retention masks (the
-// uniform quantiser's inverse runs in float64 on the vector ALUs).
+// The matrix-core fused kernel covers 8-bit input with retention masks (the
+// quantisers run on the vector ALUs); the matrix-core forward covers 8-bit
+// input to int32 or centred int16 coefficients, and 16-bit input to int32.
 bool mfma_supported(const adct16_plan_s* p) {
   return p->in_kind == IN_U8 && p->mode == MODE_MASK && p->out_kind == OUT_U8;
+}
+
+bool mfma_forward_supported(const adct16_plan_s* p) {
+  return (p->in_kind == IN_U8 && p->coef_kind != CF_F32) || (p->in_kind == IN_I16 && p->coef_kind == CF_I32);
 }
 
 // Autotuning: time the fused call for each candidate (backend, workgroups
@@ -300,7 +307,7 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
   // (matrix-core candidates also choose the task size)
   struct Cand { int backend, wgpc, grid, tsel; float best; };
   std::vector<Cand> cands;
-  if (p->d.backend != ADCT16_BACKEND_MFMA || levels)
+  if (p->d.backend != ADCT16_BACKEND_MFMA || levels || !mfma_supported(p))
     for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_VALU, wg, grid_for(p, wg), 0, 1e30f});
   if (!levels && p->d.backend != ADCT16_BACKEND_VALU && mfma_supported(p))
     for (int ts = 0; ts < 2; ++ts)
@@ -339,7 +346,8 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
   int b, wg, ts;
   adct16_status st = tune_shape(p, arch, false, b, wg, ts, p->tuned);
   if (st != ADCT16_OK) return st;
-  p->backend = b;
+  // a requested matrix-core backend stays the forward's, whatever runs the fused call
+  p->backend = p->d.backend == ADCT16_BACKEND_MFMA ? ADCT16_BACKEND_MFMA : b;
   p->grid = grid_for(p, wg);
   p->task_sel = ts;
   st = tune_shape(p, arch, true, b, wg, ts, p->tuned_lv);
@@ -566,9 +574,11 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   // task size of the matrix-core kernels (ADCT16_TASK_STRIPS = 4 or 16 overrides the default 4; the
   // autotuner may replace it)
   if (const char* env = getenv("ADCT16_TASK_STRIPS")) p->task_sel = atoi(env) >= kTaskStripsLong ? 1 : 0;
-  if (d->backend == ADCT16_BACKEND_MFMA && !mfma_supported(p)) {
+  if (d->backend == ADCT16_BACKEND_MFMA && !mfma_supported(p) && !mfma_forward_supported(p)) {
     adct16_plan_destroy(p);
-    return fail(ADCT16_E_MODE, "MFMA backend supports U8 input, retention modes and U8 output");
+    return fail(ADCT16_E_MODE,
+                "MFMA backend supports U8 input with retention modes and U8 output (fused call), or U8 input to "
+                "I32/I16 coefficients and I16 input to I32 coefficients (forward)");
   }
   p->grid_lv = p->grid;
   p->tuned_lv = "default";
@@ -621,6 +631,9 @@ adct16_status adct16_plan_info(adct16_plan p, char* buf, int32_t len) {
   o << "{\"backend\": \"" << (p->backend == ADCT16_BACKEND_MFMA ? "mfma" : "valu") << "\", \"grid\": " << p->grid
     << ", \"threads\": " << kGroupThreads << ", \"strips\": " << p->n_strips << ", \"blocks\": " << p->n_blocks
     << ", \"cus\": " << p->cu_count << ", \"rows_line_aligned\": " << (p->lines_aligned ? "true" : "false")
+    << ", \"fused_backend\": \"" << (p->backend == ADCT16_BACKEND_MFMA && mfma_supported(p) ? "mfma" : "valu")
+    << "\", \"forward_backend\": \""
+    << (p->backend == ADCT16_BACKEND_MFMA && mfma_forward_supported(p) ? "mfma" : "valu") << "\""
     << ", \"task_strips\": " << p->tasks[p->task_sel].strips
     << ", \"choice\": \"" << p->tuned << "\", \"levels_grid\": " << p->grid_lv
     << ", \"levels_choice\": \"" << p->tuned_lv << "\"}";
@@ -638,12 +651,16 @@ adct16_status adct16_forward(adct16_plan p, const void* d_in, void* d_coef, void
   P.in = d_in;
   P.coef = d_coef;
   hipError_t e;
-  if (p->backend == ADCT16_BACKEND_MFMA && p->coef_kind != CF_F32) {
+  if (p->backend == ADCT16_BACKEND_MFMA && mfma_forward_supported(p)) {
     // whole-cache-line rows and block-aligned coefficients: streaming accesses
     const bool nt = p->lines_aligned && (reinterpret_cast<uintptr_t>(d_in) & 127) == 0 &&
                     (reinterpret_cast<uintptr_t>(d_coef) & 127) == 0;
-    e = (p->d.flags & ADCT16_FLAG_MFMA_INT8) ? launch_mfma_forward_i8(p->coef_kind, nt, P, p->grid, (hipStream_t)stream)
-                                             : launch_mfma_forward(p->coef_kind, nt, P, p->grid, (hipStream_t)stream);
+    if (p->in_kind == IN_I16)  // 16-bit input: the int8 form with three digits per value
+      e = launch_mfma_forward_i16(nt, P, p->grid, (hipStream_t)stream);
+    else if (p->d.flags & ADCT16_FLAG_MFMA_INT8)
+      e = launch_mfma_forward_i8(p->coef_kind, nt, P, p->grid, (hipStream_t)stream);
+    else
+      e = launch_mfma_forward(p->coef_kind, nt, P, p->grid, (hipStream_t)stream);
   } else
     e = launch_valu_forward(p->mat, p->in_kind, p->coef_kind, P, p->grid, (hipStream_t)stream);
   return e == hipSuccess ? ADCT16_OK : hip_fail(e, "forward kernel");

@@ -612,6 +612,170 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P, const 
 }
 
 // ---------------------------------------------------------------------------
+// Forward transform of 16-bit input (any int16 sample, e.g. prediction
+// residuals) as int8 products with int32 accumulation, exact.  Every value
+// is split into three base-64 digits, v = 4096 d2 + 64 d1 + d0 with d0, d1
+// in [0, 63] and d2 = v >> 12 signed:
+//
+//   row pass     X: d2 in [-8, 7].  One K = 32 product takes d0 (slots of
+//                lane groups g < 2) and d1 (g >= 2) against [T | 64 T], a
+//                second takes d2 against T; P = first + (second << 12).
+//                |P| <= 524288.
+//   column pass  P: d2 in [-128, 127]; the same two products with the
+//                forward kernel's operand layout (lane 16g + q holds the
+//                digits of P[4g..4g+3][q]); Z = first + (second << 12),
+//                |Z| <= 2^23.
+//
+// Strips are 16 rows x 128 samples (256 bytes per row); a load instruction
+// covers 4 rows x 256 bytes (lane l: row l / 16, 16-byte chunk l % 16).  The
+// LDS regroups the rows (272-byte rows: conflict-free reads) so that lane
+// 16g + q holds the 8 samples of row q, columns 8 (g & 1) .. + 7 of a block.
+constexpr int kI16Row = 68;                  // LDS dwords per strip row (256 B + 16 B)
+constexpr int kI16WaveLds = 16 * kI16Row;    // dwords per wavefront
+
+// Bytes 0 and 2 of four dwords, in order (the low bytes of 8 packed
+// 16-bit values).
+__device__ __forceinline__ uint2 even_bytes(unsigned a, unsigned b, unsigned c, unsigned d) {
+  return make_uint2(__builtin_amdgcn_perm(b, a, 0x06040200u), __builtin_amdgcn_perm(d, c, 0x06040200u));
+}
+
+// Row-pass operands of 8 samples (packed 16-bit pairs in `w`): the first
+// product's digit (d0, or d1 when `sh` = 6) and the second's (d2, or zero
+// for lane groups g >= 2).
+__device__ __forceinline__ void i16_row_digits(const uint4& w, int sh, bool top, uint2& a1, uint2& a2) {
+  const unsigned m = 0x003F003Fu;
+  a1 = even_bytes((w.x >> sh) & m, (w.y >> sh) & m, (w.z >> sh) & m, (w.w >> sh) & m);
+  typedef short s2 __attribute__((ext_vector_type(2)));
+  auto hi = [](unsigned v) { return __builtin_bit_cast(unsigned, __builtin_bit_cast(s2, v) >> (short)12); };
+  const uint2 d2 = even_bytes(hi(w.x), hi(w.y), hi(w.z), hi(w.w));
+  a2 = top ? d2 : make_uint2(0u, 0u);
+}
+
+template <bool NT>
+__global__ __launch_bounds__(kGroupThreads) void k_mfma_forward_i16(Params P, const ImageDesc* __restrict__ images,
+                                                                    const RowTask* __restrict__ rows) {
+  __shared__ __attribute__((aligned(16))) int lds_all[kWavesPerGroup * kI16WaveLds];
+  int* lds = lds_all + (threadIdx.x >> 6) * kI16WaveLds;
+  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4, rr = lane >> 4, cc = lane & 15;
+  const signed char* tm = P.tables->tmat;
+  // row pass B: lane (n = q, g): T[n][8 (g & 1) + j], times 64 for g >= 2
+  const uint2 b1 = make_uint2(t_bytes(tm, q, 8 * (g & 1), g < 2 ? 1 : 64), t_bytes(tm, q, 8 * (g & 1) + 4, g < 2 ? 1 : 64));
+  // column pass B (as in the 8-bit int8 form): slots j < 4 T[q][4g + j], j >= 4 64 T[q][4g + j - 4]
+  const uint2 b2 = make_uint2(t_bytes(tm, q, 4 * g), t_bytes(tm, q, 4 * g, 64));
+  const int sh = g < 2 ? 0 : 6;
+  const int16_t* in = reinterpret_cast<const int16_t*>(P.in);
+  const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
+  int64_t t0 = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
+  if (t0 >= P.n_rows) return;
+  TaskRegs tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
+  int kk = 0;
+  int sy = __builtin_amdgcn_readlane(tr.sy, 0);
+  int sxi = __builtin_amdgcn_readlane(tr.sx0, 0);
+  ImgGeom d = task_geom(tr, 0);
+  int sxe = min(sxi + P.task_strips, d.sx);
+  auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
+    return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
+  };
+  // this lane's first 16 bytes of strip (ssy, ssxi): row 16 ssy + rr, chunk cc (elements)
+  auto lane_off = [&](const ImgGeom& dd, int ssy, int ssxi) {
+    return dd.offset + (int64_t)(ssy * 16 + rr) * dd.pitch + ssxi * (16 * kStripBlocks) + 8 * cc;
+  };
+  auto load4 = [&](const ImgGeom& dd, int ssy, int ssxi, uint4 (&v)[4]) {
+    const int64_t o = lane_off(dd, ssy, ssxi);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = ld_row16<NT>(reinterpret_cast<const uint8_t*>(in + o + 4 * i * (int64_t)dd.pitch));
+  };
+  uint4 nr[4] = {};
+  if (interior(d, sy, sxi)) {
+    load4(d, sy, sxi, nr);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters unchanged
+  }
+  // Z[q][4g..4g+3] of one block from its 8 samples of row q (columns 8 (g & 1) ..)
+  auto block_z = [&](const uint4& w) {
+    uint2 a1, a2;
+    i16_row_digits(w, sh, g < 2, a1, a2);
+    const i4v zero = {0, 0, 0, 0};
+    const i4v p1 = mma_i8(a1, b1, zero), p2 = mma_i8(a2, b1, zero);
+    int pv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pv[v] = p1[v] + (p2[v] << 12);  // P[4g+v][q]
+    const uint2 c1 = make_uint2(pack_low_bytes(pv[0] & 63, pv[1] & 63, pv[2] & 63, pv[3] & 63),
+                                pack_low_bytes((pv[0] >> 6) & 63, (pv[1] >> 6) & 63, (pv[2] >> 6) & 63, (pv[3] >> 6) & 63));
+    const uint2 c2 = make_uint2(pack_low_bytes(pv[0] >> 12, pv[1] >> 12, pv[2] >> 12, pv[3] >> 12), 0u);
+    const i4v z1 = mma_i8(c1, b2, zero), z2 = mma_i8(c2, b2, zero);
+    return make_int4(z1[0] + (z2[0] << 12), z1[1] + (z2[1] << 12), z1[2] + (z2[2] << 12), z1[3] + (z2[3] << 12));
+  };
+  for (;;) {
+    const bool task_end = sxi + 1 == sxe;
+    int nsy = sy, nsxi = sxi + 1, nsxe = sxe;
+    ImgGeom nd = d;
+    bool more = true;
+    if (task_end) {
+      if (++kk == 64) {
+        kk = 0;
+        t0 += 64 * W;
+        tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
+      }
+      more = t0 + kk * W < P.n_rows;
+      if (more) {
+        nsy = __builtin_amdgcn_readlane(tr.sy, kk);
+        nsxi = __builtin_amdgcn_readlane(tr.sx0, kk);
+        nd = task_geom(tr, kk);
+        nsxe = min(nsxi + P.task_strips, nd.sx);
+      }
+    }
+    const uint4 cr[4] = {nr[0], nr[1], nr[2], nr[3]};
+    auto prefetch = [&]() {
+      if (more && interior(nd, nsy, nsxi)) load4(nd, nsy, nsxi, nr);
+    };
+    const int64_t rowblk = d.block_begin + (int64_t)sy * d.bx + sxi * kStripBlocks;
+    if (interior(d, sy, sxi)) {
+      prefetch();
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        *reinterpret_cast<uint4*>(lds + (4 * i + rr) * kI16Row + 4 * cc) = cr[i];
+      wave_lds_sync();
+      uint4 w[kStripBlocks];
+#pragma unroll
+      for (int b = 0; b < kStripBlocks; ++b)
+        w[b] = *reinterpret_cast<const uint4*>(lds + q * kI16Row + 4 * (2 * b + (g & 1)));
+      wave_lds_sync();
+#pragma unroll
+      for (int b = 0; b < kStripBlocks; ++b) store_z<CF_I32, NT>(P.coef, rowblk + b, q, g, block_z(w[b]));
+      __builtin_amdgcn_s_waitcnt(0x0F78);  // all but the 8 stores: the prefetched rows are in
+    } else {
+      prefetch();
+      // edge strip: row q (the last row repeated), columns past the width
+      // repeat the last one
+      const int y = min(sy * 16 + q, d.h - 1);
+      const int b0 = sxi * kStripBlocks;
+      const int nb = min(kStripBlocks, d.bx - b0);
+      const int16_t* row = in + d.offset + (int64_t)y * d.pitch;
+#pragma unroll
+      for (int b = 0; b < kStripBlocks; ++b) {
+        if (b < nb) {
+          const int x0 = (b0 + b) * 16 + 8 * (g & 1);
+          unsigned v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const unsigned lo = (uint16_t)row[min(x0 + 2 * j, d.w - 1)];
+            const unsigned hi = (uint16_t)row[min(x0 + 2 * j + 1, d.w - 1)];
+            v[j] = lo | (hi << 16);
+          }
+          store_z<CF_I32, false>(P.coef, rowblk + b, q, g, block_z(make_uint4(v[0], v[1], v[2], v[3])));
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+    }
+    if (!more) break;
+    sy = nsy;
+    sxi = nsxi;
+    sxe = nsxe;
+    d = nd;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Exact DCT-II comparison transform, Y = C X C^T, operands rounded to BF16
 // or F16, FP32 accumulation.  Stage 2 runs transposed for row-wise stores.
 __device__ __forceinline__ float dct_c(int k, int m) {
@@ -691,6 +855,11 @@ static hipError_t launch_mfma_forward_form(int coef_kind, const Params& P, int g
 hipError_t launch_mfma_forward_i8(int coef_kind, bool nt, const Params& P, int grid, hipStream_t s) {
   return nt ? launch_mfma_forward_form<FWD_I8, true>(coef_kind, P, grid, s)
             : launch_mfma_forward_form<FWD_I8, false>(coef_kind, P, grid, s);
+}
+
+hipError_t launch_mfma_forward_i16(bool nt, const Params& P, int grid, hipStream_t s) {
+  if (nt) ADCT16_MLAUNCH((k_mfma_forward_i16<true>), grid, s, P, P.images, P.rows);
+  ADCT16_MLAUNCH((k_mfma_forward_i16<false>), grid, s, P, P.images, P.rows);
 }
 
 hipError_t launch_mfma_forward(int coef_kind, bool nt, const Params& P, int grid, hipStream_t s) {

@@ -12,7 +12,7 @@ from oracle import transform as tf
 from synth import BASE_SEED, luma_batch, mixed_image, random_blocks_u8
 
 from batch_util import Batch
-from test_gpu_parity import _images_u8
+from test_gpu_parity import _images_i16, _images_u8
 
 pytestmark = pytest.mark.gpu
 
@@ -212,11 +212,68 @@ def test_dct_mfma_error_bound(batch_u8, prec):
     print(f"DCT-II {prec}: max abs error {worst_abs:.4g}, relative to max|Y| {worst_rel:.3g}")
 
 
-@pytest.mark.parametrize("kw", [dict(in_dtype=2, out_dtype=2), dict(out_dtype=4), dict(qmode=3, q=8)])
+@pytest.mark.parametrize("kw", [dict(in_dtype=2, coef_dtype=4, out_dtype=2), dict(coef_dtype=4, out_dtype=4)])
 def test_mfma_unsupported_plans_rejected(kw):
+    # no call of these plans has a matrix-core form (float coefficients, and
+    # no fused matrix-core call for the mode or dtypes)
     mod = A()
     args = dict(in_dtype=mod.U8, coef_dtype=mod.I32, qmode=mod.Q_ZONAL, r=8, backend=mod.BACKEND_MFMA)
     args.update(kw)
     with pytest.raises(mod.Adct16Error) as e:
         mod.Plan([32], [32], [32], [0], **args)
     assert e.value.status == mod.E_MODE
+
+
+def test_mfma_backend_per_call():
+    """A matrix-core plan runs each call that has a matrix-core form there;
+    the others (here the quantiser's fused call) run on the vector ALUs."""
+    import json
+    mod = A()
+    p = mod.Plan([32], [32], [32], [0], in_dtype=mod.I16, coef_dtype=mod.I32, qmode=mod.Q_UNIFORM, q=8,
+                 qcoef_dtype=mod.I16, out_dtype=mod.I16, backend=mod.BACKEND_MFMA)
+    info = json.loads(p.info())
+    assert info["forward_backend"] == "mfma" and info["fused_backend"] == "valu"
+    p = mod.Plan([32], [32], [32], [0], in_dtype=mod.U8, coef_dtype=mod.I32, qmode=mod.Q_ZONAL, r=8,
+                 backend=mod.BACKEND_MFMA)
+    info = json.loads(p.info())
+    assert info["forward_backend"] == "mfma" and info["fused_backend"] == "mfma"
+
+
+def _images_i16_full():
+    """Residual planes plus full-range 16-bit content: uniform samples, the
+    extreme values, and the sign patterns of pairs of rows of T at +-32767 /
+    -32768, which reach the extreme coefficients; widths and heights give
+    interior strips, partial strips and partial blocks."""
+    rng = np.random.default_rng(16)
+    ims = list(_images_i16())
+    ims.append(rng.integers(-32768, 32768, (48, 300)).astype(np.int16))
+    ims.append(rng.integers(-32768, 32768, (32, 256)).astype(np.int16))
+    ims.append(np.full((20, 130), -32768, dtype=np.int16))
+    ims.append(np.full((16, 144), 32767, dtype=np.int16))
+    t = tf.T
+    pats = [np.where(np.outer(t[u], t[v]) > 0, 32767, -32768).astype(np.int16) for u in range(16) for v in range(16)]
+    ims.append(np.concatenate([np.concatenate(pats[k * 16:(k + 1) * 16], axis=1) for k in range(16)], axis=0))
+    return ims
+
+
+@pytest.mark.parametrize("align,strips", [(16, 4), (128, 4), (128, 16)])
+def test_mfma_forward_i16_bit_exact(monkeypatch, align, strips):
+    """16-bit input through the int8 form with three base-64 digits per value
+    (both passes): bit-exact with the oracle and the vector-ALU forward on
+    the whole int16 range."""
+    monkeypatch.setenv("ADCT16_TASK_STRIPS", str(strips))
+    T = torch()
+    mod = A()
+    ims = _images_i16_full()
+    b = Batch(ims, align)
+    coefs = {}
+    for be in (mod.BACKEND_MFMA, mod.BACKEND_VALU):
+        plan = b.plan(coef_dtype=mod.I32, out_dtype=mod.I16, backend=be)
+        coef = b.coef_tensor(T.int32)
+        plan.forward(b.dev, coef)
+        T.cuda.synchronize()
+        coefs[be] = b.split_coef(coef)
+    for i, im in enumerate(ims):
+        want = codec.forward_image(im)
+        assert np.array_equal(coefs[mod.BACKEND_MFMA][i].astype(np.int64), want), f"image {i} {im.shape}"
+        assert np.array_equal(coefs[mod.BACKEND_MFMA][i], coefs[mod.BACKEND_VALU][i])
