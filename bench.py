@@ -338,8 +338,9 @@ def bench_residual(args, A, torch):
             graphs.append(plan.graph(dev, rec, lv, sse, psnr))
             keep.append((plan, dev, rec, lv, sse, psnr))
         run = lambda: [g.launch() for g in graphs]
-        run()
-        ms = _events_ms(run, max(2, args.steps // 4), stream)
+        for _ in range(max(3, args.warmup)):
+            run()
+        ms = _events_ms(run, max(10, args.steps), stream)
         out[f"q{q}_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
         out[f"q{q}_psnr_y_db"] = round(float(keep[0][5][0]), 4)
         del graphs, keep
@@ -353,11 +354,27 @@ def bench_residual(args, A, torch):
         sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
         psnr = torch.zeros(len(hs), dtype=torch.float64, device="cuda")
         f = lambda: plan.compress_and_measure(dev, rec, lv, sse, psnr)
-        f()
-        ms = _events_ms(f, max(2, args.steps // 4), stream)
+        for _ in range(max(3, args.warmup)):
+            f()
+        ms = _events_ms(f, max(10, args.steps), stream)
         out[f"q{q}_one_launch_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
         out[f"q{q}_one_launch_plan"] = json.loads(plan.info())
         del dev, rec, lv
+    # forward only, the whole stream in one launch: vector ALUs against the
+    # int8 matrix-core form (three base-64 digits per value), 2 + 4 B/sample
+    buf, hs, ws, ps, offs = pack_images(planes)
+    dev = torch.from_numpy(buf).cuda()
+    for name, be in (("valu", A.BACKEND_VALU), ("mfma_int8", A.BACKEND_MFMA)):
+        pf = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, out_dtype=A.I16, backend=be)
+        coef = torch.empty(pf.num_blocks * 256, dtype=torch.int32, device="cuda")
+        f = lambda: pf.forward(dev, coef)
+        for _ in range(max(3, args.warmup)):
+            f()
+        ms = _events_ms(f, max(10, args.steps), stream)
+        out[f"forward_{name}_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
+        out[f"forward_{name}_gbs"] = round(6 * npx / (ms * 1e-3) / 1e9, 1)
+        del coef
+    del dev
     return {"metric": "Gsample/s 2D fwd+quant+inv 16x16, 4:2:0 int16 residual stream, graph per frame",
             "value": out["q16_gsample_s"], "unit": "Gsample/s", "n_gpus": 1, "steps": args.steps,
             "dtype": "i16/f32/f64", "data": "synthetic", "higher_is_better": True,

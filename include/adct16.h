@@ -187,7 +187,13 @@ adct16_status adct16_plan_info(adct16_plan plan, char *buf, int32_t buf_len);
 
 /* Section 4, forward: d_in (in_dtype) -> d_coef (coef_dtype, block-major).
  * Evaluates T by the 60-addition factorisation of Eq. (1) (VALU backend)
- * or as exact FP16 matrix-core products (MFMA backend); results are identical. */
+ * or as exact matrix-core products (MFMA backend): FP16 products for 8-bit
+ * input, int8 products with ADCT16_FLAG_MFMA_INT8, and for 16-bit input
+ * (I32 coefficients) int8 products on three base-64 digits per value.
+ * Results are identical in every case.  With the MFMA backend, calls
+ * without a matrix-core form run on the vector ALUs (adct16_plan_info
+ * reports "forward_backend" and "fused_backend"); a plan none of whose
+ * calls has one is rejected with ADCT16_E_MODE. */
 adct16_status adct16_forward(adct16_plan plan, const void *d_in, void *d_coef, void *stream);
 
 /* Section 4, retention (mask modes) or the uniform quantiser (Section 2: S

@@ -303,7 +303,8 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
   if (e != hipSuccess) return hip_fail(e, "autotune set-up");
   // Candidates are timed round-robin, one launch at a time, and each keeps
   // its fastest launch: clocks drift over a few milliseconds of sustained
-  // load, and a sequential sweep would favour whichever ran first.
+  // load, and a sequential sweep would favour whichever ran first (4 to 32
+  // rounds, by the length of a round).
   // (matrix-core candidates also choose the task size)
   struct Cand { int backend, wgpc, grid, tsel; float best; };
   std::vector<Cand> cands;
@@ -313,11 +314,26 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
     for (int ts = 0; ts < 2; ++ts)
       for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_MFMA, wg, grid_for(p, wg), ts, 1e30f});
   void* const tout = p->out_kind == OUT_F32 ? nullptr : w.dout;
-  for (const Cand& c : cands) {  // warm-up (code objects, clocks)
-    adct16_status st = compress_impl(p, c.backend, c.grid, c.tsel, w.din, tout, w.dq, nullptr, nullptr, w.s);
-    if (st != ADCT16_OK) return st;
+  // Warm-up (code objects, and the engine clock, which ramps up under load):
+  // passes over all candidates until about 20 ms of work has run.  Short
+  // launches then also get more timed rounds, so that every candidate is
+  // sampled over about 20 ms of sustained load.
+  float warm_ms = 0, pass_ms = 0;
+  for (int pass = 0; pass < 64 && warm_ms < 20.0f; ++pass) {
+    e = hipEventRecord(w.e0, w.s);
+    if (e != hipSuccess) return hip_fail(e, "autotune event");
+    for (const Cand& c : cands) {
+      adct16_status st = compress_impl(p, c.backend, c.grid, c.tsel, w.din, tout, w.dq, nullptr, nullptr, w.s);
+      if (st != ADCT16_OK) return st;
+    }
+    e = hipEventRecord(w.e1, w.s);
+    if (e == hipSuccess) e = hipEventSynchronize(w.e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&pass_ms, w.e0, w.e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    warm_ms += pass_ms;
   }
-  for (int round = 0; round < 4; ++round) {
+  const int rounds = std::max(4, std::min(32, (int)(20.0f / std::max(pass_ms, 1e-3f))));
+  for (int round = 0; round < rounds; ++round) {
     for (Cand& c : cands) {
       e = hipEventRecord(w.e0, w.s);
       if (e != hipSuccess) return hip_fail(e, "autotune event");
