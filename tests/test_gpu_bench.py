@@ -24,8 +24,9 @@ def _run(workload, frames, **kw):
     import torch
 
     import paper_1606_05562_amd as A
-    fn = {"luma": bench.bench_luma, "ragged": bench.bench_ragged, "residual": bench.bench_residual,
-          "rd": bench.bench_rd, "sweep": bench.bench_sweep, "vector": bench.bench_vector}[workload]
+    fn = {"luma": bench.bench_luma, "uhd": bench.bench_uhd, "ragged": bench.bench_ragged,
+          "residual": bench.bench_residual, "rd": bench.bench_rd, "sweep": bench.bench_sweep,
+          "vector": bench.bench_vector}[workload]
     res = fn(_args(workload, frames, **kw), A, torch)
     line = json.loads(json.dumps(res))  # plain JSON types only
     for key in ("metric", "value", "unit", "n_gpus", "config", "higher_is_better"):
@@ -49,6 +50,11 @@ def test_bench_luma_small():
     cb = line["cpu_baseline"]
     assert cb["kind"] == "oracle" and _positive(cb["value"]) and cb["cores"] >= 1
     assert all(_positive(v) for v in line["variants"].values())
+
+
+def test_bench_uhd_small():
+    line = _run("uhd", 1)
+    assert _positive(line["value"]) and line["roofline"]["bound"] == "hbm"
 
 
 def test_bench_ragged_small():
