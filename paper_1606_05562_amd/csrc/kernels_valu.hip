@@ -21,16 +21,6 @@ namespace adct16 {
 __device__ __forceinline__ us2 as_us2(unsigned v) { return __builtin_bit_cast(us2, v); }
 __device__ __forceinline__ unsigned as_u32(us2 v) { return __builtin_bit_cast(unsigned, v); }
 
-// s_u = 1/sqrt(n_u), n = (16,16,12,8,8,16,12,12,16,12,12,8,8,12,12,12).
-__device__ __forceinline__ double s_of(int u) {
-  constexpr double q4 = 0.25, r12 = 0.28867513459481287, r8 = 0.35355339059327373;
-  switch (u) {
-    case 0: case 1: case 5: case 8: return q4;
-    case 3: case 4: case 11: case 12: return r8;
-    default: return r12;
-  }
-}
-
 struct LaneGeom {
   bool rowok;      // this lane's row (row layout) lies inside the image
   int na, nb;      // valid columns of blocks a / b (0: block absent)
