@@ -119,9 +119,12 @@ enum {
  * Batch descriptor, read by adct16_plan_create (arrays are copied).
  *
  * in_dtype    ADCT16_U8 (8-bit images, Section 4) or ADCT16_I16 (prediction
- *             residuals, Section 5.3).  The MFMA backend needs U8 input,
- *             a mask qmode and U8 out_dtype (else ADCT16_E_MODE); the VALU
- *             backend takes any int16.
+ *             residuals, Section 5.3).  The MFMA backend runs the fused
+ *             call for U8 input, a mask qmode and U8 out_dtype, and the
+ *             forward transform for U8 input to I32/I16 coefficients or
+ *             I16 input to I32 coefficients; a plan with neither form is
+ *             rejected (ADCT16_E_MODE).  The VALU backend takes every
+ *             combination.
  * coef_dtype  output of adct16_forward:
  *               ADCT16_I32  Z = T A T^T exactly;
  *               ADCT16_I16  (U8 input only) Z of the centred block A - 128,

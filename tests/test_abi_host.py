@@ -82,15 +82,25 @@ def test_validation_errors():
     assert _plan_status(backend=5) == A.E_MODE
     assert _plan_status(matrix=A.MATRIX_DCT) == A.E_MODE
     assert _plan_status(matrix=9) == A.E_MODE
+    # size limits: 65536 per side, 2^20 images, 2^36 blocks
+    assert _plan_status(heights=[65537], pitches=[64]) == A.E_SHAPE
+    assert _plan_status(widths=[65537], pitches=[65552]) == A.E_SHAPE
+    n = (1 << 20) + 1
+    assert _plan_status(heights=[1] * n, widths=[1] * n, pitches=[16] * n, offsets=[0] * n) == A.E_SHAPE
+    n = 1 << 13  # 2^13 images of 2^24 blocks
+    assert _plan_status(heights=[65536] * n, widths=[65536] * n, pitches=[65536] * n,
+                        offsets=[i << 32 for i in range(n)]) == A.E_SHAPE
 
 
 def test_valid_desc_reaches_device_check():
     A = _mod()
-    st = _plan_status(qmode=A.Q_ZONAL, r=8)
-    if _have_gpu():
-        assert st == A.OK
-    else:
-        assert st == A.E_DEVICE
+    want = A.OK if _have_gpu() else A.E_DEVICE
+    assert _plan_status(qmode=A.Q_ZONAL, r=8) == want
+    # every limit itself is accepted
+    assert _plan_status(heights=[65536], widths=[65536], pitches=[65536]) == want
+    if not _have_gpu():
+        n = 1 << 20
+        assert _plan_status(heights=[1] * n, widths=[1] * n, pitches=[16] * n, offsets=[0] * n) == want
 
 
 def test_null_arguments():
