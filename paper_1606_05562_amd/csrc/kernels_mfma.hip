@@ -56,20 +56,17 @@ __device__ __forceinline__ void roundtrip8(const unsigned (&x)[kStripBlocks], un
 #pragma unroll
   for (int b0 = 0; b0 < kStripBlocks; b0 += NB) {
     if constexpr (COLLAPSE) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b) out[b0 + b] = round_pack(collapsed_block(x[b0 + b], k));
+      collapsed_blocks<NB>(&x[b0], &out[b0], k);
     } else {
       f4 z[NB];
+      fwd_blocks<NB>(&x[b0], z, k);
+      if constexpr (ZIGZAG) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        z[b] = fwd_block(x[b0 + b], k);
-        if constexpr (ZIGZAG) {
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
           for (int v = 0; v < 4; ++v) z[b][v] = keepz[v] ? z[b][v] : 0.0f;
-        }
       }
-#pragma unroll
-      for (int b = 0; b < NB; ++b) out[b0 + b] = round_pack(inv_block(z[b], k));
+      inv_blocks<NB>(z, &out[b0], k);
     }
   }
 }

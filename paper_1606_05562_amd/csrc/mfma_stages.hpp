@@ -96,54 +96,7 @@ __device__ __forceinline__ uint2 bytes_to_h4(unsigned x) {
                     __builtin_amdgcn_perm(0x64646464u, x, 0x04030402u));
 }
 
-// Forward stages 1-2 for one block: returns Z_c[4g+v][q] (fp32, exact).
-__device__ __forceinline__ f4 fwd_block(unsigned xdw, const MfmaConsts& k) {
-  const f4 c1 = {k.c1, k.c1, k.c1, k.c1};
-  const f4 p = mma16(bytes_to_h4(xdw), k.tq, c1);                 // P_c[4g+v][q]
-  const uint2 ph = make_uint2(pack_h(p[0], p[1]), pack_h(p[2], p[3]));
-  const f4 zero = {0, 0, 0, 0};
-  return mma16(k.tq, ph, zero);                                    // Z_c[4g+v][q]
-}
-
-// Stage 4 from U' = 1536 + U 2^-11 (U'[v] = U[q][4g+v]); returns
-// s[v] = N[q][4g+v] / 2048.  U' lies in [1024, 2048), where fp16 steps by 1:
-// A = floor(U') (the round-toward-zero pack) and B = fract(U') (a multiple
-// of 2^-11 in [0, 1)) are both exact in fp16.
-__device__ __forceinline__ f4 stage4(f4 u, const MfmaConsts& k) {
-  const unsigned A0 = h2bits(u[0], u[1]), A1 = h2bits(u[2], u[3]);
-  const unsigned B0 = h2bits(__builtin_amdgcn_fractf(u[0]), __builtin_amdgcn_fractf(u[1]));
-  const unsigned B1 = h2bits(__builtin_amdgcn_fractf(u[2]), __builtin_amdgcn_fractf(u[3]));
-  // Two chained products, integer digit first.  One K = 32 product would
-  // let the hardware add the integer terms (|sum| up to 16 * 6 * 2048) and
-  // the 2^-11 terms in any order, and such partial sums need 29 significand
-  // bits; chained, every partial sum stays an integer below 2^24 or a
-  // multiple of 2^-11 below 2^12.  (Stage 3's K = 32 product is exact: all
-  // its terms are multiples of 2^-11 and their magnitudes sum below 2^12.)
-  const f4 sa = mma16(k.w4, make_uint2(A0, A1), k.c4);
-  return mma16(k.w4, make_uint2(B0, B1), sa);
-}
-
-// Inverse stages 3-4 from Z_c (already masked); returns s[v] = N[q][4g+v] / 2048.
-__device__ __forceinline__ f4 inv_block(f4 z, const MfmaConsts& k) {
-  const unsigned a0 = h2bits(z[0], z[1]), a1 = h2bits(z[2], z[3]);
-  const unsigned b0 = residual_pair(a0, z[0], z[1]), b1 = residual_pair(a1, z[2], z[3]);
-  const f4 c3 = {1536.0f, 1536.0f, 1536.0f, 1536.0f};
-  const f4 u = mma32(make_uint4(a0, a1, b0, b1), k.w3, c3);       // 1536 + U[q][4g+v] 2^-11
-  return stage4(u, k);
-}
-
-// Separable masks: forward row pass, then U^T = P^T G^T in one contraction
-// (the forward column pass, the retention and the inverse column pass
-// together: T^T diag(w m) T P = T^T (w .* m .* T P)), then stage 4.
-__device__ __forceinline__ f4 collapsed_block(unsigned xdw, const MfmaConsts& k) {
-  const f4 c1 = {k.c1, k.c1, k.c1, k.c1};
-  const f4 p = mma16(bytes_to_h4(xdw), k.tq, c1);                 // P_c[4g+v][q], columns masked
-  const uint2 ph = make_uint2(pack_h(p[0], p[1]), pack_h(p[2], p[3]));
-  const f4 c3 = {1536.0f, 1536.0f, 1536.0f, 1536.0f};
-  const f4 u = mma16(ph, k.gq, c3);                                 // 1536 + U[q][4g+v] 2^-11
-  return stage4(u, k);
-}
-
+// pixel = clamp(floor(N / 2304 + 1/2) + 128, 0, 255) from s = N / 2048
 __device__ __forceinline__ unsigned round_pack(f4 s) {
   constexpr float c = 8.0f / 9.0f;           // fl32(2048 / 2304)
   constexpr float off = 128.0f + 1.0f / 4096.0f;
@@ -153,6 +106,77 @@ __device__ __forceinline__ unsigned round_pack(f4 s) {
   r = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_fmaf(s[2], c, off), 2, r);
   r = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_fmaf(s[3], c, off), 3, r);
   return r;
+}
+
+// The batched forms below carry NB blocks through each stage together: the
+// NB products of a stage are independent, so each one's latency is covered
+// by the others.
+
+// Stage 4 and the rounding for NB blocks, from U' = 1536 + U 2^-11 in v
+// (v[b][j] = U'[q][4g+j]).  U' lies in [1024, 2048), where fp16 steps by 1:
+// A = floor(U') (the round-toward-zero pack) and B = fract(U') (a multiple
+// of 2^-11 in [0, 1)) are both exact in fp16, and
+// s = sum_f w_f T[f][j] (A - 1536) + sum_f w_f T[f][j] B = N[q][4g+j] / 2048.
+// Two chained products, integer digit first.  One K = 32 product would let
+// the hardware add the integer terms (|sum| up to 16 * 6 * 2048) and the
+// 2^-11 terms in any order, and such partial sums need 29 significand bits;
+// chained, every partial sum stays an integer below 2^24 or a multiple of
+// 2^-11 below 2^12.  (Stage 3's K = 32 product is exact: all its terms are
+// multiples of 2^-11 and their magnitudes sum below 2^12.)
+template <int NB>
+__device__ __forceinline__ void stage4_round(f4 (&v)[NB], unsigned* out, const MfmaConsts& k) {
+  uint2 lo[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    lo[b] = make_uint2(h2bits(__builtin_amdgcn_fractf(v[b][0]), __builtin_amdgcn_fractf(v[b][1])),
+                       h2bits(__builtin_amdgcn_fractf(v[b][2]), __builtin_amdgcn_fractf(v[b][3])));
+    v[b] = mma16(k.w4, make_uint2(h2bits(v[b][0], v[b][1]), h2bits(v[b][2], v[b][3])), k.c4);
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) v[b] = mma16(k.w4, lo[b], v[b]);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) out[b] = round_pack(v[b]);
+}
+
+// Forward stages 1-2 for NB blocks: z[b][j] = Z_c[4g+j][q] of block b (fp32, exact).
+template <int NB>
+__device__ __forceinline__ void fwd_blocks(const unsigned* x, f4 (&z)[NB], const MfmaConsts& k) {
+  const f4 c1 = {k.c1, k.c1, k.c1, k.c1};
+  const f4 zero = {0, 0, 0, 0};
+#pragma unroll
+  for (int b = 0; b < NB; ++b) z[b] = mma16(bytes_to_h4(x[b]), k.tq, c1);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) z[b] = mma16(k.tq, make_uint2(pack_h(z[b][0], z[b][1]), pack_h(z[b][2], z[b][3])), zero);
+}
+
+// Inverse stages 3-4 and the rounding for NB blocks of (masked) Z_c.
+template <int NB>
+__device__ __forceinline__ void inv_blocks(f4 (&z)[NB], unsigned* out, const MfmaConsts& k) {
+  const f4 c3 = {1536.0f, 1536.0f, 1536.0f, 1536.0f};
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const unsigned a0 = h2bits(z[b][0], z[b][1]), a1 = h2bits(z[b][2], z[b][3]);
+    const unsigned b0 = residual_pair(a0, z[b][0], z[b][1]), b1 = residual_pair(a1, z[b][2], z[b][3]);
+    z[b] = mma32(make_uint4(a0, a1, b0, b1), k.w3, c3);
+  }
+  stage4_round<NB>(z, out, k);
+}
+
+// Separable masks, NB blocks: forward row pass, then U^T = P^T G^T in one
+// contraction (the forward column pass, the retention and the inverse column
+// pass together: T^T diag(w m) T P = T^T (w .* m .* T P)), then stage 4 and
+// the rounding.
+template <int NB>
+__device__ __forceinline__ void collapsed_blocks(const unsigned* x, unsigned* out, const MfmaConsts& k) {
+  const f4 c1 = {k.c1, k.c1, k.c1, k.c1};
+  const f4 c3 = {1536.0f, 1536.0f, 1536.0f, 1536.0f};
+  f4 v[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) v[b] = mma16(bytes_to_h4(x[b]), k.tq, c1);  // P_c[4g+v][q], columns masked
+#pragma unroll
+  for (int b = 0; b < NB; ++b)                                               // 1536 + U[q][4g+v] 2^-11
+    v[b] = mma16(make_uint2(pack_h(v[b][0], v[b][1]), pack_h(v[b][2], v[b][3])), k.gq, c3);
+  stage4_round<NB>(v, out, k);
 }
 
 }  // namespace adct16
