@@ -241,15 +241,15 @@ __device__ __forceinline__ ImgGeom task_geom(const TaskRegs& tr, int k) {
 }
 
 // Work distribution: wavefront w of W takes tasks w, w + W, w + 2W, ... of
-// the batch (the task table lists runs of up to four strips of one block
-// row, image by image and row by row) and walks each task strip by strip,
-// so that at any time the wavefronts of the chip stream through one
-// contiguous window of the batch, while short tasks keep the work per
-// wavefront even.  The rows of the next interior strip (possibly of the
-// next task) are loaded one strip ahead; the stores of interior strips are
-// unconditional, and each branch ends with an explicit wait for everything
-// but its own stores, so that the loads of the next strip never wait for
-// the stores of the previous one.
+// the batch (the task table lists runs of up to P.task_strips strips, 4 or
+// 16, of one block row, image by image and row by row) and walks each task
+// strip by strip, so that at any time the wavefronts of the chip stream
+// through one contiguous window of the batch, while short tasks keep the
+// work per wavefront even.  The rows of the next interior strip (possibly
+// of the next task) are loaded one strip ahead; the stores of interior
+// strips are unconditional, and each branch ends with an explicit wait for
+// everything but its own stores, so that the loads of the next strip never
+// wait for the stores of the previous one.
 template <bool ZIGZAG, bool COLLAPSE, int OUT, bool NT>
 __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fused(
     Params P, const ImageDesc* __restrict__ images, const RowTask* __restrict__ rows) {
@@ -292,7 +292,6 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   // strips x 2048 pixels x 255^2 < 2^32); a second kernel sums the partials
   // of each image.  No atomics: tasks of one image run on many wavefronts at
   // once, and contended atomics would serialise them.
-  // (tasks hold at most 16 strips)
   unsigned lane_sse = 0, sum_aa = 0, sum_rr = 0, sum_ar = 0;
   int64_t tcur = t0;  // index of the current task
   for (;;) {
