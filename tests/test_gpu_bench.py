@@ -67,6 +67,8 @@ def test_bench_residual_small():
     per_q = line["config"]["per_q"]
     assert all(_positive(per_q[f"q{q}_gsample_s"]) and _positive(per_q[f"q{q}_one_launch_gsample_s"])
                for q in (8, 16, 32))
+    r = line["roofline"]
+    assert r["bound"] == "hbm" and _positive(r["achieved"]) and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
 
 
 def test_bench_rd_small():
@@ -76,6 +78,7 @@ def test_bench_rd_small():
     # coarser steps never cost more bits
     bits = [p["bits_per_sample"] for p in pts]
     assert all(a >= b for a, b in zip(bits, bits[1:]))
+    assert line["roofline"]["bound"] == "hbm" and _positive(line["roofline"]["achieved"])
 
 
 def test_bench_sweep_small():
