@@ -294,6 +294,12 @@ __device__ __forceinline__ void store_row_i16(int16_t* img, int64_t off, int n, 
 // how many of the four (consecutive) blocks exist; both are the same for
 // the whole wavefront.  32-bit kinds: CF_I32, CF_L32 and CF_F32 (float
 // bits); 16-bit: CF_I16C (DC centred by -32768) and CF_L16 (saturated).
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef unsigned v2u_t __attribute__((ext_vector_type(2)));
+
+// The stores are non-temporal: each instruction writes whole cache lines of
+// a block (1 KB or 512 B at a multiple of that offset) that nothing reads
+// again in the same pass.
 template <int CF>
 __device__ __forceinline__ void store_blocks(void* buf, int* lds, int p, int x, int lane, int64_t first, int nb,
                                              const int (&z)[16]) {
@@ -306,15 +312,17 @@ __device__ __forceinline__ void store_blocks(void* buf, int* lds, int p, int x, 
       int4 v = *reinterpret_cast<const int4*>(lds + m * kSlot + u * kRow + 4 * j);
       const int64_t off = (first + m) * 256 + u * 16 + 4 * j;
       if constexpr (CF == CF_I32 || CF == CF_L32 || CF == CF_F32) {
-        *reinterpret_cast<int4*>(reinterpret_cast<int*>(buf) + off) = v;
+        const v4i_t w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<v4i_t*>(reinterpret_cast<int*>(buf) + off));
       } else {
         if constexpr (CF == CF_I16C) {
           if (lane == 0) v.x -= 32768;
         } else {
           v = make_int4(sat16(v.x), sat16(v.y), sat16(v.z), sat16(v.w));
         }
-        *reinterpret_cast<uint2*>(reinterpret_cast<int16_t*>(buf) + off) =
-            make_uint2(((unsigned)v.x & 0xffffu) | ((unsigned)v.y << 16), ((unsigned)v.z & 0xffffu) | ((unsigned)v.w << 16));
+        const v2u_t w = {((unsigned)v.x & 0xffffu) | ((unsigned)v.y << 16),
+                         ((unsigned)v.z & 0xffffu) | ((unsigned)v.w << 16)};
+        __builtin_nontemporal_store(w, reinterpret_cast<v2u_t*>(reinterpret_cast<int16_t*>(buf) + off));
       }
     }
   }
@@ -327,7 +335,8 @@ __device__ __forceinline__ void store_blocks(void* buf, int* lds, int p, int x, 
 // x of the lane group's block.
 // The loads are unconditional (a missing block reads block `safe`, which
 // exists, and is zeroed afterwards): loads under a branch would each be
-// waited for before the branch joins.
+// waited for before the branch joins.  Like the stores above they are
+// non-temporal (whole lines, read once).
 template <int CF>
 __device__ __forceinline__ void fetch_blocks(const void* buf, int lane, int64_t first, int nb, int64_t safe,
                                              int4 (&v)[4]) {
@@ -337,9 +346,10 @@ __device__ __forceinline__ void fetch_blocks(const void* buf, int lane, int64_t 
     const int64_t off = (m < nb ? first + m : safe) * 256 + u * 16 + 4 * j;
     int4 t;
     if constexpr (CF == CF_I32 || CF == CF_L32) {
-      t = *reinterpret_cast<const int4*>(reinterpret_cast<const int*>(buf) + off);
+      const v4i_t w = __builtin_nontemporal_load(reinterpret_cast<const v4i_t*>(reinterpret_cast<const int*>(buf) + off));
+      t = make_int4(w.x, w.y, w.z, w.w);
     } else {
-      const uint2 w = *reinterpret_cast<const uint2*>(reinterpret_cast<const int16_t*>(buf) + off);
+      const v2u_t w = __builtin_nontemporal_load(reinterpret_cast<const v2u_t*>(reinterpret_cast<const int16_t*>(buf) + off));
       t = make_int4((int)(short)(w.x & 0xffffu), ((int)w.x) >> 16, (int)(short)(w.y & 0xffffu), ((int)w.y) >> 16);
       if constexpr (CF == CF_I16C) {
         if (lane == 0) t.x += 32768;
