@@ -263,9 +263,14 @@ __device__ __forceinline__ unsigned sse_u8(uint4 o, uint4 r, int n) {
   return oo + rr - 2u * orr;
 }
 
+// Whole block rows of the reconstruction are stored non-temporally (written
+// once, never read back in the pass).
+typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void store_row_u8(uint8_t* img, int64_t off, int n, uint4 v) {
   if (n >= 16) {
-    *reinterpret_cast<uint4*>(img + off) = v;
+    const v4u_t w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<v4u_t*>(img + off));
   } else {
     for (int k = 0; k < n; ++k) img[off + k] = (uint8_t)byte_of(v, k);
   }
@@ -277,8 +282,9 @@ __device__ __forceinline__ void store_row_i16(int16_t* img, int64_t off, int n, 
     unsigned w[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) w[k] = ((unsigned)v[2 * k] & 0xffffu) | ((unsigned)v[2 * k + 1] << 16);
-    q[0] = make_uint4(w[0], w[1], w[2], w[3]);
-    q[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    const v4u_t s0 = {w[0], w[1], w[2], w[3]}, s1 = {w[4], w[5], w[6], w[7]};
+    __builtin_nontemporal_store(s0, reinterpret_cast<v4u_t*>(q));
+    __builtin_nontemporal_store(s1, reinterpret_cast<v4u_t*>(q) + 1);
   } else {
     for (int k = 0; k < n; ++k) img[off + k] = (int16_t)v[k];
   }
