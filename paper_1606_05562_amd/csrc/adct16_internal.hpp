@@ -39,16 +39,21 @@ struct ImageDesc {
 };
 static_assert(sizeof(ImageDesc) == 56, "ImageDesc layout");
 
-// Up to P.task_strips (at most 16) consecutive strips of one block row of
-// one image: the unit of work that the matrix-core kernels deal out to
-// wavefronts cyclically (strips sx0 .. min(sx0 + task_strips, sx) - 1 of
-// block row sy).  Plans hold task tables for 4-strip tasks and for 16-strip
-// tasks (whole rows of images up to 2048 pixels wide); the autotuner picks.
+// A run of consecutive strips of one block row of one image: the unit of
+// work that the matrix-core kernels deal out to wavefronts cyclically.
+// Each block row of sx strips is split into k = ceil(sx / N) runs of equal
+// length (within one strip): run j covers strips j sx / k .. (j + 1) sx / k
+// - 1.  Plans hold the tables for N = 4 and N = 16 (whole rows of images up
+// to 2048 pixels wide, two runs of 15 strips for 3840); the autotuner picks.
+// Equal runs keep the wavefronts that share a row in step.
 constexpr int kTaskStripsShort = 4, kTaskStripsLong = 16;
 struct RowTask {
   int32_t img;
-  int16_t sy, sx0;
+  int16_t sy;
+  int16_t run;  // first strip (bits 0-9, sx0 < 512) | strip count << 10 (1..16)
 };
+__host__ __device__ constexpr int task_run_first(int run) { return run & 1023; }
+__host__ __device__ constexpr int task_run_count(int run) { return run >> 10; }
 static_assert(sizeof(RowTask) == 8, "RowTask layout");
 
 // Per-plan constant tables, indexed u * 16 + v.
@@ -95,7 +100,7 @@ struct Params {
   int64_t n_rows;
   uint32_t* task_sse;   // per-task SSE partials (matrix-core fused kernel)
   const int64_t* task_first;  // index of each image's first task (n_images + 1 entries)
-  int32_t task_strips;  // strips per task (4 or 16)
+  int32_t task_strips;  // longest run of the task table (4 or 16)
   int32_t pad1;
 };
 

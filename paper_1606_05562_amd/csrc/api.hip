@@ -548,8 +548,13 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
     p->tasks[ts].strips = n;
     for (size_t i = 0; i < images.size(); ++i) {
       first[ts].push_back((int64_t)rows[ts].size());
+      // k = ceil(sx / n) runs of equal length (within one strip) per block row
+      const int sx = images[i].sx, k = (sx + n - 1) / n;
       for (int sy = 0; sy < images[i].by; ++sy)
-        for (int sx0 = 0; sx0 < images[i].sx; sx0 += n) rows[ts].push_back(RowTask{(int32_t)i, (int16_t)sy, (int16_t)sx0});
+        for (int j = 0; j < k; ++j) {
+          const int a = (int)((int64_t)j * sx / k), b = (int)((int64_t)(j + 1) * sx / k);
+          rows[ts].push_back(RowTask{(int32_t)i, (int16_t)sy, (int16_t)(a | ((b - a) << 10))});
+        }
     }
     first[ts].push_back((int64_t)rows[ts].size());
     p->tasks[ts].n_rows = (int64_t)rows[ts].size();

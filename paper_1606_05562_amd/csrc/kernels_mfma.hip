@@ -195,7 +195,7 @@ __device__ __forceinline__ void edge_strip(const ImgGeom& d, int sy, int sxi, co
 // with one set of vector loads; the task in use is read back with readlane.
 // The table latency is paid once per 64 tasks instead of once per task.
 struct TaskRegs {
-  int sy, sx0, off_lo, off_hi, h, w, pitch, bx, sx, bb_lo, bb_hi;
+  int sy, run, off_lo, off_hi, h, w, pitch, bx, sx, bb_lo, bb_hi;
 };
 
 __device__ __forceinline__ TaskRegs gather_tasks(const ImageDesc* __restrict__ images,
@@ -208,7 +208,7 @@ __device__ __forceinline__ TaskRegs gather_tasks(const ImageDesc* __restrict__ i
     const ImageDesc* d = images + e.img;
     const int64_t off = d->offset;
     tr.sy = e.sy;
-    tr.sx0 = e.sx0;
+    tr.run = e.run;
     tr.off_lo = (int)(uint32_t)off;
     tr.off_hi = (int)(off >> 32);
     tr.h = d->h;
@@ -241,8 +241,8 @@ __device__ __forceinline__ ImgGeom task_geom(const TaskRegs& tr, int k) {
 }
 
 // Work distribution: wavefront w of W takes tasks w, w + W, w + 2W, ... of
-// the batch (the task table lists runs of up to P.task_strips strips, 4 or
-// 16, of one block row, image by image and row by row) and walks each task
+// the batch (the task table lists equal runs of at most 4 or 16 strips of
+// one block row, image by image and row by row) and walks each task
 // strip by strip, so that at any time the wavefronts of the chip stream
 // through one contiguous window of the batch, while short tasks keep the
 // work per wavefront even.  The rows of the next interior strip (possibly
@@ -268,9 +268,10 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   TaskRegs tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
   int kk = 0;  // current task: t0 + kk W
   int sy = __builtin_amdgcn_readlane(tr.sy, 0);
-  int sxi = __builtin_amdgcn_readlane(tr.sx0, 0);
+  const int run0 = __builtin_amdgcn_readlane(tr.run, 0);
+  int sxi = task_run_first(run0);
   ImgGeom d = task_geom(tr, 0);
-  int sxe = min(sxi + P.task_strips, d.sx);  // end of the current task
+  int sxe = min(sxi + task_run_count(run0), d.sx);  // end of the current task
   auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
     return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
   };
@@ -309,9 +310,10 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
       more = t0 + kk * W < P.n_rows;
       if (more) {
         nsy = __builtin_amdgcn_readlane(tr.sy, kk);
-        nsxi = __builtin_amdgcn_readlane(tr.sx0, kk);
+        const int nrun = __builtin_amdgcn_readlane(tr.run, kk);
+        nsxi = task_run_first(nrun);
         nd = task_geom(tr, kk);
-        nsxe = min(nsxi + P.task_strips, nd.sx);
+        nsxe = min(nsxi + task_run_count(nrun), nd.sx);
       }
     }
     const uint4 cr[2] = {nr[0], nr[1]};
@@ -518,9 +520,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P, const 
   TaskRegs tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
   int kk = 0;
   int sy = __builtin_amdgcn_readlane(tr.sy, 0);
-  int sxi = __builtin_amdgcn_readlane(tr.sx0, 0);
+  const int run0 = __builtin_amdgcn_readlane(tr.run, 0);
+  int sxi = task_run_first(run0);
   ImgGeom d = task_geom(tr, 0);
-  int sxe = min(sxi + P.task_strips, d.sx);
+  int sxe = min(sxi + task_run_count(run0), d.sx);
   auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
     return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
   };
@@ -548,9 +551,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P, const 
       more = t0 + kk * W < P.n_rows;
       if (more) {
         nsy = __builtin_amdgcn_readlane(tr.sy, kk);
-        nsxi = __builtin_amdgcn_readlane(tr.sx0, kk);
+        const int nrun = __builtin_amdgcn_readlane(tr.run, kk);
+        nsxi = task_run_first(nrun);
         nd = task_geom(tr, kk);
-        nsxe = min(nsxi + P.task_strips, nd.sx);
+        nsxe = min(nsxi + task_run_count(nrun), nd.sx);
       }
     }
     const uint4 cr[2] = {nr[0], nr[1]};
@@ -666,9 +670,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward_i16(Params P, co
   TaskRegs tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
   int kk = 0;
   int sy = __builtin_amdgcn_readlane(tr.sy, 0);
-  int sxi = __builtin_amdgcn_readlane(tr.sx0, 0);
+  const int run0 = __builtin_amdgcn_readlane(tr.run, 0);
+  int sxi = task_run_first(run0);
   ImgGeom d = task_geom(tr, 0);
-  int sxe = min(sxi + P.task_strips, d.sx);
+  int sxe = min(sxi + task_run_count(run0), d.sx);
   auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
     return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
   };
@@ -715,9 +720,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward_i16(Params P, co
       more = t0 + kk * W < P.n_rows;
       if (more) {
         nsy = __builtin_amdgcn_readlane(tr.sy, kk);
-        nsxi = __builtin_amdgcn_readlane(tr.sx0, kk);
+        const int nrun = __builtin_amdgcn_readlane(tr.run, kk);
+        nsxi = task_run_first(nrun);
         nd = task_geom(tr, kk);
-        nsxe = min(nsxi + P.task_strips, nd.sx);
+        nsxe = min(nsxi + task_run_count(nrun), nd.sx);
       }
     }
     const uint4 cr[4] = {nr[0], nr[1], nr[2], nr[3]};
