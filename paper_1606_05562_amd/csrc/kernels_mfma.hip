@@ -156,40 +156,6 @@ __device__ __forceinline__ unsigned load_dword_edge(const uint8_t* img, const Im
   return r;
 }
 
-// Edge strip: fewer than 8 blocks, a partial last block (columns past the
-// width repeat the last one) and / or rows past the height (the last row
-// repeated, neither written nor counted).  Dword loads and stores.
-template <bool ZIGZAG, bool COLLAPSE, int OUT>
-__device__ __forceinline__ void edge_strip(const ImgGeom& d, int sy, int sxi, const uint8_t* in, uint8_t* outp,
-                                           const MfmaConsts& k, const bool (&keepz)[4], int g, int q,
-                                           unsigned& sse) {
-  const int y0 = sy * 16;
-  const int y = min(y0 + q, d.h - 1);
-  const bool rowok = (y0 + q) < d.h;
-  const int b0 = sxi * kStripBlocks;
-  const int64_t off = d.offset + (int64_t)y * d.pitch;
-  const int nb = min(kStripBlocks, d.bx - b0);
-  unsigned x[kStripBlocks], out[kStripBlocks];
-#pragma unroll
-  for (int b = 0; b < kStripBlocks; ++b) x[b] = b < nb ? load_dword_edge(in, d, y, (b0 + b) * 16 + 4 * g) : 0u;
-  roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
-  if (!rowok) return;
-#pragma unroll
-  for (int b = 0; b < kStripBlocks; ++b) {
-    const int x0 = (b0 + b) * 16 + 4 * g;
-    const int n = b < nb ? min(4, d.w - x0) : 0;
-    if (n > 0) {
-      if constexpr (OUT == OUT_U8) {
-        uint8_t* o = outp + off + x0;
-        if (n == 4) *reinterpret_cast<unsigned*>(o) = out[b];
-        else for (int j = 0; j < n; ++j) o[j] = (uint8_t)(out[b] >> (8 * j));
-      }
-      const unsigned m = n >= 4 ? 0xffffffffu : ((1u << (8 * n)) - 1u);
-      sse += sse4(x[b] & m, out[b] & m);
-    }
-  }
-}
-
 // Task registers: lane k of a wavefront holds the table entry and the image
 // geometry of its task t0 + k W (the k-th of its next 64 tasks), gathered
 // with one set of vector loads; the task in use is read back with readlane.
@@ -275,19 +241,21 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
     return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
   };
-  // this lane's first 16 bytes of strip (ssy, ssxi): row 16 ssy + r, block 8 ssxi + c
-  auto lane_off = [&](const ImgGeom& dd, int ssy, int ssxi) {
-    return dd.offset + (int64_t)(ssy * 16 + r) * dd.pitch + ssxi * (16 * kStripBlocks) + 16 * c;
+  // this lane's 16 bytes of strip (ssy, ssxi) in half hh: row 16 ssy + 8 hh + r,
+  // block 8 ssxi + c.  Edge strips read inside the image: rows past the
+  // height read the last row (its edge extension), and a block past the last
+  // reads the row's first block (its result is neither stored nor counted).
+  auto lane_off = [&](const ImgGeom& dd, int ssy, int ssxi, int hh) {
+    const int y = min(ssy * 16 + 8 * hh + r, dd.h - 1);
+    const int blk = ssxi * kStripBlocks + c;
+    return dd.offset + (int64_t)y * dd.pitch + (blk < dd.bx ? 16 * blk : 0);
   };
-  uint4 nr[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
-  if (interior(d, sy, sxi)) {
-    const int64_t o = lane_off(d, sy, sxi);
-    nr[0] = ld_row16<NT>(in + o);
-    nr[1] = ld_row16<NT>(in + o + 8 * (int64_t)d.pitch);
-    // complete these loads here rather than at the loop head, where the
-    // wait would also cover the previous strip's stores
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters unchanged
-  }
+  uint4 nr[2];
+  nr[0] = ld_row16<NT>(in + lane_off(d, sy, sxi, 0));
+  nr[1] = ld_row16<NT>(in + lane_off(d, sy, sxi, 1));
+  // complete these loads here rather than at the loop head, where the wait
+  // would also cover the previous strip's stores
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters unchanged
   // SSE: per lane over the current task, reduced across the wavefront at
   // the end of the task and stored as that task's partial (at most 16
   // strips x 2048 pixels x 255^2 < 2^32); a second kernel sums the partials
@@ -320,10 +288,9 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
     // issued inside each branch below, so that no load is outstanding where
     // the branches join
     auto prefetch = [&]() {
-      if (more && interior(nd, nsy, nsxi)) {
-        const int64_t o = lane_off(nd, nsy, nsxi);
-        nr[0] = ld_row16<NT>(in + o);
-        nr[1] = ld_row16<NT>(in + o + 8 * (int64_t)nd.pitch);
+      if (more) {
+        nr[0] = ld_row16<NT>(in + lane_off(nd, nsy, nsxi, 0));
+        nr[1] = ld_row16<NT>(in + lane_off(nd, nsy, nsxi, 1));
       }
     };
     if (interior(d, sy, sxi)) {
@@ -334,9 +301,8 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
       if constexpr (OUT == OUT_U8) {
         uint4 orow[2];
         operands_to_rows(lds, r, c, g, q, out, orow);
-        const int64_t o = lane_off(d, sy, sxi);
-        st_row16<NT>(outp + o, orow[0]);
-        st_row16<NT>(outp + o + 8 * (int64_t)d.pitch, orow[1]);
+        st_row16<NT>(outp + lane_off(d, sy, sxi, 0), orow[0]);
+        st_row16<NT>(outp + lane_off(d, sy, sxi, 1), orow[1]);
         // the prefetched rows were issued before these two stores: wait for
         // everything but the stores (vmcnt(2))
         __builtin_amdgcn_s_waitcnt(0x0F72);
@@ -352,8 +318,49 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
         sum_ar = __builtin_amdgcn_udot4(x[b], out[b], sum_ar, false);
       }
     } else {
+      // edge strip: fewer than 8 blocks, a partial last block and / or rows
+      // past the height.  The rows were loaded as for interior strips; the
+      // partial block's row is extended by its last pixel, and only pixels
+      // inside the image are stored and counted.
       prefetch();
-      edge_strip<ZIGZAG, COLLAPSE, OUT>(d, sy, sxi, in, outp, k, keepz, g, q, lane_sse);
+      const int blk = sxi * kStripBlocks + c;
+      const int nvalid = d.w - 16 * blk;  // pixels of this lane's block row inside the image
+      uint4 er[2] = {cr[0], cr[1]};
+      if (nvalid > 0 && nvalid < 16) {
+        er[0] = extend_bytes(er[0], nvalid);
+        er[1] = extend_bytes(er[1], nvalid);
+      }
+      unsigned x[kStripBlocks], out[kStripBlocks];
+      rows_to_operands(lds, r, c, g, q, er, x);
+      roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
+      if constexpr (OUT == OUT_U8) {
+        uint4 orow[2];
+        operands_to_rows(lds, r, c, g, q, out, orow);
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int y = sy * 16 + 8 * hh + r;
+          if (y < d.h && nvalid > 0) {
+            uint8_t* o = outp + d.offset + (int64_t)y * d.pitch + 16 * blk;
+            if (nvalid >= 16) {
+              *reinterpret_cast<uint4*>(o) = orow[hh];
+            } else {
+              for (int j = 0; j < nvalid; ++j) o[j] = (uint8_t)byte_of(orow[hh], j);
+            }
+          }
+        }
+      }
+      // SSE over the pixels inside the image, in the operand layout (lane
+      // 16 g + q: row q, columns 4g..4g+3 of each block)
+      if (sy * 16 + q < d.h) {
+#pragma unroll
+        for (int b = 0; b < kStripBlocks; ++b) {
+          const int n = min(4, d.w - ((sxi * kStripBlocks + b) * 16 + 4 * g));
+          if (n > 0) {
+            const unsigned m = n >= 4 ? 0xffffffffu : ((1u << (8 * n)) - 1u);
+            lane_sse += sse4(x[b] & m, out[b] & m);
+          }
+        }
+      }
       __builtin_amdgcn_s_waitcnt(0x0F70);
     }
     if (task_end) {
