@@ -131,12 +131,13 @@ def test_mfma_ragged(align):
 
 @pytest.mark.parametrize("strips", [4, 16])
 def test_mfma_task_sizes(monkeypatch, strips):
-    """Both task tables (tasks of up to 4 or 16 strips of a block row), on
-    images whose block rows hold fewer and more strips than a task, through
-    the fused kernel and both forward forms."""
+    """Both task tables (equal runs of at most 4 or 16 strips of a block
+    row), on images whose block rows hold fewer and more strips than a run
+    and split into runs of unequal length (2050 pixels: 17 strips, 8 + 9 or
+    3 + 3 + 4 + 3 + 4), through the fused kernel and both forward forms."""
     monkeypatch.setenv("ADCT16_TASK_STRIPS", str(strips))
     T = torch()
-    sizes = [(48, 16), (40, 130), (33, 2050), (20, 4000), (272, 384), (70, 1920), (16, 2048)]
+    sizes = [(48, 16), (40, 130), (33, 2050), (20, 4000), (272, 384), (70, 1920), (16, 2048), (24, 3840)]
     ims = [mixed_image(BASE_SEED + 6, k, h, w) for k, (h, w) in enumerate(sizes)]
     b = Batch(ims, 128)
     plan = b.plan(coef_dtype=A().I32, qmode=A().Q_ZONAL, r=6, backend=A().BACKEND_MFMA)
