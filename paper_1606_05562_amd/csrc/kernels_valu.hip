@@ -22,6 +22,7 @@ __device__ __forceinline__ us2 as_us2(unsigned v) { return __builtin_bit_cast(us
 __device__ __forceinline__ unsigned as_u32(us2 v) { return __builtin_bit_cast(unsigned, v); }
 
 struct LaneGeom {
+  bool full;       // the strip is 8 whole blocks wide (the same in every lane): no column is extended
   bool rowok;      // this lane's row (row layout) lies inside the image
   int na, nb;      // valid columns of blocks a / b (0: block absent)
   int64_t rowoff;  // element offset of the (clamped) row
@@ -31,6 +32,7 @@ struct LaneGeom {
 
 __device__ __forceinline__ LaneGeom lane_geom(const StripCursor& c, int x, int p) {
   LaneGeom g;
+  g.full = (c.sxi + 1) * (16 * kStripBlocks) <= c.d.w;
   const int y0 = c.sy * 16;
   g.rowok = (y0 + x) < c.d.h;
   const int y = min(y0 + x, c.d.h - 1);
@@ -56,15 +58,18 @@ __device__ __forceinline__ uint4 load_row_u8(const uint8_t* img, int64_t off, in
 }
 
 // 16 int16 samples from two raw 16-byte words; when 0 < n < 16 the row is
-// extended by its last valid sample (n >= 16: no extension).
-__device__ __forceinline__ void unpack_i16(const uint4& q0, const uint4& q1, int n, int (&v)[16]) {
+// extended by its last valid sample (n >= 16: no extension).  `full` (the
+// same in every lane) says that no lane has n < 16, which skips the
+// extension's selects altogether.
+__device__ __forceinline__ void unpack_i16(const uint4& q0, const uint4& q1, int n, int (&v)[16],
+                                           bool full = false) {
   const unsigned w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     v[2 * k] = (int)(short)(w[k] & 0xffffu);
     v[2 * k + 1] = ((int)w[k]) >> 16;
   }
-  if (n < 16) {
+  if (!full && n < 16) {
     int last = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) last = (k == n - 1) ? v[k] : last;
@@ -137,6 +142,7 @@ __device__ __forceinline__ void load_rows_u8(const uint8_t* img, const LaneGeom&
 }
 
 __device__ __forceinline__ void fix_edges_u8(const LaneGeom& g, uint4& ra, uint4& rb) {
+  if (g.full) return;
   if (g.na > 0 && g.na < 16) ra = extend_bytes(ra, g.na);
   if (g.nb > 0 && g.nb < 16) rb = extend_bytes(rb, g.nb);
 }
@@ -179,8 +185,8 @@ __device__ __forceinline__ void widen_u8(const us2 (&Z)[16], int x, int (&za)[16
 template <int MAT>
 __device__ __forceinline__ void forward_i16_rows(const RawI16& r, const LaneGeom& g, int* lds, int x, int p,
                                                  int (&za)[16], int (&zb)[16]) {
-  unpack_i16(r.a0, r.a1, g.na, za);
-  unpack_i16(r.b0, r.b1, g.nb, zb);
+  unpack_i16(r.a0, r.a1, g.na, za, g.full);
+  unpack_i16(r.b0, r.b1, g.nb, zb, g.full);
   m_fwd<MAT>(za);
   m_fwd<MAT>(zb);
   transpose_rows_to_cols(lds, p, x, za);
@@ -622,7 +628,8 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
           if (g.na > 0) store_row_u8(o, g.rowoff + g.xa, g.na, qa);
           if (g.nb > 0) store_row_u8(o, g.rowoff + g.xb, g.nb, qb);
         }
-        acc.lane += (g.na > 0 ? sse_u8(ra, qa, g.na) : 0u) + (g.nb > 0 ? sse_u8(rb, qb, g.nb) : 0u);
+        if (g.full) acc.lane += sse_u8(ra, qa, 16) + sse_u8(rb, qb, 16);
+        else acc.lane += (g.na > 0 ? sse_u8(ra, qa, g.na) : 0u) + (g.nb > 0 ? sse_u8(rb, qb, g.nb) : 0u);
       }
     } else {
       int pa[16], pb[16];
@@ -643,12 +650,22 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_VALU_MIN_WG) void k_fused(Par
           if (g.na > 0) store_row_i16(o, g.rowoff + g.xa, g.na, pa);
           if (g.nb > 0) store_row_i16(o, g.rowoff + g.xb, g.nb, pb);
         }
+        // |error| < 2^16, so its square is the low 32 bits of a 24-bit product
         unsigned long long s = 0;
+        if (g.full) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const long long da = (k < g.na) ? (long long)(ia[k] - pa[k]) : 0;
-          const long long db = (k < g.nb) ? (long long)(ib[k] - pb[k]) : 0;
-          s += (unsigned long long)(da * da) + (unsigned long long)(db * db);
+          for (int k = 0; k < 16; ++k) {
+            s += (unsigned)__mul24(ia[k] - pa[k], ia[k] - pa[k]);
+            s += (unsigned)__mul24(ib[k] - pb[k], ib[k] - pb[k]);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const int da = (k < g.na) ? ia[k] - pa[k] : 0;
+            const int db = (k < g.nb) ? ib[k] - pb[k] : 0;
+            s += (unsigned)__mul24(da, da);
+            s += (unsigned)__mul24(db, db);
+          }
         }
         acc.lane += s;
       }
