@@ -181,6 +181,43 @@ def test_mfma_full_size_sampled():
     assert T.equal(out, out2) and T.equal(sse, sse2)
 
 
+def test_full_size_bench_configuration():
+    """The default benchmark's call, exactly as bench.py makes it (256 luma
+    frames 1920x1088, zonal r = 8, backend and launch shape chosen by the
+    autotuner): sampled frames completely against the oracle, and every
+    pixel, SSE and PSNR of the batch against the vector adder kernel."""
+    import json
+    T = torch()
+    mod = A()
+    n, h, w = 256, 1088, 1920
+    frames = luma_batch(BASE_SEED + 2, n, h, w)  # the benchmark's frames
+    dev = T.from_numpy(frames.reshape(-1)).cuda()
+    offs = [i * h * w for i in range(n)]
+    plan = mod.Plan([h] * n, [w] * n, [w] * n, offs, in_dtype=mod.U8, coef_dtype=mod.I32, qmode=mod.Q_ZONAL,
+                    r=8, backend=mod.BACKEND_AUTO, flags=mod.FLAG_AUTOTUNE)
+    info = json.loads(plan.info())
+    out = T.empty_like(dev)
+    sse = T.zeros(n, dtype=T.int64, device="cuda")
+    psnr = T.zeros(n, dtype=T.float64, device="cuda")
+    for _ in range(2):  # a replay sees the state the first call left
+        plan.compress_and_measure(dev, out, None, sse, psnr)
+    T.cuda.synchronize()
+    keep = codec.mask_zonal(8)
+    for t in (0, 131, 255):
+        got = out[t * h * w:(t + 1) * h * w].cpu().numpy().reshape(h, w)
+        want, s, p = codec.compress_kept(frames[t], keep)
+        assert np.array_equal(got, want), f"frame {t} ({info})"
+        assert int(sse[t]) == s and abs(float(psnr[t]) - p) <= 1e-3, f"frame {t}"
+    ref = mod.Plan([h] * n, [w] * n, [w] * n, offs, in_dtype=mod.U8, coef_dtype=mod.I32, qmode=mod.Q_ZONAL,
+                   r=8, backend=mod.BACKEND_VALU)
+    out2 = T.empty_like(dev)
+    sse2 = T.zeros(n, dtype=T.int64, device="cuda")
+    psnr2 = T.zeros(n, dtype=T.float64, device="cuda")
+    ref.compress_and_measure(dev, out2, None, sse2, psnr2)
+    T.cuda.synchronize()
+    assert T.equal(out, out2) and T.equal(sse, sse2) and T.equal(psnr, psnr2)
+
+
 # ----------------------------------------------------------------------------
 # Exact DCT-II on BF16 / F16 operands (comparison transform).
 
