@@ -203,3 +203,43 @@ def test_transform_measures_errors():
     assert e.value.status == A.E_MODE
     assert A.lib().adct16_transform_matrix(0, None) == A.E_NULL
     assert A.lib().adct16_transform_measures(None, 0.95, None) == A.E_NULL
+
+
+# ----------------------------------------------------------------------------
+# A plain C99 client (tests/abi_client.c) built with gcc against the header
+# and the library alone: the header stands on its own as C, and the ABI is
+# usable without Python.
+
+def _build_c_client(tmp_path):
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    lib_dir = os.path.join(ROOT, "paper_1606_05562_amd")
+    if not os.path.exists(os.path.join(lib_dir, "libadct16.so")):
+        pytest.fail("libadct16.so is not built")
+    exe = str(tmp_path / "abi_client")
+    cmd = [gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+           os.path.join(ROOT, "tests", "abi_client.c"), "-o", exe,
+           "-L", lib_dir, "-ladct16", "-L", "/opt/rocm/lib", "-lamdhip64", "-lm",
+           f"-Wl,-rpath,{lib_dir}", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def test_c_client_host(tmp_path):
+    import subprocess
+    exe = _build_c_client(tmp_path)
+    r = subprocess.run([exe, "host"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "abi_client host ok" in r.stdout, r.stdout + r.stderr
+
+
+@pytest.mark.gpu
+def test_c_client_device(tmp_path):
+    import subprocess
+    exe = _build_c_client(tmp_path)
+    r = subprocess.run([exe, "device"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "abi_client device ok" in r.stdout, r.stdout + r.stderr
