@@ -29,6 +29,8 @@ HBM_PEAK_GBS = 8000.0
 N_FRAMES, H, W = 256, 1088, 1920
 COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_hbm_counters.json")
 SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_sq_counters.json")
+RES_COUNTERS = os.path.join(ROOT, "profiles", "fused_residual8_hbm_counters.json")
+RES_SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_residual8_sq_counters.json")
 # Issue capacity of the chip's 256 CUs x 4 SIMDs at 2.4 GHz: a wave64 VALU
 # instruction occupies its 16-lane SIMD for 4 cycles, and each SIMD's matrix
 # core has 2.4e9 busy cycles per second.
@@ -47,6 +49,8 @@ def _parse():
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--backend", choices=["auto", "valu", "mfma"], default="auto")
     ap.add_argument("--frames", type=int, default=None)
+    ap.add_argument("--q", type=int, choices=[8, 16, 32], default=None,
+                    help="residual workload: one uniform step instead of all three")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=128)
@@ -85,17 +89,28 @@ def _events_ms(fn, reps, stream):
     return e0.elapsed_time(e1) / reps
 
 
-def _traffic(kernel_name: str):
-    """HBM bytes per launch of the fused kernel from committed rocprofv3 PMC
-    runs (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter
-    reads for a plain device copy of known size); None if the kernel
-    sources changed since the counters were taken."""
+def _load_counters(path: str, kernel_name: str, workload: dict):
+    """A committed counter summary, if it was taken on this kernel's current
+    device sources and on this workload (every key of `workload` equal)."""
     try:
-        with open(COUNTERS) as f:
+        with open(path) as f:
             c = json.load(f)
     except OSError:
         return None
     if c.get("source_sha256") != kernel_source_hash(kernel_name) or c.get("kernel") != kernel_name:
+        return None
+    if any(c.get(k) != v for k, v in workload.items()):
+        return None
+    return c
+
+
+def _traffic(kernel_name: str, path: str = COUNTERS, workload: dict = {}):
+    """HBM bytes per launch of the fused kernel from committed rocprofv3 PMC
+    runs (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter
+    reads for a plain device copy of known size); None if the kernel
+    sources or the workload changed since the counters were taken."""
+    c = _load_counters(path, kernel_name, workload)
+    if c is None:
         return None
     copy_kib = c["copy_bytes"] / 1024.0
     fetch = c["fetch_kib"] * copy_kib / c["copy_fetch_kib"]
@@ -103,26 +118,25 @@ def _traffic(kernel_name: str):
     return (fetch + write) * 1024.0
 
 
-def _compute(kernel_name: str, kernel_s: float):
+def _compute(kernel_name: str, kernel_s: float, path: str = SQ_COUNTERS, workload: dict = {}):
     """Vector-ALU issue and matrix-core occupancy of one launch of the fused
     kernel: the instruction and busy-cycle counts of the committed SQ
     counter run (fixed by the code and the workload) over the live launch
     duration, against the chip's issue capacity; None if the kernel sources
-    changed since the counters were taken."""
-    try:
-        with open(SQ_COUNTERS) as f:
-            c = json.load(f)
-    except OSError:
-        return None
-    if c.get("source_sha256") != kernel_source_hash(kernel_name) or c.get("kernel") != kernel_name:
+    or the workload changed since the counters were taken."""
+    c = _load_counters(path, kernel_name, workload)
+    if c is None:
         return None
     valu = c["sq_insts_valu"] / kernel_s
-    mfma = c["sq_valu_mfma_busy_cycles"] / kernel_s
-    return {"valu_instr_per_strip": round(c["sq_insts_valu"] / c["strips"], 2),
-            "mfma_instr_per_strip": round(c["sq_insts_mfma"] / c["strips"], 2),
-            "valu_issue_gwave_instr_s": round(valu / 1e9, 1), "valu_issue_peak": round(VALU_ISSUE_PEAK / 1e9, 1),
-            "valu_issue_frac": round(valu / VALU_ISSUE_PEAK, 4),
-            "mfma_busy_frac": round(mfma / MFMA_CYCLES_PEAK, 4)}
+    res = {"valu_instr_per_strip": round(c["sq_insts_valu"] / c["strips"], 2),
+           "valu_issue_gwave_instr_s": round(valu / 1e9, 1), "valu_issue_peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+           "valu_issue_frac": round(valu / VALU_ISSUE_PEAK, 4)}
+    if "sq_insts_mfma" in c:
+        res["mfma_instr_per_strip"] = round(c["sq_insts_mfma"] / c["strips"], 2)
+        res["mfma_busy_frac"] = round(c["sq_valu_mfma_busy_cycles"] / kernel_s / MFMA_CYCLES_PEAK, 4)
+    if "sq_insts_valu_f64" in c:
+        res["valu_f64_share"] = round(c["sq_insts_valu_f64"] / c["sq_insts_valu"], 4)
+    return res
 
 
 def _cpu_baseline(frames, keep_r, n):
@@ -361,7 +375,9 @@ def bench_residual(args, A, torch):
     npx = sum(p.size for p in planes)
     stream = torch.cuda.current_stream()
     out = {}
-    for q in (8, 16, 32):
+    qs = (args.q,) if args.q else (8, 16, 32)
+    rq = 16 if 16 in qs else qs[0]  # the step the roofline is quoted at
+    for q in qs:
         graphs, keep = [], []
         for buf, hs, ws, ps, offs in bufs:
             dev = torch.from_numpy(buf).cuda()
@@ -395,17 +411,29 @@ def bench_residual(args, A, torch):
         ms = _events_ms(f, max(10, args.steps), stream)
         out[f"q{q}_one_launch_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
         out[f"q{q}_one_launch_plan"] = json.loads(plan.info())
-        if q == 16:
+        if q == rq:
             # algorithmic bytes of the one-launch call: the int16 samples read
             # once, the int16 reconstruction and the int16 levels (256 per
             # block, padded blocks included) written once
             alg = 4 * npx + 2 * 256 * plan.num_blocks
             gbs = alg / (ms * 1e-3) / 1e9
+            kname = "k_fused<approx, int16 in, uniform, int16 levels, int16 out>"
+            wl = {"frames": nf, "q": q}
+            traffic = _traffic(kname, RES_COUNTERS, wl)
             roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "traffic_unit": "GB per launch",
-                    "algorithmic_bytes": alg, "kernel": "k_fused<approx, int16 in, uniform, int16 levels, int16 out>",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic / 1e9, 4) if traffic else None,
+                    "traffic_unit": "GB per launch", "algorithmic_bytes": alg, "kernel": kname,
                     "kernel_ms": round(ms, 4), "timing": "HIP events around the one-launch call (fused kernel "
-                                                        "and the per-image SSE finalise), q = 16"}
+                                                        f"and the per-image SSE finalise), q = {q}",
+                    "compute": _compute(kname, ms * 1e-3, RES_SQ_COUNTERS, wl)}
+            if args.calibrate_copy:
+                # plain copy kernel of the input buffer (HBM counter scaling)
+                torch.cuda.synchronize()
+                rec.copy_(dev)
+                torch.cuda.synchronize()
+                f()
+                torch.cuda.synchronize()
+                roof["calibration_copy_bytes"] = dev.nbytes
         del dev, rec, lv
     # forward only, the whole stream in one launch: vector ALUs against the
     # int8 matrix-core form (three base-64 digits per value), 2 + 4 B/sample
@@ -423,10 +451,11 @@ def bench_residual(args, A, torch):
         del coef
     del dev
     return {"metric": "Gsample/s 2D fwd+quant+inv 16x16, 4:2:0 int16 residual stream, graph per frame",
-            "value": out["q16_gsample_s"], "unit": "Gsample/s", "n_gpus": 1, "steps": args.steps,
+            "value": out[f"q{rq}_gsample_s"], "unit": "Gsample/s", "n_gpus": 1, "steps": args.steps,
             "dtype": "i16/f32/f64", "data": "synthetic", "higher_is_better": True,
             "config": {"workload": f"{nf} frames 3840x2160 4:2:0 int16 residuals (AR(1) frames, per-block "
-                                   f"motion +-8), uniform q in {{8,16,32}}, levels + reconstruction written",
+                                   f"motion +-8), uniform q in {{{','.join(map(str, qs))}}} (value at q = {rq}), levels + "
+                                   "reconstruction written",
                        "per_q": out},
             "roofline": roof}
 

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 def _args(workload, frames, **kw):
     a = dict(gpus=1, steps=2, warmup=1, workload=workload, r=8, backend="auto", frames=frames,
-             no_cpu_baseline=True, no_variants=False, cpu_frames=1, calibrate_copy=False)
+             no_cpu_baseline=True, no_variants=False, cpu_frames=1, calibrate_copy=False, q=None)
     a.update(kw)
     return argparse.Namespace(**a)
 
@@ -69,6 +69,17 @@ def test_bench_residual_small():
                for q in (8, 16, 32))
     r = line["roofline"]
     assert r["bound"] == "hbm" and _positive(r["achieved"]) and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
+    # the committed counters were taken on 8 frames: none reported for 1
+    assert r["traffic"] is None and r["compute"] is None
+
+
+def test_bench_residual_one_step_with_copy_calibration():
+    line = _run("residual", 1, q=8, calibrate_copy=True)
+    per_q = line["config"]["per_q"]
+    assert _positive(per_q["q8_gsample_s"]) and "q16_gsample_s" not in per_q
+    assert line["value"] == per_q["q8_gsample_s"]
+    r = line["roofline"]
+    assert "q = 8" in r["timing"] and r["calibration_copy_bytes"] > 0
 
 
 def test_bench_rd_small():
