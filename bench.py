@@ -31,6 +31,8 @@ COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_hbm_counters.json")
 SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_sq_counters.json")
 RES_COUNTERS = os.path.join(ROOT, "profiles", "fused_residual8_hbm_counters.json")
 RES_SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_residual8_sq_counters.json")
+RD_COUNTERS = os.path.join(ROOT, "profiles", "fused_rd8_hbm_counters.json")
+RD_SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_rd8_sq_counters.json")
 # Issue capacity of the chip's 256 CUs x 4 SIMDs at 2.4 GHz: a wave64 VALU
 # instruction occupies its 16-lane SIMD for 4 cycles, and each SIMD's matrix
 # core has 2.4e9 busy cycles per second.
@@ -51,6 +53,8 @@ def _parse():
     ap.add_argument("--frames", type=int, default=None)
     ap.add_argument("--q", type=int, choices=[8, 16, 32], default=None,
                     help="residual workload: one uniform step instead of all three")
+    ap.add_argument("--qp", type=int, choices=[22, 27, 32, 37], default=None,
+                    help="rd workload: one QP instead of all four")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=128)
@@ -476,7 +480,9 @@ def bench_rd(args, A, torch):
     npx = sum(p.size for p in planes)
     stream = torch.cuda.current_stream()
     points = []
-    for qp in (22, 27, 32, 37):
+    qps = (args.qp,) if args.qp else (22, 27, 32, 37)
+    rqp = 27 if 27 in qps else qps[0]  # the point the roofline is quoted at
+    for qp in qps:
         plan = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, qmode=A.Q_DEADZONE, q=qp,
                       qcoef_dtype=A.I16, out_dtype=A.I16, flags=A.FLAG_AUTOTUNE | A.FLAG_DEADZONE_INTER)
         lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
@@ -493,21 +499,33 @@ def bench_rd(args, A, torch):
         points.append({"qp": qp, "bits_per_sample": round(int(bits.sum()) / npx, 5),
                        "psnr_y_db": round(10 * np.log10(65025.0 * n_y / s_y), 4) if s_y else None,
                        "gsample_s": round(npx / (ms * 1e-3) / 1e9, 4), "plan": json.loads(plan.info())})
-        if qp == 27:
+        if qp == rqp:
             # samples read, reconstruction and levels (256 per block) written
             alg = 4 * npx + 2 * 256 * plan.num_blocks
             gbs = alg / (ms * 1e-3) / 1e9
+            kname = "k_fused<approx, int16 in, deadzone, int16 levels, int16 out>"
+            wl = {"frames": nf, "qp": qp}
+            traffic = _traffic(kname, RD_COUNTERS, wl)
             roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "traffic_unit": "GB per launch",
-                    "algorithmic_bytes": alg,
-                    "kernel": "k_fused<approx, int16 in, deadzone, int16 levels, int16 out>", "kernel_ms": round(ms, 4),
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic / 1e9, 4) if traffic else None,
+                    "traffic_unit": "GB per launch", "algorithmic_bytes": alg, "kernel": kname,
+                    "kernel_ms": round(ms, 4),
                     "timing": "HIP events around the one-launch call (fused kernel and the per-image SSE "
-                              "finalise), QP 27"}
+                              f"finalise), QP {qp}",
+                    "compute": _compute(kname, ms * 1e-3, RD_SQ_COUNTERS, wl)}
+            if args.calibrate_copy:
+                # plain copy kernel of the input buffer (HBM counter scaling)
+                torch.cuda.synchronize()
+                rec.copy_(dev)
+                torch.cuda.synchronize()
+                f()
+                torch.cuda.synchronize()
+                roof["calibration_copy_bytes"] = dev.nbytes
     return {"metric": "Gsample/s 2D fwd+deadzone quant+inv 16x16 with rate proxy, 4:2:0 int16 residual stream",
-            "value": points[1]["gsample_s"], "unit": "Gsample/s", "n_gpus": 1, "steps": args.steps,
+            "value": points[qps.index(rqp)]["gsample_s"], "unit": "Gsample/s", "n_gpus": 1, "steps": args.steps,
             "dtype": "i16/f32/f64", "data": "synthetic", "higher_is_better": True,
             "config": {"workload": f"{nf} frames 3840x2160 4:2:0 int16 residuals, deadzone quantiser "
-                                   "(inter offset 1/6), QP 22/27/32/37, levels + reconstruction written",
+                                   f"(inter offset 1/6), QP {'/'.join(map(str, qps))} (value at QP {rqp}), levels + reconstruction written",
                        "rd_curve": points},
             "roofline": roof}
 

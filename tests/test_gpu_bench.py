@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 def _args(workload, frames, **kw):
     a = dict(gpus=1, steps=2, warmup=1, workload=workload, r=8, backend="auto", frames=frames,
-             no_cpu_baseline=True, no_variants=False, cpu_frames=1, calibrate_copy=False, q=None)
+             no_cpu_baseline=True, no_variants=False, cpu_frames=1, calibrate_copy=False, q=None, qp=None)
     a.update(kw)
     return argparse.Namespace(**a)
 
@@ -82,10 +82,21 @@ def test_bench_residual_one_step_with_copy_calibration():
     assert "q = 8" in r["timing"] and r["calibration_copy_bytes"] > 0
 
 
+def test_bench_rd_one_point_with_copy_calibration():
+    line = _run("rd", 1, qp=32, calibrate_copy=True)
+    pts = line["config"]["rd_curve"]
+    assert [p["qp"] for p in pts] == [32] and line["value"] == pts[0]["gsample_s"]
+    r = line["roofline"]
+    assert "QP 32" in r["timing"] and r["calibration_copy_bytes"] > 0
+
+
 def test_bench_rd_small():
     line = _run("rd", 1)
     pts = line["config"]["rd_curve"]
     assert [p["qp"] for p in pts] == [22, 27, 32, 37]
+    assert line["value"] == pts[1]["gsample_s"]
+    # the committed counters were taken on 8 frames: none reported for 1
+    assert line["roofline"]["traffic"] is None and line["roofline"]["compute"] is None
     # coarser steps never cost more bits
     bits = [p["bits_per_sample"] for p in pts]
     assert all(a >= b for a, b in zip(bits, bits[1:]))
