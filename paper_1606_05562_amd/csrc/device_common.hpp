@@ -260,9 +260,17 @@ __device__ __forceinline__ ImageDesc load_desc(const ImageDesc* images, int i) {
   return d;
 }
 
+// The hardware hands workgroup b to XCD b mod 8.  When the grid is a
+// multiple of 8, workgroup b takes slot (b mod 8) (G / 8) + b / 8 (a
+// bijection), so that each XCD works through one contiguous eighth of the
+// strips instead of every eighth group of four waves.
+__device__ __forceinline__ int xcd_slot(int b, int G) {
+  return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+}
+
 __device__ __forceinline__ bool cursor_init(StripCursor& c, const Params& P) {
   const int wave = uniform_int(threadIdx.x >> 6);
-  const int64_t g = (int64_t)blockIdx.x * kWavesPerGroup + wave;
+  const int64_t g = (int64_t)xcd_slot(blockIdx.x, gridDim.x) * kWavesPerGroup + wave;
   const int64_t G = (int64_t)gridDim.x * kWavesPerGroup;
   c.s = P.n_strips * g / G;
   c.s_end = P.n_strips * (g + 1) / G;
