@@ -262,10 +262,21 @@ adct16_status adct16_rate(adct16_plan plan, const void *d_qcoef, int64_t *d_bits
 adct16_status adct16_measure(adct16_plan plan, const void *d_a, const void *d_b,
                              int64_t *d_sse, double *d_psnr, void *stream);
 
-/* Forward -> retention/quantiser -> inverse -> SSE/PSNR fused in one pass
- * over the batch (one persistent kernel plus a finalisation kernel).
- * d_out (out_dtype U8/I16) and d_qcoef (qcoef_dtype) are optional (NULL =
- * not written); d_sse may be NULL (plan workspace), d_psnr may be NULL. */
+/* Section 4's compression experiment in one pass over the batch: every
+ * 16x16 block A is transformed (B = C_hat A C_hat^T, Section 2 with Eq. (1)),
+ * its coefficients retained (zonal / zig-zag) or quantised (uniform step
+ * with S absorbed into it, Section 2; the deadzone stand-in of Section 5.3),
+ * the block rebuilt as A' = C_hat^T B' C_hat and rounded as adct16_inverse
+ * does, and the per-image SSE and PSNR accumulated as adct16_measure
+ * computes them.  Results equal those of adct16_forward, adct16_quantise,
+ * adct16_inverse and adct16_measure called in turn.  One persistent kernel
+ * plus a finalisation kernel.
+ * d_in: in_dtype, the batch layout.  d_out (out_dtype U8/I16, the input
+ * layout) and d_qcoef (qcoef_dtype, block-major) are optional (NULL = not
+ * written).  d_sse: n_images int64, overwritten; NULL uses the plan's
+ * workspace.  d_psnr: n_images doubles, may be NULL.  ADCT16_E_NULL for a
+ * NULL d_in, ADCT16_E_ALIGN for misaligned pointers, ADCT16_E_STATE for a
+ * d_out with an F32 out_dtype, ADCT16_E_LAUNCH if a launch fails. */
 adct16_status adct16_compress_and_measure(adct16_plan plan, const void *d_in, void *d_out,
                                           void *d_qcoef, int64_t *d_sse, double *d_psnr,
                                           void *stream);

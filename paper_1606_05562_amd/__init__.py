@@ -5,8 +5,10 @@ Video Compression").
 This module is a thin ctypes binding of the C ABI declared in
 include/adct16.h: it marshals arguments (device pointers of torch tensors,
 the current HIP stream) and raises on error status.  Every step of the
-transform runs in the HIP library libadct16.so; if that library is missing
-the import fails loudly, there is no CPU fallback.
+transform runs in the HIP library libadct16.so.  The library is loaded on
+first use, so that the build step (paper_1606_05562_amd.build) can run in a
+tree where it does not exist yet; any call made while it is missing raises
+ImportError.  There is no CPU fallback.
 """
 from __future__ import annotations
 
@@ -110,16 +112,21 @@ def _load():
     return lib
 
 
-_lib = _load()
+_LIB = None
 
 
 def lib():
-    return _lib
+    """The loaded libadct16.so (loaded on the first call; raises ImportError
+    if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB
 
 
 def _check(st: int):
     if st != OK:
-        raise Adct16Error(st, f"{_lib.adct16_status_string(st).decode()}: {_lib.adct16_last_error_string().decode()}")
+        raise Adct16Error(st, f"{lib().adct16_status_string(st).decode()}: {lib().adct16_last_error_string().decode()}")
 
 
 def _ptr(t) -> int | None:
@@ -165,7 +172,7 @@ class Plan:
         d = _Desc(n, self._h, self._w, self._p, self._o, in_dtype, coef_dtype, qcoef_dtype, out_dtype,
                   qmode, r, q, backend, flags, matrix)
         h = ctypes.c_void_p()
-        _check(_lib.adct16_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        _check(lib().adct16_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._plan = h
         self.n_images = n
         self.in_dtype, self.coef_dtype, self.qcoef_dtype, self.out_dtype = in_dtype, coef_dtype, qcoef_dtype, out_dtype
@@ -173,7 +180,7 @@ class Plan:
 
     def close(self):
         if getattr(self, "_plan", None):
-            _lib.adct16_plan_destroy(self._plan)
+            lib().adct16_plan_destroy(self._plan)
             self._plan = None
 
     def __del__(self):
@@ -185,45 +192,45 @@ class Plan:
     @property
     def num_blocks(self) -> int:
         n = ctypes.c_int64()
-        _check(_lib.adct16_plan_num_blocks(self._plan, ctypes.byref(n)))
+        _check(lib().adct16_plan_num_blocks(self._plan, ctypes.byref(n)))
         return n.value
 
     def info(self) -> str:
         buf = ctypes.create_string_buffer(1024)
-        _check(_lib.adct16_plan_info(self._plan, buf, len(buf)))
+        _check(lib().adct16_plan_info(self._plan, buf, len(buf)))
         return buf.value.decode()
 
     def forward(self, inp, coef, stream=None):
-        _check(_lib.adct16_forward(self._plan, _ptr(inp), _ptr(coef), _stream(stream)))
+        _check(lib().adct16_forward(self._plan, _ptr(inp), _ptr(coef), _stream(stream)))
 
     def quantise(self, coef, qcoef, stream=None):
-        _check(_lib.adct16_quantise(self._plan, _ptr(coef), _ptr(qcoef), _stream(stream)))
+        _check(lib().adct16_quantise(self._plan, _ptr(coef), _ptr(qcoef), _stream(stream)))
 
     def inverse(self, qcoef, out, stream=None):
-        _check(_lib.adct16_inverse(self._plan, _ptr(qcoef), _ptr(out), _stream(stream)))
+        _check(lib().adct16_inverse(self._plan, _ptr(qcoef), _ptr(out), _stream(stream)))
 
     def measure(self, a, b, sse, psnr=None, stream=None):
-        _check(_lib.adct16_measure(self._plan, _ptr(a), _ptr(b), _ptr(sse), _ptr(psnr), _stream(stream)))
+        _check(lib().adct16_measure(self._plan, _ptr(a), _ptr(b), _ptr(sse), _ptr(psnr), _stream(stream)))
 
     def dct_compress_and_measure(self, inp, out=None, sse=None, psnr=None, stream=None):
         """The same retention with the exact DCT-II in float64 (comparison)."""
-        _check(_lib.adct16_dct_compress_and_measure(self._plan, _ptr(inp), _ptr(out), _ptr(sse), _ptr(psnr),
+        _check(lib().adct16_dct_compress_and_measure(self._plan, _ptr(inp), _ptr(out), _ptr(sse), _ptr(psnr),
                                                     _stream(stream)))
 
     def ssim(self, a, b, out, stream=None):
         """Per-image mean SSIM (float64) of b against a."""
-        _check(_lib.adct16_ssim(self._plan, _ptr(a), _ptr(b), _ptr(out), _stream(stream)))
+        _check(lib().adct16_ssim(self._plan, _ptr(a), _ptr(b), _ptr(out), _stream(stream)))
 
     def rate(self, qcoef, bits, stream=None):
         """Per-image signed Exp-Golomb code length (bits, int64) of the levels."""
-        _check(_lib.adct16_rate(self._plan, _ptr(qcoef), _ptr(bits), _stream(stream)))
+        _check(lib().adct16_rate(self._plan, _ptr(qcoef), _ptr(bits), _stream(stream)))
 
     def compress_and_measure(self, inp, out=None, qcoef=None, sse=None, psnr=None, stream=None):
-        _check(_lib.adct16_compress_and_measure(self._plan, _ptr(inp), _ptr(out), _ptr(qcoef), _ptr(sse),
+        _check(lib().adct16_compress_and_measure(self._plan, _ptr(inp), _ptr(out), _ptr(qcoef), _ptr(sse),
                                                 _ptr(psnr), _stream(stream)))
 
     def dct_forward(self, inp, y, precision=F16, stream=None):
-        _check(_lib.adct16_dct_forward(self._plan, _ptr(inp), _ptr(y), precision, _stream(stream)))
+        _check(lib().adct16_dct_forward(self._plan, _ptr(inp), _ptr(y), precision, _stream(stream)))
 
     def graph(self, inp, out=None, qcoef=None, sse=None, psnr=None):
         return Graph(self, inp, out, qcoef, sse, psnr)
@@ -234,17 +241,17 @@ class Graph:
 
     def __init__(self, plan: Plan, inp, out=None, qcoef=None, sse=None, psnr=None):
         g = ctypes.c_void_p()
-        _check(_lib.adct16_graph_create(plan._plan, _ptr(inp), _ptr(out), _ptr(qcoef), _ptr(sse), _ptr(psnr),
+        _check(lib().adct16_graph_create(plan._plan, _ptr(inp), _ptr(out), _ptr(qcoef), _ptr(sse), _ptr(psnr),
                                         ctypes.byref(g)))
         self._g = g
         self._keep = (plan, inp, out, qcoef, sse, psnr)
 
     def launch(self, stream=None):
-        _check(_lib.adct16_graph_launch(self._g, _stream(stream)))
+        _check(lib().adct16_graph_launch(self._g, _stream(stream)))
 
     def close(self):
         if getattr(self, "_g", None):
-            _lib.adct16_graph_destroy(self._g)
+            lib().adct16_graph_destroy(self._g)
             self._g = None
 
     def __del__(self):
@@ -256,12 +263,12 @@ class Graph:
 
 def forward_1d(x, y, stream=None):
     """y = T x for each row of an (n, 16) int32 device tensor."""
-    _check(_lib.adct16_forward_1d(_ptr(x), _ptr(y), x.shape[0], _stream(stream)))
+    _check(lib().adct16_forward_1d(_ptr(x), _ptr(y), x.shape[0], _stream(stream)))
 
 
 def inverse_1d(x, y, stream=None):
     """y = T^T x for each row of an (n, 16) int32 device tensor."""
-    _check(_lib.adct16_inverse_1d(_ptr(x), _ptr(y), x.shape[0], _stream(stream)))
+    _check(lib().adct16_inverse_1d(_ptr(x), _ptr(y), x.shape[0], _stream(stream)))
 
 
 def transform_matrix(which: int = MATRIX_APPROX):
@@ -269,7 +276,7 @@ def transform_matrix(which: int = MATRIX_APPROX):
     MATRIX_DCT) as a float64 numpy array."""
     import numpy as np
     m = np.empty((16, 16), dtype=np.float64)
-    _check(_lib.adct16_transform_matrix(which, m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    _check(lib().adct16_transform_matrix(which, m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return m
 
 
@@ -283,9 +290,9 @@ def transform_measures(ct, rho: float = 0.95) -> dict:
         raise ValueError("ct must be 16x16")
     out = np.empty(5, dtype=np.float64)
     dp = ctypes.POINTER(ctypes.c_double)
-    _check(_lib.adct16_transform_measures(a.ctypes.data_as(dp), float(rho), out.ctypes.data_as(dp)))
+    _check(lib().adct16_transform_measures(a.ctypes.data_as(dp), float(rho), out.ctypes.data_as(dp)))
     return dict(zip(("d2", "epsilon", "mse", "cg", "eta"), out.tolist()))
 
 
 def status_string(st: int) -> str:
-    return _lib.adct16_status_string(st).decode()
+    return lib().adct16_status_string(st).decode()

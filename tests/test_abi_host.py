@@ -132,8 +132,11 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     spec = importlib.util.spec_from_file_location("adct16_probe_copy", src)
     mod = importlib.util.module_from_spec(spec)
     monkeypatch.setattr(os.path, "exists", lambda p: False)
+    spec.loader.exec_module(mod)   # the build step imports the package before the library exists
     with pytest.raises(ImportError):
-        spec.loader.exec_module(mod)
+        mod.lib()
+    with pytest.raises(ImportError):
+        mod.status_string(0)
 
 
 # ---------------------------------------------------------------------------
