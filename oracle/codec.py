@@ -230,26 +230,32 @@ def _gauss_window(size: int = 11, sigma: float = 1.5) -> np.ndarray:
     return g / g.sum()
 
 
-def ssim(a: np.ndarray, b: np.ndarray, peak: float = 255.0) -> float:
-    """Mean SSIM index of Wang, Bovik, Sheikh and Simoncelli (the measure
-    Section 4 cites): 11x11 Gaussian window (sigma 1.5), K1 = 0.01,
-    K2 = 0.03, statistics over every window position fully inside the image.
-    Parity is pinned only by closed forms (identical images, constant
-    images), not by any value the paper prints."""
+def _local_moments(x: np.ndarray, y: np.ndarray, g: np.ndarray):
+    """Weighted means, variances and covariance of x and y over every window
+    position fully inside the image (population moments: E[xy] - E[x]E[y]
+    under the normalised window weights)."""
     from scipy.signal import correlate2d
-    x = np.asarray(a, dtype=np.float64)
-    y = np.asarray(b, dtype=np.float64)
-    g = _gauss_window()
-    c1 = (0.01 * peak) ** 2
-    c2 = (0.03 * peak) ** 2
 
     def f(z):
         return correlate2d(z, g, mode="valid")
 
     mx, my = f(x), f(y)
-    sxx = f(x * x) - mx * mx
-    syy = f(y * y) - my * my
-    sxy = f(x * y) - mx * my
+    return mx, my, f(x * x) - mx * mx, f(y * y) - my * my, f(x * y) - mx * my
+
+
+def ssim(a: np.ndarray, b: np.ndarray, peak: float = 255.0) -> float:
+    """Mean SSIM index of Wang, Bovik, Sheikh and Simoncelli (the measure
+    Section 4 cites): 11x11 Gaussian window (sigma 1.5), K1 = 0.01,
+    K2 = 0.03, statistics over every window position fully inside the image.
+    The paper prints no SSIM of an image available here; the window, sigma
+    and population moments are pinned by closed forms (checkerboards against
+    flat and against other checkerboards) and by brute force on an 11x11
+    image."""
+    x = np.asarray(a, dtype=np.float64)
+    y = np.asarray(b, dtype=np.float64)
+    c1 = (0.01 * peak) ** 2
+    c2 = (0.03 * peak) ** 2
+    mx, my, sxx, syy, sxy = _local_moments(x, y, _gauss_window())
     m = ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
     return float(m.mean())
 

@@ -420,6 +420,198 @@ def test_lossless_and_zonal_experiment():
 
 
 # ----------------------------------------------------------------------------
+# Pins of the image-level codec functions: SSIM, the dequantised
+# reconstructions, the reconstruction rounding and APE.  Each is a function
+# of the codec module as it stands, so that a planted mistake in that module
+# (test_codec_pins_catch_planted_mistakes) shows up as a failure here.
+
+def _norm_products():
+    """n_u n_v from the printed S (Section 2), not from the oracle's T."""
+    n = np.array(_golden("s_diag.json")["inv_sqrt_of"], dtype=np.float64)
+    return np.outer(n, n)
+
+
+def _gauss_1d(size, sigma):
+    """The 1-D factor of the SSIM window of the Wang et al. reading: samples
+    of exp(-t^2 / (2 sigma^2)) at integer t centred on the window, normalised
+    to sum 1 (the 2-D window is the outer product)."""
+    t = [k - (size - 1) / 2.0 for k in range(size)]
+    g = [math.exp(-x * x / (2.0 * sigma * sigma)) for x in t]
+    tot = sum(g)
+    return [x / tot for x in g]
+
+
+def _checkerboard(h, w, mu, d):
+    i, j = np.indices((h, w))
+    return mu + d * np.where((i + j) % 2 == 0, 1.0, -1.0)
+
+
+def _ssim_of_checkerboards(h, w, mu1, d1, mu2, d2, size=11, sigma=1.5, peak=255.0):
+    """Closed form of the mean SSIM of two checkerboards x = mu1 + d1 (-1)^(i+j)
+    and y = mu2 + d2 (-1)^(i+j).  With c = sum_k g_k (-1)^k, a window whose
+    corner has parity s = (-1)^(p+q) sees mu_x = mu1 + s d1 c^2,
+    var_x = d1^2 (1 - c^4), var_y = d2^2 (1 - c^4) and cov_xy = d1 d2 (1 - c^4)
+    (population moments under the window weights)."""
+    g = _gauss_1d(size, sigma)
+    c = sum(gk * (-1) ** k for k, gk in enumerate(g))
+    c1, c2 = (0.01 * peak) ** 2, (0.03 * peak) ** 2
+    vx, vy, cxy = d1 * d1 * (1 - c ** 4), d2 * d2 * (1 - c ** 4), d1 * d2 * (1 - c ** 4)
+    tot, cnt = 0.0, 0
+    for p_ in range(h - size + 1):
+        for q_ in range(w - size + 1):
+            s = 1 if (p_ + q_) % 2 == 0 else -1
+            mx, my = mu1 + s * d1 * c * c, mu2 + s * d2 * c * c
+            tot += ((2 * mx * my + c1) * (2 * cxy + c2)) / ((mx * mx + my * my + c1) * (vx + vy + c2))
+            cnt += 1
+    return tot / cnt
+
+
+def _ssim_bruteforce(x, y, size=11, sigma=1.5, peak=255.0):
+    """Mean SSIM with every window's weighted sums written out as loops."""
+    g = _gauss_1d(size, sigma)
+    c1, c2 = (0.01 * peak) ** 2, (0.03 * peak) ** 2
+    h, w = x.shape
+    vals = []
+    for p_ in range(h - size + 1):
+        for q_ in range(w - size + 1):
+            sx = sy = sxx = syy = sxy = 0.0
+            for k in range(size):
+                for l_ in range(size):
+                    wt = g[k] * g[l_]
+                    a, b = float(x[p_ + k, q_ + l_]), float(y[p_ + k, q_ + l_])
+                    sx += wt * a
+                    sy += wt * b
+                    sxx += wt * a * a
+                    syy += wt * b * b
+                    sxy += wt * a * b
+            vx, vy, cv = sxx - sx * sx, syy - sy * sy, sxy - sx * sy
+            vals.append(((2 * sx * sy + c1) * (2 * cv + c2)) / ((sx * sx + sy * sy + c1) * (vx + vy + c2)))
+    return sum(vals) / len(vals)
+
+
+def pin_ssim():
+    bad = []
+    for (h, w, mu1, d1, mu2, d2) in ((30, 37, 120.0, 50.0, 120.0, 0.0),   # checkerboard against flat
+                                     (24, 24, 100.0, 40.0, 130.0, -30.0),  # anti-correlated checkerboards
+                                     (13, 12, 60.0, 20.0, 70.0, 45.0)):    # correlated, 3 x 2 windows
+        x = _checkerboard(h, w, mu1, d1)
+        y = _checkerboard(h, w, mu2, d2)
+        got, want = codec.ssim(x, y), _ssim_of_checkerboards(h, w, mu1, d1, mu2, d2)
+        if not abs(got - want) < 1e-12:
+            bad.append(f"ssim checkerboard {h}x{w}: {got} vs closed form {want}")
+    rng = np.random.default_rng(31)
+    for (h, w) in ((11, 11), (12, 13)):
+        x = rng.integers(0, 256, size=(h, w)).astype(np.float64)
+        y = np.clip(x + rng.integers(-40, 41, size=(h, w)), 0, 255)
+        got, want = codec.ssim(x, y), _ssim_bruteforce(x, y)
+        if not abs(got - want) < 1e-12:
+            bad.append(f"ssim brute force {h}x{w}: {got} vs {want}")
+    return bad
+
+
+# Reconstruction steps of the deadzone reading, worked by hand from
+# D = {40, 45, 51, 57, 64, 72} and step(QP) = D[QP mod 6] 2^(QP div 6) / 64.
+DEADZONE_STEPS = {4: 1.0, 10: 2.0, 22: 8.0, 27: 14.25, 37: 45.0, 0: 0.625}
+
+
+def pin_dequantised_reconstruction():
+    """C_hat is orthogonal (Section 2), so for every block the unrounded
+    reconstruction error equals the coefficient error (Parseval):
+    ||A' - A||^2 = sum_uv (B_uv - step L_uv)^2 with B = Z / sqrt(n_u n_v),
+    whatever the levels L are.  The DC level alone rebuilds a flat block of
+    step L / 16 (row 0 of T is all ones and S_00 = 1/4)."""
+    bad = []
+    rng = np.random.default_rng(41)
+    nn = _norm_products()
+    for k in range(12):
+        a = rng.integers(-255, 256, size=(16, 16)) if k % 2 else rng.integers(0, 256, size=(16, 16))
+        z = codec.forward_image(a)[0]
+        b = z / np.sqrt(nn)
+        lv = rng.integers(-40, 41, size=(1, 16, 16))
+        for q in (1, 8, 16, 32):
+            rec = codec.reconstruct_uniform(lv, q, 16, 16, np.int16, rounded=False)
+            lhs = float(np.sum((rec - a) ** 2))
+            rhs = float(np.sum((b - q * lv[0]) ** 2))
+            if not abs(lhs - rhs) <= 1e-9 * max(1.0, rhs):
+                bad.append(f"uniform Parseval q={q}: {lhs} vs {rhs}")
+        for qp, step in DEADZONE_STEPS.items():
+            # reconstruct_deadzone rounds; compare the rounding of the
+            # Parseval-checked real reconstruction A_r = C_hat^T (step L) C_hat.
+            rec = codec.reconstruct_deadzone(lv, qp, 16, 16, np.int16).astype(np.float64)
+            real = codec.reconstruct_uniform(lv, 1, 16, 16, np.int16, rounded=False) * step
+            if np.max(np.abs(rec - real)) > 0.5 + 1e-9:
+                bad.append(f"deadzone QP {qp}: reconstruction off the step {step}")
+            lhs = float(np.sum((real - a) ** 2))
+            rhs = float(np.sum((b - step * lv[0]) ** 2))
+            if not abs(lhs - rhs) <= 1e-9 * max(1.0, rhs):
+                bad.append(f"deadzone Parseval QP {qp}: {lhs} vs {rhs}")
+    for q in (1, 8, 32):
+        dc = np.zeros((1, 16, 16), dtype=np.int64)
+        dc[0, 0, 0] = 7
+        rec = codec.reconstruct_uniform(dc, q, 16, 16, np.int16, rounded=False)
+        if np.max(np.abs(rec - q * 7 / 16.0)) > 1e-12:
+            bad.append(f"uniform DC closed form q={q}")
+    return bad
+
+
+def pin_rounding_half_up():
+    """floor(x + 1/2) then clamp (u8) or saturate (int16), checked against
+    exact rationals on halves, quarters and values just off a half."""
+    bad = []
+    xs = [Fraction(k, 4) for k in range(-131080, 131081, 3)]
+    xs += [Fraction(k, 2) for k in (-65537, -65536, -5, -3, -1, 1, 3, 5, 509, 511, 65533, 65535)]
+    eps = Fraction(1, 2 ** 30)
+    xs += [Fraction(2 * k + 1, 2) + e for k in (-7, 0, 7, 200) for e in (-eps, eps)]
+    arr = np.array([float(x) for x in xs])
+    u8, i16 = codec.round_half_up_u8(arr), codec.round_half_up_i16(arr)
+    for x, g8, g16 in zip(xs, u8.tolist(), i16.tolist()):
+        r = math.floor(x + Fraction(1, 2))
+        if g8 != min(255, max(0, r)):
+            bad.append(f"u8 rounding of {x}: {g8}")
+        if g16 != min(32767, max(-32768, r)):
+            bad.append(f"i16 rounding of {x}: {g16}")
+    return bad
+
+
+def pin_ape():
+    """Section 4's absolute percentage error of a measure with respect to the
+    exact DCT, 100 |x - x_dct| / |x_dct|, on the Lena PSNRs the paper prints
+    (27.13 dB proposed, 28.55 dB exact DCT at 16 retained coefficients),
+    worked as exact rationals."""
+    bad = []
+    cases = ((Fraction(2713, 100), Fraction(2855, 100)), (Fraction(2855, 100), Fraction(2713, 100)),
+             (Fraction(95, 100), Fraction(97, 100)), (Fraction(-3, 2), Fraction(-2, 1)))
+    for x, ref in cases:
+        want = 100 * abs(x - ref) / abs(ref)
+        got = codec.ape(float(x), float(ref))
+        if not abs(got - float(want)) <= 1e-12 * float(want):
+            bad.append(f"ape({float(x)}, {float(ref)}) = {got}, want {float(want)}")
+    if not abs(codec.ape(27.13, 28.55) - 4.97373029772329) < 1e-9:
+        bad.append("ape of the printed Lena PSNRs")
+    return bad
+
+
+def _codec_pins():
+    return pin_ssim() + pin_dequantised_reconstruction() + pin_rounding_half_up() + pin_ape()
+
+
+def test_ssim_checkerboard_and_bruteforce():
+    assert pin_ssim() == []
+
+
+def test_dequantised_reconstruction_parseval():
+    assert pin_dequantised_reconstruction() == []
+
+
+def test_reconstruction_rounding_half_up():
+    assert pin_rounding_half_up() == []
+
+
+def test_ape_worked_values():
+    assert pin_ape() == []
+
+
+# ----------------------------------------------------------------------------
 # Planted mistakes: each plausible error in the oracle trips some pin.
 
 def _mutants():
@@ -440,6 +632,42 @@ def test_pins_catch_planted_mistakes(name, T, fwd, inv):
     failures = (pin_orthogonality(T) + pin_table2(T, tf.dct_matrix())
                 + pin_forward_bruteforce(fwd, nblk=1) + pin_inverse_identity(inv, fwd))
     assert failures, f"planted mistake '{name}' went undetected"
+
+
+def _codec_mutants():
+    n_win = 121.0
+
+    def sample_cov(x, y, g, _orig=codec._local_moments):
+        mx, my, sxx, syy, sxy = _orig(x, y, g)
+        f = n_win / (n_win - 1.0)
+        return mx, my, sxx * f, syy * f, sxy * f
+
+    sv = 1.0 / np.sqrt(_norm_products())
+    return [
+        ("SSIM window sigma 1.0", "_gauss_window", lambda size=11, sigma=1.5, _o=codec._gauss_window: _o(size, 1.0)),
+        ("SSIM window 7x7", "_gauss_window", lambda size=11, sigma=1.5, _o=codec._gauss_window: _o(7, sigma)),
+        ("SSIM sample covariance", "_local_moments", sample_cov),
+        ("dequantisation without q", "dequantise_uniform", lambda lv, q: np.asarray(lv, dtype=np.float64)),
+        ("S applied twice", "dequantise_uniform", lambda lv, q: float(q) * np.asarray(lv, dtype=np.float64) * sv),
+        ("deadzone step dropped", "deadzone_step", lambda qp: 1.0),
+        ("deadzone step off by one QP", "deadzone_step",
+         lambda qp, _o=codec.deadzone_step: _o(qp + 1) if qp + 1 < 64 else _o(qp)),
+        ("half-even rounding u8", "round_half_up_u8",
+         lambda a: np.clip(np.rint(np.asarray(a, dtype=np.float64)), 0, 255).astype(np.uint8)),
+        ("half-away-from-zero rounding i16", "round_half_up_i16",
+         lambda a: np.clip(np.sign(a) * np.floor(np.abs(np.asarray(a, dtype=np.float64)) + 0.5),
+                           -32768, 32767).astype(np.int16)),
+        ("truncating rounding i16", "round_half_up_i16",
+         lambda a: np.clip(np.trunc(np.asarray(a, dtype=np.float64) + 0.5), -32768, 32767).astype(np.int16)),
+        ("APE divided by x", "ape", lambda x, ref: 100.0 * abs(x - ref) / abs(x)),
+        ("APE without the factor 100", "ape", lambda x, ref: abs(x - ref) / abs(ref)),
+    ]
+
+
+@pytest.mark.parametrize("name,attr,fn", _codec_mutants(), ids=[m[0] for m in _codec_mutants()])
+def test_codec_pins_catch_planted_mistakes(name, attr, fn, monkeypatch):
+    monkeypatch.setattr(codec, attr, fn)
+    assert _codec_pins(), f"planted mistake '{name}' went undetected"
 
 
 def test_oracle_header_declares_test_infrastructure():
