@@ -281,6 +281,27 @@ adct16_status adct16_compress_and_measure(adct16_plan plan, const void *d_in, vo
                                           void *d_qcoef, int64_t *d_sse, double *d_psnr,
                                           void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as adct16_compress_and_measure, with the same arguments and
+ * identical results, whose scratch memory (the per-task SSE partials of the
+ * matrix-core kernel, the per-image accumulators of the vector kernel, and
+ * the per-image SSE when d_sse is NULL) comes from a fixed device array of
+ * 4 MiB inside the library instead of the plan's workspace.  Each GPU the
+ * library runs on holds one such array until the process ends.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine);
+ * its first use on a device resolves that device's array.  All calls on one
+ * GPU share the array: calls that overlap in time on one GPU (other streams,
+ * other threads) race and give undefined results; calls ordered on one
+ * stream do not.  The plan's device must be current (ADCT16_E_DEVICE
+ * otherwise).  A batch whose scratch exceeds 4 MiB is ADCT16_E_SHAPE (about
+ * 4 bytes per task of the matrix-core kernel, 8 bytes per accumulator slot
+ * of the vector kernel: n_images x 64 slots up to 1024 images, x 8 up to
+ * 16384).  Other errors as adct16_compress_and_measure. */
+adct16_status adct16_compress_and_measure_static(adct16_plan plan, const void *d_in, void *d_out,
+                                                 void *d_qcoef, int64_t *d_sse, double *d_psnr,
+                                                 void *stream);
+
 /* Comparison transform (Section 3): exact orthonormal DCT-II of every block,
  * Y = C X C^T, on the BF16 or F16 matrix cores with float32 accumulation.
  * X is the block centred to [-128, 127] for U8 input, the raw samples for

@@ -39,7 +39,7 @@ EXPORTED = [
     "adct16_plan_create", "adct16_plan_destroy", "adct16_plan_num_blocks", "adct16_plan_info",
     "adct16_forward", "adct16_quantise", "adct16_inverse", "adct16_measure", "adct16_rate",
     "adct16_dct_compress_and_measure", "adct16_ssim",
-    "adct16_compress_and_measure", "adct16_dct_forward", "adct16_forward_1d", "adct16_inverse_1d",
+    "adct16_compress_and_measure", "adct16_compress_and_measure_static", "adct16_dct_forward", "adct16_forward_1d", "adct16_inverse_1d",
     "adct16_graph_create", "adct16_graph_launch", "adct16_graph_destroy",
     "adct16_transform_matrix", "adct16_transform_measures",
     "adct16_status_string", "adct16_last_error_string",
@@ -91,6 +91,7 @@ def _load():
         "adct16_dct_compress_and_measure": [vp, vp, vp, vp, vp, vp],
         "adct16_ssim": [vp, vp, vp, vp, vp],
         "adct16_compress_and_measure": [vp, vp, vp, vp, vp, vp, vp],
+        "adct16_compress_and_measure_static": [vp, vp, vp, vp, vp, vp, vp],
         "adct16_dct_forward": [vp, vp, vp, i32, vp],
         "adct16_forward_1d": [vp, vp, i64, vp],
         "adct16_inverse_1d": [vp, vp, i64, vp],
@@ -228,6 +229,12 @@ class Plan:
     def compress_and_measure(self, inp, out=None, qcoef=None, sse=None, psnr=None, stream=None):
         _check(lib().adct16_compress_and_measure(self._plan, _ptr(inp), _ptr(out), _ptr(qcoef), _ptr(sse),
                                                 _ptr(psnr), _stream(stream)))
+
+    def compress_and_measure_static(self, inp, out=None, qcoef=None, sse=None, psnr=None, stream=None):
+        """compress_and_measure with the library's fixed device scratch array
+        (no allocation); calls that overlap on one GPU race."""
+        _check(lib().adct16_compress_and_measure_static(self._plan, _ptr(inp), _ptr(out), _ptr(qcoef), _ptr(sse),
+                                                       _ptr(psnr), _stream(stream)))
 
     def dct_forward(self, inp, y, precision=F16, stream=None):
         _check(lib().adct16_dct_forward(self._plan, _ptr(inp), _ptr(y), precision, _stream(stream)))

@@ -96,6 +96,34 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 }  // namespace
 
+// Scratch of adct16_compress_and_measure_static: every GPU the library runs
+// on holds one copy of this array (kStaticScratchBytes) until the process
+// ends.  Host code never uses the name as an address: static_scratch()
+// resolves each device's copy once, with that device current.
+constexpr uint64_t kStaticScratchBytes = 4ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<unsigned char*> g_scratch_ptr;  // device address of `scratch`, per device id
+
+// The current device's copy of `scratch` (resolved on its first use).
+adct16_status static_scratch(int device, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e == hipSuccess ? hipErrorInvalidSymbol : e, "static scratch address");
+    g_scratch_ptr[device] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return ADCT16_OK;
+}
+
+}  // namespace
+
 struct adct16_plan_s {
   adct16_desc d{};
   std::vector<ImageDesc> images;
@@ -163,9 +191,31 @@ adct16_status check_plan(adct16_plan p) {
 
 bool mfma_supported(const adct16_plan_s* p);
 
-adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, const void* d_in, void* d_out,
-                            void* d_qcoef, int64_t* d_sse, double* d_psnr, hipStream_t s) {
+// Device memory a fused call uses besides its inputs and outputs: the
+// per-task SSE partials of the matrix-core kernel, the per-image accumulator
+// slots of the vector kernel (zero on entry unless `clear_slots`), and the
+// per-image SSE when the caller passes none.
+struct Workspace {
+  uint32_t* task_sse;
+  unsigned long long* sse_slots;
+  unsigned long long* sse_out;
+  bool clear_slots;
+};
+
+Workspace plan_workspace(const adct16_plan_s* p) {
+  return Workspace{p->d_task_sse, p->d_sse_ws, p->d_sse_out, false};
+}
+
+// Whether a fused call runs the matrix-core kernel (else the vector kernel).
+bool fused_on_mfma(const adct16_plan_s* p, int backend, bool levels) {
+  return backend == ADCT16_BACKEND_MFMA && !levels && mfma_supported(p);
+}
+
+adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, const Workspace& ws,
+                            const void* d_in, void* d_out, void* d_qcoef, int64_t* d_sse, double* d_psnr,
+                            hipStream_t s) {
   Params P = base_params(p);
+  P.task_sse = ws.task_sse;
   P.rows = p->tasks[tsel].d_rows;
   P.n_rows = p->tasks[tsel].n_rows;
   P.task_first = p->tasks[tsel].d_first;
@@ -182,8 +232,8 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, c
   // partials, which a second kernel sums per image (SSE and PSNR); a call
   // that also asks for the retained coefficients runs the vector kernel,
   // which accumulates per image directly.
-  if (backend == ADCT16_BACKEND_MFMA && qk == CF_NONE && mfma_supported(p)) {
-    P.sse = out_sse ? out_sse : p->d_sse_out;  // the reduce writes final sums
+  if (fused_on_mfma(p, backend, qk != CF_NONE)) {
+    P.sse = out_sse ? out_sse : ws.sse_out;  // the reduce writes final sums
     // whole-cache-line rows: streaming (non-temporal) accesses pay off
     const bool nt = p->lines_aligned && (reinterpret_cast<uintptr_t>(d_in) & 127) == 0 &&
                     (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 127) == 0);
@@ -194,7 +244,11 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, c
     if (e != hipSuccess) return hip_fail(e, "SSE reduction kernel");
     return ADCT16_OK;
   }
-  P.sse = p->d_sse_ws;  // accumulator slots (zero on entry)
+  P.sse = ws.sse_slots;  // accumulator slots (zero on entry)
+  if (ws.clear_slots) {
+    e = launch_zero_u64(ws.sse_slots, P.n_images * P.sse_slots, s);
+    if (e != hipSuccess) return hip_fail(e, "clearing kernel");
+  }
   e = launch_valu_fused(p->mat, p->in_kind, p->mode, qk, ok, P, grid, s);
   if (e != hipSuccess) return hip_fail(e, "fused kernel");
   e = launch_sse_finalize(P, out_sse, s);  // also clears the slots
@@ -323,7 +377,7 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
     e = hipEventRecord(w.e0, w.s);
     if (e != hipSuccess) return hip_fail(e, "autotune event");
     for (const Cand& c : cands) {
-      adct16_status st = compress_impl(p, c.backend, c.grid, c.tsel, w.din, tout, w.dq, nullptr, nullptr, w.s);
+      adct16_status st = compress_impl(p, c.backend, c.grid, c.tsel, plan_workspace(p), w.din, tout, w.dq, nullptr, nullptr, w.s);
       if (st != ADCT16_OK) return st;
     }
     e = hipEventRecord(w.e1, w.s);
@@ -337,7 +391,7 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
     for (Cand& c : cands) {
       e = hipEventRecord(w.e0, w.s);
       if (e != hipSuccess) return hip_fail(e, "autotune event");
-      adct16_status st = compress_impl(p, c.backend, c.grid, c.tsel, w.din, tout, w.dq, nullptr, nullptr, w.s);
+      adct16_status st = compress_impl(p, c.backend, c.grid, c.tsel, plan_workspace(p), w.din, tout, w.dq, nullptr, nullptr, w.s);
       if (st != ADCT16_OK) return st;
       e = hipEventRecord(w.e1, w.s);
       if (e == hipSuccess) e = hipEventSynchronize(w.e1);
@@ -782,9 +836,46 @@ adct16_status adct16_compress_and_measure(adct16_plan p, const void* d_in, void*
   if (d_out && p->out_kind == OUT_F32)
     return fail(ADCT16_E_STATE, "the fused call writes rounded reconstructions (out_dtype U8 or I16)");
   if (d_qcoef)
-    return compress_impl(p, ADCT16_BACKEND_VALU, p->grid_lv, p->task_sel, d_in, d_out, d_qcoef, d_sse, d_psnr,
-                         (hipStream_t)stream);
-  return compress_impl(p, p->backend, p->grid, p->task_sel, d_in, d_out, d_qcoef, d_sse, d_psnr, (hipStream_t)stream);
+    return compress_impl(p, ADCT16_BACKEND_VALU, p->grid_lv, p->task_sel, plan_workspace(p), d_in, d_out, d_qcoef,
+                         d_sse, d_psnr, (hipStream_t)stream);
+  return compress_impl(p, p->backend, p->grid, p->task_sel, plan_workspace(p), d_in, d_out, d_qcoef, d_sse, d_psnr,
+                       (hipStream_t)stream);
+}
+
+adct16_status adct16_compress_and_measure_static(adct16_plan p, const void* d_in, void* d_out, void* d_qcoef,
+                                                 int64_t* d_sse, double* d_psnr, void* stream) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!d_in) return fail(ADCT16_E_NULL, "d_in is NULL");
+  if (!aligned16(d_in) || (d_out && !aligned16(d_out)) || (d_qcoef && !aligned16(d_qcoef)))
+    return fail(ADCT16_E_ALIGN, "buffers must be 16-byte aligned");
+  if (d_out && p->out_kind == OUT_F32)
+    return fail(ADCT16_E_STATE, "the fused call writes rounded reconstructions (out_dtype U8 or I16)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(ADCT16_E_DEVICE, "the plan's device (%d) must be current (current: %d)", p->device, dev);
+  const bool levels = d_qcoef != nullptr;
+  const int backend = levels ? ADCT16_BACKEND_VALU : p->backend;
+  const int grid = levels ? p->grid_lv : p->grid;
+  // carve the call's workspace out of the array, 256-byte aligned pieces
+  auto up = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
+  uint64_t need = 0, o_task = 0, o_slots = 0, o_out = 0;
+  if (fused_on_mfma(p, backend, levels)) {
+    o_task = need;
+    need += up(sizeof(uint32_t) * (uint64_t)p->tasks[p->task_sel].n_rows);
+    o_out = need;
+    if (!d_sse) need += up(sizeof(unsigned long long) * p->images.size());
+  } else {
+    o_slots = need;
+    need += up(sizeof(unsigned long long) * p->images.size() * (uint64_t)p->sse_slots);
+  }
+  if (need > kStaticScratchBytes)
+    return fail(ADCT16_E_SHAPE, "the batch needs %llu bytes of scratch; the static scratch holds %llu",
+                (unsigned long long)need, (unsigned long long)kStaticScratchBytes);
+  unsigned char* base = nullptr;
+  if (adct16_status st = static_scratch(dev, &base)) return st;
+  const Workspace ws{reinterpret_cast<uint32_t*>(base + o_task), reinterpret_cast<unsigned long long*>(base + o_slots),
+                     reinterpret_cast<unsigned long long*>(base + o_out), true};
+  return compress_impl(p, backend, grid, p->task_sel, ws, d_in, d_out, d_qcoef, d_sse, d_psnr, (hipStream_t)stream);
 }
 
 adct16_status adct16_dct_forward(adct16_plan p, const void* d_in, float* d_y, int32_t precision, void* stream) {
