@@ -1,13 +1,15 @@
 """Throughput of the 16x16 approximate-DCT hot path on one MI355X.
 
-Default workload: 256 synthetic luma frames of 1920x1088 uint8 (AR(1)
-fields, rho = 0.95, plus 8 translating 64x64 flat rectangles per frame).
-One step = one adct16_compress_and_measure call over the whole batch:
-forward transform -> zonal retention of the top-left r x r coefficients ->
-exact inverse -> reconstruction written to HBM -> per-frame SSE and PSNR.
-Inputs are resident in HBM before timing starts.
+Default workload: 64 synthetic luma frames of 3840x2160 uint8 (AR(1)
+fields, rho = 0.95, plus 8 translating 64x64 flat rectangles per frame),
+531 Mpx.  One step = one adct16_compress_and_measure call over the whole
+batch: forward transform -> zonal retention of the top-left r x r
+coefficients -> exact inverse -> reconstruction written to HBM -> per-frame
+SSE and PSNR.  The same line carries the 256-frame 1920x1088 batch.  Inputs
+are resident in HBM before timing starts.
 
-    python bench.py [--steps K] [--warmup W] [--workload luma|ragged|residual]
+    python bench.py [--steps K] [--warmup W]
+                    [--workload target|luma|ragged|residual|rd|sweep|vector]
 
 Prints one JSON line.  --gpus N > 1 is refused (one-GPU build).
 """
@@ -16,6 +18,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -29,6 +32,8 @@ HBM_PEAK_GBS = 8000.0
 N_FRAMES, H, W = 256, 1088, 1920
 COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_hbm_counters.json")
 SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_sq_counters.json")
+UHD_COUNTERS = os.path.join(ROOT, "profiles", "fused_uhd64_hbm_counters.json")
+UHD_SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_uhd64_sq_counters.json")
 RES_COUNTERS = os.path.join(ROOT, "profiles", "fused_residual8_hbm_counters.json")
 RES_SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_residual8_sq_counters.json")
 RD_COUNTERS = os.path.join(ROOT, "profiles", "fused_rd8_hbm_counters.json")
@@ -46,8 +51,8 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["luma", "uhd", "ragged", "residual", "rd", "sweep", "vector"],
-                    default="luma")
+    ap.add_argument("--workload", choices=["target", "luma", "uhd", "ragged", "residual", "rd", "sweep", "vector"],
+                    default="target")
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--backend", choices=["auto", "valu", "mfma"], default="auto")
     ap.add_argument("--frames", type=int, default=None)
@@ -57,7 +62,8 @@ def _parse():
                     help="rd workload: one QP instead of all four")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=128)
+    ap.add_argument("--cpu-frames", type=int, default=64)
+    ap.add_argument("--no-c2", action="store_true", help="target workload: skip the 1920x1088 batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the input size (HBM counter scaling)")
     return ap.parse_args()
@@ -143,20 +149,40 @@ def _compute(kernel_name: str, kernel_s: float, path: str = SQ_COUNTERS, workloa
     return res
 
 
-def _cpu_baseline(frames, keep_r, n):
-    """The oracle, as it stands, on the first n frames, one frame per thread."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_baseline(frames, keep_r, n_single, n_all, threads=16):
+    """The oracle, as it stands, timed on the host: single-threaded on the
+    first n_single frames, then on `threads` threads (the GPU's share of the
+    host cores) over the first n_all frames, one frame per task."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import codec
     keep = codec.mask_zonal(keep_r)
-    cores = max(1, min(16, os.cpu_count() or 1))
+    h, w = frames.shape[1:]
+    t0 = time.perf_counter()
+    for t in range(n_single):
+        codec.compress_kept(frames[t], keep)
+    dt1 = time.perf_counter() - t0
+    cores = max(1, min(threads, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else threads))
     t0 = time.perf_counter()
     with ThreadPoolExecutor(cores) as ex:
-        list(ex.map(lambda t: codec.compress_kept(frames[t], keep), range(n)))
+        list(ex.map(lambda t: codec.compress_kept(frames[t], keep), range(n_all)))
     dt = time.perf_counter() - t0
-    h, w = frames.shape[1:]
-    return {"value": round(n * h * w / dt / 1e9, 6), "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} of the {len(frames)} frames, forward + zonal r={keep_r} + inverse + PSNR "
-                      f"({dt:.1f} s wall on {cores} threads)"}
+    return {"value": round(n_all * h * w / dt / 1e9, 6), "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_all} of the {len(frames)} {w}x{h} frames, forward + zonal r={keep_r} + inverse + SSE/PSNR "
+                      f"({dt:.1f} s wall on {cores} threads, one frame per thread)",
+            "single_thread": {"value": round(n_single * h * w / dt1 / 1e9, 6), "unit": "Gpixel/s", "cores": 1,
+                              "sample": f"{n_single} frames ({dt1:.1f} s)"},
+            "host_nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def _fused_kernel_name(plan_info):
@@ -166,160 +192,248 @@ def _fused_kernel_name(plan_info):
     return "k_fused<0, 0, 5, 1>"
 
 
-def bench_luma(args, A, torch):
-    from synth import BASE_SEED, luma_batch
-    n = args.frames or N_FRAMES
-    frames = luma_batch(BASE_SEED + 2, n, H, W)
-    dev = torch.from_numpy(frames.reshape(-1)).cuda()
-    out = torch.empty_like(dev)
-    sse = torch.zeros(n, dtype=torch.int64, device="cuda")
-    psnr = torch.zeros(n, dtype=torch.float64, device="cuda")
-    offs = [i * H * W for i in range(n)]
-    backend = {"auto": A.BACKEND_AUTO, "valu": A.BACKEND_VALU, "mfma": A.BACKEND_MFMA}[args.backend]
+def _arith(plan_info) -> str:
+    """The arithmetic the fused kernel computes in."""
+    if plan_info["backend"] == "mfma":
+        return "fp16 x fp16 -> fp32 MFMA (exact integer values) + fp32 rounding"
+    return "int16/int32 vector adds (Eq. 1 butterflies)"
 
-    def make(be, r=args.r, flags=0):
-        return A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32,
-                      qmode=A.Q_ZONAL, r=r, backend=be, flags=flags)
 
-    plan = make(backend, flags=A.FLAG_AUTOTUNE if backend == A.BACKEND_AUTO else 0)
-    info = json.loads(plan.info())
-    stream = torch.cuda.current_stream()
-    step = lambda: plan.compress_and_measure(dev, out, None, sse, psnr)
-    for _ in range(args.warmup):
+def _timed_fused(plan, step, steps, warmup, stream, torch):
+    """Warm-up, then `steps` timed calls: HIP events on the launch stream
+    around the whole timed loop (step time, both kernels), and the library's
+    event pair around the persistent kernel of every timed call."""
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ms = _events_ms(step, args.steps, stream)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / args.steps * 1e3
-    npx = n * H * W
-    value = npx / (ms * 1e-3) / 1e9
-
-    # Dominant kernel: the fused persistent kernel (plus a 1-thread-per-image
-    # clear of the SSE accumulators), timed on the launch stream.
-    kms = _events_ms(lambda: plan.compress_and_measure(dev, out, None, sse, None), args.steps, stream)
-    alg_bytes = 2 * npx  # read the 8-bit input once, write the 8-bit reconstruction once
-    achieved = alg_bytes / (kms * 1e-3) / 1e9
-    kname = _fused_kernel_name(info)
-    traffic = _traffic(kname)
-    # Attainable-bandwidth context: a plain device copy of the same bytes.
-    cms = _events_ms(lambda: out.copy_(dev), args.steps, stream)
-    copy_gbs = alg_bytes / (cms * 1e-3) / 1e9
-    if args.calibrate_copy:
-        torch.cuda.synchronize()
-        out.copy_(dev)  # plain copy kernel: reads npx bytes, writes npx bytes
-        torch.cuda.synchronize()
-        step()
-        torch.cuda.synchronize()
-    res = {
-        "metric": "Gpixel/s 2D fwd+quant+inv 16x16 (MFMA vs VALU), % HBM peak, bit-exact",
-        "value": round(value, 4), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "wall_ms_per_step": round(wall, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": f"{n} luma frames {W}x{H} uint8 (AR(1) rho=0.95 + 8 moving 64x64 flat "
-                               f"rectangles): forward -> zonal r={args.r} -> inverse -> reconstruction -> "
-                               f"per-frame PSNR, one fused launch",
-                   "frames": n, "height": H, "width": W, "r": args.r, "plan": info},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": round(traffic / 1e9, 4) if traffic else None,
-                     "traffic_unit": "GB per launch", "algorithmic_bytes": alg_bytes,
-                     "kernel": kname, "kernel_ms": round(kms, 4),
-                     "copy_same_bytes_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
-                     "compute": _compute(kname, kms * 1e-3)},
-        "psnr_mean_db": round(float(psnr[torch.isfinite(psnr)].mean()), 4),
-    }
-    if not args.no_variants:
-        v = {}
-        for name, be, fl in (("valu", A.BACKEND_VALU, 0), ("mfma", A.BACKEND_MFMA, 0),
-                             ("mfma_explicit_coef", A.BACKEND_MFMA, A.FLAG_EXPLICIT_COEF)):
-            for r in (args.r, 16):
-                p2 = make(be, r=r, flags=A.FLAG_AUTOTUNE | fl)
-                f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)
-                f()
-                vms = _events_ms(f, max(3, args.steps // 2), stream)
-                v[f"fused_{name}_r{r}_gpix_s"] = round(npx / (vms * 1e-3) / 1e9, 4)
-        # the Walsh-Hadamard matrix through the same fused kernels
-        for name, be in (("valu", A.BACKEND_VALU), ("mfma", A.BACKEND_MFMA)):
-            p2 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32, qmode=A.Q_ZONAL,
-                        r=args.r, backend=be, flags=A.FLAG_AUTOTUNE, matrix=A.MATRIX_WHT)
-            f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)
-            f()
-            vms = _events_ms(f, max(3, args.steps // 2), stream)
-            v[f"fused_wht_{name}_r{args.r}_gpix_s"] = round(npx / (vms * 1e-3) / 1e9, 4)
-        # Unfused pipeline through HBM: forward (int16 centred Z, matrix
-        # cores) -> retention in place -> inverse -> measure.
-        p3 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I16, qmode=A.Q_ZONAL,
-                    r=args.r, backend=A.BACKEND_MFMA)
-        coef = torch.empty(p3.num_blocks * 256, dtype=torch.int16, device="cuda")
-        stages = {"forward_u8_to_i16": (lambda: p3.forward(dev, coef), 3),
-                  "quantise_i16_inplace": (lambda: p3.quantise(coef, coef), 4),
-                  "inverse_i16_to_u8": (lambda: p3.inverse(coef, out), 3),
-                  "measure_u8": (lambda: p3.measure(dev, out, sse, psnr), 2)}
-        tot = 0.0
-        for key, (f, bpp) in stages.items():
-            f()
-            t = _events_ms(f, max(3, args.steps // 2), stream)
-            tot += t
-            v[f"{key}_gbs"] = round(bpp * npx / (t * 1e-3) / 1e9, 1)
-        v["unfused_pipeline_gpix_s"] = round(npx / (tot * 1e-3) / 1e9, 4)
-        p4 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32, backend=A.BACKEND_MFMA)
-        coef32 = torch.empty(p4.num_blocks * 256, dtype=torch.int32, device="cuda")
-        f = lambda: p4.forward(dev, coef32)
-        f()
-        t = _events_ms(f, max(3, args.steps // 2), stream)
-        v["forward_mfma_u8_to_i32_gbs"] = round(5 * npx / (t * 1e-3) / 1e9, 1)
-        p5 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32, backend=A.BACKEND_MFMA,
-                    flags=A.FLAG_MFMA_INT8)
-        f = lambda: p5.forward(dev, coef32)
-        f()
-        t = _events_ms(f, max(3, args.steps // 2), stream)
-        v["forward_mfma_int8_u8_to_i32_gbs"] = round(5 * npx / (t * 1e-3) / 1e9, 1)
-        p6 = A.Plan([H] * n, [W] * n, [W] * n, offs, in_dtype=A.U8, coef_dtype=A.I32, backend=A.BACKEND_VALU)
-        f = lambda: p6.forward(dev, coef32)
-        f()
-        t = _events_ms(f, max(3, args.steps // 2), stream)
-        v["forward_valu_u8_to_i32_gbs"] = round(5 * npx / (t * 1e-3) / 1e9, 1)
-        res["variants"] = v
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = _cpu_baseline(frames, args.r, min(args.cpu_frames, n))
-    return res
+    plan.time_fused(steps)
+    ms = _events_ms(step, steps, stream)
+    kt = plan.fused_times()
+    plan.time_fused(0)
+    return ms, kt
 
 
-def bench_uhd(args, A, torch):
-    """3840x2160 luma frames (AR(1) plus moving flat rectangles, as the 1080p
-    workload): one fused forward -> zonal r -> inverse -> per-frame PSNR
-    launch over the batch, autotuned, against HBM peak and a device copy."""
-    from synth import BASE_SEED, luma_batch
-    n, h, w = args.frames or 64, 2160, 3840
-    frames = luma_batch(BASE_SEED + 7, n, h, w)
+def _frames_point(A, torch, frames, r, backend, flags, steps, warmup):
+    """One fused forward -> zonal r -> inverse -> reconstruction -> per-frame
+    SSE/PSNR call over a batch of equal frames, autotuned."""
+    n, h, w = frames.shape
     dev = torch.from_numpy(frames.reshape(-1)).cuda()
     out = torch.empty_like(dev)
     sse = torch.zeros(n, dtype=torch.int64, device="cuda")
     psnr = torch.zeros(n, dtype=torch.float64, device="cuda")
     plan = A.Plan([h] * n, [w] * n, [w] * n, [i * h * w for i in range(n)], in_dtype=A.U8, coef_dtype=A.I32,
-                  qmode=A.Q_ZONAL, r=args.r, flags=A.FLAG_AUTOTUNE)
+                  qmode=A.Q_ZONAL, r=r, backend=backend, flags=flags)
     stream = torch.cuda.current_stream()
     step = lambda: plan.compress_and_measure(dev, out, None, sse, psnr)
-    for _ in range(args.warmup):
-        step()
-    ms = _events_ms(step, args.steps, stream)
+    ms, kt = _timed_fused(plan, step, steps, warmup, stream, torch)
+    return {"plan": plan, "dev": dev, "out": out, "sse": sse, "psnr": psnr, "ms": ms, "kt": kt,
+            "npx": n * h * w, "info": json.loads(plan.info())}
+
+
+def _parity_sample(frames, pt, r, idx):
+    """Frames `idx` of the batch against the oracle (outside the timed
+    region): reconstruction and SSE bit-exact, PSNR within 1e-3 dB."""
+    from oracle import codec
+    n, h, w = frames.shape
+    keep = codec.mask_zonal(r)
+    out = pt["out"].view(n, h, w)
+    ok = True
+    for t in idx:
+        rec, s, p = codec.compress_kept(frames[t], keep)
+        ok &= bool(np.array_equal(out[t].cpu().numpy(), rec)) and int(pt["sse"][t]) == s
+        g = float(pt["psnr"][t])
+        ok &= (g == p) if math.isinf(p) else abs(g - p) < 1e-3
+    return {"frames": list(idx), "bar": "reconstruction and SSE bit-exact, PSNR within 1e-3 dB of the oracle",
+            "ok": ok}
+
+
+def _roofline_hbm(pt, alg_bytes, kname, copy_gbs, counters=None, sq=None):
+    kt = pt["kt"]
+    kmean = float(np.mean(kt))
+    achieved = alg_bytes / (kmean * 1e-3) / 1e9
+    traffic = _traffic(kname, counters) if counters else None
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic / 1e9, 4) if traffic else None, "traffic_unit": "GB per launch",
+            "algorithmic_bytes": alg_bytes, "kernel": kname,
+            "kernel_ms_mean": round(kmean, 4), "kernel_ms_median": round(float(np.median(kt)), 4),
+            "kernel_launches": len(kt),
+            "timing": "HIP events on the launch stream around the persistent kernel of every timed step "
+                      "(adct16_plan_time_fused); the step also runs the per-image SSE/PSNR kernel",
+            "copy_same_bytes_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+            "compute": _compute(kname, kmean * 1e-3, sq) if sq else None}
+
+
+FORM = ("collapsed operator: N = G Xc G with G = T^T diag(w m) T (forward column pass, zonal retention and "
+        "inverse column pass as one exact contraction; Z is not formed)")
+
+
+def bench_target(args, A, torch):
+    """Default line: the spec configuration, 2-D forward + zonal
+    retention + inverse at 3840x2160 (64 luma frames, 531 Mpx, above the
+    256 MB MALL), one fused launch per step; the 1920x1088 batch (256 frames)
+    measured the same way in the same line."""
+    from synth import BASE_SEED, luma_batch
+    n = args.frames or 64
+    seed = BASE_SEED + 7
+    frames = luma_batch(seed, n, 2160, 3840)
+    backend = {"auto": A.BACKEND_AUTO, "valu": A.BACKEND_VALU, "mfma": A.BACKEND_MFMA}[args.backend]
+    pt = _frames_point(A, torch, frames, args.r, backend, A.FLAG_AUTOTUNE, args.steps, args.warmup)
+    stream = torch.cuda.current_stream()
+    npx = pt["npx"]
+    alg = 2 * npx  # read the 8-bit input once, write the 8-bit reconstruction once
+    cbuf = torch.empty_like(pt["dev"])  # a plain copy of the same bytes (not into the reconstruction)
+    cms = _events_ms(lambda: cbuf.copy_(pt["dev"]), args.steps, stream)
+    del cbuf
+    kname = _fused_kernel_name(pt["info"])
+    res = {
+        "metric": "Gpixel/s 2D fwd+quant+inv 16x16 (MFMA vs VALU), % HBM peak, bit-exact",
+        "value": round(npx / (pt["ms"] * 1e-3) / 1e9, 4), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(pt["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": _arith(pt["info"]), "data": "synthetic",
+        "config": {"workload": f"{n} luma frames 3840x2160 uint8 (AR(1) rho=0.95 + 8 moving 64x64 flat rectangles): "
+                               f"forward -> zonal r={args.r} -> inverse -> reconstruction -> per-frame SSE/PSNR, "
+                               "one fused launch per step",
+                   "frames": n, "height": 2160, "width": 3840, "r": args.r, "seed": seed, "form": FORM,
+                   "plan": pt["info"]},
+        "roofline": _roofline_hbm(pt, alg, kname, alg / (cms * 1e-3) / 1e9, UHD_COUNTERS, UHD_SQ_COUNTERS),
+        "target_frac": 0.70,
+        "parity": _parity_sample(frames, pt, args.r, (0, n - 1)),
+        "psnr_mean_db": round(float(pt["psnr"][torch.isfinite(pt["psnr"])].mean()), 4),
+    }
+    if not args.no_variants:
+        v = {}
+        for name, be, fl in (("valu", A.BACKEND_VALU, 0), ("mfma", A.BACKEND_MFMA, 0),
+                             ("mfma_explicit_coef", A.BACKEND_MFMA, A.FLAG_EXPLICIT_COEF)):
+            q = _frames_point(A, torch, frames, args.r, be, A.FLAG_AUTOTUNE | fl, max(3, args.steps // 2), 1)
+            v[f"fused_{name}_r{args.r}_gpix_s"] = round(npx / (q["ms"] * 1e-3) / 1e9, 4)
+            v[f"fused_{name}_r{args.r}_kernel_frac"] = round(alg / (np.mean(q["kt"]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            del q
+        res["variants"] = v
+    del pt
+    # the 1920x1088 batch (256 frames), the same call
+    if not args.no_c2:
+        from synth import luma_batch as lb
+        seed2 = BASE_SEED + 2
+        f2 = lb(seed2, N_FRAMES, H, W)
+        p2 = _frames_point(A, torch, f2, args.r, backend, A.FLAG_AUTOTUNE, args.steps, args.warmup)
+        k2 = _fused_kernel_name(p2["info"])
+        cbuf = torch.empty_like(p2["dev"])
+        c2ms = _events_ms(lambda: cbuf.copy_(p2["dev"]), args.steps, stream)
+        del cbuf
+        roof2 = _roofline_hbm(p2, 2 * p2["npx"], k2, 2 * p2["npx"] / (c2ms * 1e-3) / 1e9, COUNTERS, SQ_COUNTERS)
+        res["c2_1920x1088"] = {
+            "workload": f"{N_FRAMES} luma frames {W}x{H} uint8, same content model and call, zonal r={args.r}",
+            "seed": seed2, "value": round(p2["npx"] / (p2["ms"] * 1e-3) / 1e9, 4), "unit": "Gpixel/s",
+            "ms_per_step": round(p2["ms"], 4), "roofline": roof2, "plan": p2["info"],
+            "parity": _parity_sample(f2, p2, args.r, (0, N_FRAMES - 1))}
+        del p2
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = _cpu_baseline(frames, args.r, min(4, n), min(args.cpu_frames, n))
+    return res
+
+
+def bench_luma(args, A, torch):
+    """The 1920x1088 batch alone (256 frames, or --frames)."""
+    from synth import BASE_SEED, luma_batch
+    n = args.frames or N_FRAMES
+    seed = BASE_SEED + 2
+    frames = luma_batch(seed, n, H, W)
+    backend = {"auto": A.BACKEND_AUTO, "valu": A.BACKEND_VALU, "mfma": A.BACKEND_MFMA}[args.backend]
+    pt = _frames_point(A, torch, frames, args.r, backend, A.FLAG_AUTOTUNE if backend == A.BACKEND_AUTO else 0,
+                       args.steps, args.warmup)
+    stream = torch.cuda.current_stream()
+    npx = pt["npx"]
+    cbuf = torch.empty_like(pt["dev"])  # a plain copy of the same bytes (not into the reconstruction)
+    cms = _events_ms(lambda: cbuf.copy_(pt["dev"]), args.steps, stream)
+    del cbuf
+    kname = _fused_kernel_name(pt["info"])
+    res = {
+        "metric": "Gpixel/s 2D fwd+quant+inv 16x16 (MFMA vs VALU), % HBM peak, bit-exact",
+        "value": round(npx / (pt["ms"] * 1e-3) / 1e9, 4), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(pt["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": _arith(pt["info"]), "data": "synthetic",
+        "config": {"workload": f"{n} luma frames {W}x{H} uint8 (AR(1) rho=0.95 + 8 moving 64x64 flat "
+                               f"rectangles): forward -> zonal r={args.r} -> inverse -> reconstruction -> "
+                               f"per-frame PSNR, one fused launch",
+                   "frames": n, "height": H, "width": W, "r": args.r, "seed": seed, "form": FORM, "plan": pt["info"]},
+        "roofline": _roofline_hbm(pt, 2 * npx, kname, 2 * npx / (cms * 1e-3) / 1e9, COUNTERS, SQ_COUNTERS),
+        "parity": _parity_sample(frames, pt, args.r, (0, n - 1)),
+        "psnr_mean_db": round(float(pt["psnr"][torch.isfinite(pt["psnr"])].mean()), 4),
+    }
+    if args.calibrate_copy:
+        torch.cuda.synchronize()
+        pt["out"].copy_(pt["dev"])  # plain copy kernel: reads npx bytes, writes npx bytes
+        torch.cuda.synchronize()
+    if not args.no_variants:
+        res["variants"] = _luma_variants(args, A, torch, pt, frames)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = _cpu_baseline(frames, args.r, min(8, n), min(args.cpu_frames, n))
+    return res
+
+
+def _luma_variants(args, A, torch, pt, frames):
+    n, h, w = frames.shape
     npx = n * h * w
-    cms = _events_ms(lambda: out.copy_(dev), args.steps, stream)
-    achieved = 2 * npx / (ms * 1e-3) / 1e9
-    copy_gbs = 2 * npx / (cms * 1e-3) / 1e9
-    return {"metric": "Gpixel/s 2D fwd+quant+inv 16x16, 3840x2160 frames, % HBM peak",
-            "value": round(npx / (ms * 1e-3) / 1e9, 4), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "u8",
-            "data": "synthetic",
-            "config": {"workload": f"{n} luma frames {w}x{h} uint8 (AR(1) rho=0.95 + 8 moving 64x64 flat "
-                                   f"rectangles), zonal r={args.r}, one fused launch, per-frame PSNR",
-                       "frames": n, "plan": json.loads(plan.info())},
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes": 2 * npx,
-                         "copy_same_bytes_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
-            "psnr_mean_db": round(float(psnr[torch.isfinite(psnr)].mean()), 4)}
+    dev, out, sse, psnr = pt["dev"], pt["out"], pt["sse"], pt["psnr"]
+    offs = [i * h * w for i in range(n)]
+    stream = torch.cuda.current_stream()
+    reps = max(3, args.steps // 2)
+
+    def make(be, r=args.r, flags=0, **kw):
+        return A.Plan([h] * n, [w] * n, [w] * n, offs, in_dtype=A.U8, coef_dtype=kw.pop("coef", A.I32),
+                      qmode=A.Q_ZONAL, r=r, backend=be, flags=flags, **kw)
+
+    v = {}
+    for name, be, fl in (("valu", A.BACKEND_VALU, 0), ("mfma", A.BACKEND_MFMA, 0),
+                         ("mfma_explicit_coef", A.BACKEND_MFMA, A.FLAG_EXPLICIT_COEF)):
+        for r in (args.r, 16):
+            p2 = make(be, r=r, flags=A.FLAG_AUTOTUNE | fl)
+            f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)
+            f()
+            vms = _events_ms(f, reps, stream)
+            v[f"fused_{name}_r{r}_gpix_s"] = round(npx / (vms * 1e-3) / 1e9, 4)
+    # the Walsh-Hadamard matrix through the same fused kernels
+    for name, be in (("valu", A.BACKEND_VALU), ("mfma", A.BACKEND_MFMA)):
+        p2 = make(be, flags=A.FLAG_AUTOTUNE, matrix=A.MATRIX_WHT)
+        f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)
+        f()
+        vms = _events_ms(f, reps, stream)
+        v[f"fused_wht_{name}_r{args.r}_gpix_s"] = round(npx / (vms * 1e-3) / 1e9, 4)
+    # Unfused pipeline through HBM: forward (int16 centred Z, matrix cores)
+    # -> retention in place -> inverse -> measure.
+    p3 = make(A.BACKEND_MFMA, coef=A.I16)
+    coef = torch.empty(p3.num_blocks * 256, dtype=torch.int16, device="cuda")
+    stages = {"forward_u8_to_i16": (lambda: p3.forward(dev, coef), 3),
+              "quantise_i16_inplace": (lambda: p3.quantise(coef, coef), 4),
+              "inverse_i16_to_u8": (lambda: p3.inverse(coef, out), 3),
+              "measure_u8": (lambda: p3.measure(dev, out, sse, psnr), 2)}
+    tot = 0.0
+    for key, (f, bpp) in stages.items():
+        f()
+        t = _events_ms(f, reps, stream)
+        tot += t
+        v[f"{key}_gbs"] = round(bpp * npx / (t * 1e-3) / 1e9, 1)
+    v["unfused_pipeline_gpix_s"] = round(npx / (tot * 1e-3) / 1e9, 4)
+    del coef
+    coef32 = torch.empty(p3.num_blocks * 256, dtype=torch.int32, device="cuda")
+    for key, be, fl in (("forward_mfma_u8_to_i32_gbs", A.BACKEND_MFMA, 0),
+                        ("forward_mfma_int8_u8_to_i32_gbs", A.BACKEND_MFMA, A.FLAG_MFMA_INT8),
+                        ("forward_valu_u8_to_i32_gbs", A.BACKEND_VALU, 0)):
+        p4 = A.Plan([h] * n, [w] * n, [w] * n, offs, in_dtype=A.U8, coef_dtype=A.I32, backend=be, flags=fl)
+        f = lambda: p4.forward(dev, coef32)
+        f()
+        t = _events_ms(f, reps, stream)
+        v[key] = round(5 * npx / (t * 1e-3) / 1e9, 1)
+    # the exact DCT-II comparison transform on the matrix cores: uint8 in,
+    # float32 Y out (1 + 4 bytes per pixel)
+    y = coef32.view(torch.float32)
+    for key, prec in (("dct_fp16_mfma_u8_to_f32_gbs", A.F16), ("dct_bf16_mfma_u8_to_f32_gbs", A.BF16)):
+        f = lambda: p3.dct_forward(dev, y, prec)
+        f()
+        t = _events_ms(f, reps, stream)
+        v[key] = round(5 * npx / (t * 1e-3) / 1e9, 1)
+    return v
 
 
 def bench_ragged(args, A, torch):
@@ -364,15 +478,27 @@ def bench_ragged(args, A, torch):
     return res
 
 
+def _residual_planes(seed, nf):
+    """Y, U, V residual planes of frames 0..nf-1 (3840x2160 4:2:0), generated
+    on 16 host threads, with a progress line on stderr every 30 frames."""
+    from concurrent.futures import ThreadPoolExecutor
+    from synth import yuv420_residual_frame
+    out = [None] * nf
+    with ThreadPoolExecutor(16) as ex:
+        for t, fr in enumerate(ex.map(lambda k: yuv420_residual_frame(seed, k), range(nf))):
+            out[t] = fr
+            if (t + 1) % 30 == 0:
+                print(f"bench: generated {t + 1}/{nf} residual frames", file=sys.stderr, flush=True)
+    return [p for fr in out for p in fr]
+
+
 def bench_residual(args, A, torch):
     """4:2:0 int16 residual frames (Y 3840x2160, U/V 1920x1080); uniform
     quantiser q in {8, 16, 32}; per frame one fused call (levels and
     reconstruction written, per-plane PSNR) replayed from a HIP graph."""
-    from synth import BASE_SEED, pack_images, yuv420_residual_frame
-    nf = args.frames or 8
-    planes = []
-    for t in range(nf):
-        planes += yuv420_residual_frame(BASE_SEED + 5, t)
+    from synth import BASE_SEED, pack_images
+    nf = args.frames or 120
+    planes = _residual_planes(BASE_SEED + 5, nf)
     per = len(planes) // nf
     # one packed buffer per frame so that each frame has its own graph
     bufs = [pack_images(planes[i * per:(i + 1) * per]) for i in range(nf)]
@@ -469,11 +595,9 @@ def bench_rd(args, A, torch):
     residual stream: for QP in {22, 27, 32, 37} (inter offset 1/6), one fused
     launch over all frames (levels and reconstruction written, per-plane SSE),
     then the signed Exp-Golomb rate proxy of the levels."""
-    from synth import BASE_SEED, pack_images, yuv420_residual_frame
-    nf = args.frames or 8
-    planes = []
-    for t in range(nf):
-        planes += yuv420_residual_frame(BASE_SEED + 5, t)
+    from synth import BASE_SEED, pack_images
+    nf = args.frames or 120
+    planes = _residual_planes(BASE_SEED + 5, nf)
     buf, hs, ws, ps, offs = pack_images(planes, align_elems=64, pitch_multiple=64)
     dev = torch.from_numpy(buf).cuda()
     rec = torch.empty_like(dev)
@@ -555,12 +679,14 @@ def bench_sweep(args, A, torch):
         plan.ssim(dev, out, ssim_d)
         pa, pd = psnr_a.cpu().numpy(), psnr_d.cpu().numpy()
         sa, sd = ssim_a.cpu().numpy(), ssim_d.cpu().numpy()
-        ape = 100.0 * np.abs(pa - pd) / pd
         fin = lambda x, nd: round(float(x), nd) if np.isfinite(x) else None  # lossless: +inf dB, no APE
+        # APE is defined where both PSNRs are finite (a lossless reference has none)
+        both = np.isfinite(pa) & np.isfinite(pd)
+        ape = 100.0 * np.abs(pa[both] - pd[both]) / pd[both]
         rows.append({"r": r, "compression_pct": round(100.0 * (1 - r / 256.0), 2),
                      "psnr_approx_db": fin(pa.mean(), 4), "psnr_dct_db": fin(pd.mean(), 4),
                      "ssim_approx": fin(sa.mean(), 5), "ssim_dct": fin(sd.mean(), 5),
-                     "ape_pct": fin(ape.mean(), 4) if np.all(np.isfinite(pd)) else None})
+                     "ape_pct": fin(ape.mean(), 4) if both.all() else None})
     wall = time.perf_counter() - t0
     return {"metric": "Section 4 sweep: mean PSNR / SSIM / APE vs zig-zag r (approximate vs exact DCT-II)",
             "value": rows[8]["ape_pct"], "unit": "APE % at r=16", "n_gpus": 1, "higher_is_better": False,
@@ -607,7 +733,7 @@ def main():
     import torch
 
     import paper_1606_05562_amd as A
-    fn = {"luma": bench_luma, "uhd": bench_uhd, "ragged": bench_ragged, "residual": bench_residual, "rd": bench_rd,
+    fn = {"target": bench_target, "uhd": bench_target, "luma": bench_luma, "ragged": bench_ragged, "residual": bench_residual, "rd": bench_rd,
           "sweep": bench_sweep, "vector": bench_vector}[args.workload]
     print(json.dumps(fn(args, A, torch)), flush=True)
 

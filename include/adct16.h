@@ -107,12 +107,31 @@ enum {
                                     forward column pass, the zonal retention and the inverse
                                     column pass are applied as one exact contraction with
                                     G = T^T diag(w m) T; results are identical) */
-  ADCT16_FLAG_MFMA_INT8 = 4,     /* adct16_forward with the MFMA backend: int8 products with
-                                    int32 accumulation (the pixels centred to int8, the
-                                    column pass on base-64 hi/lo digit planes of the row-pass
-                                    result) instead of FP16 products; results are identical */
-  ADCT16_FLAG_DEADZONE_INTER = 8 /* deadzone quantiser rounding offset f = 1/6 (inter-coded
+  ADCT16_FLAG_MFMA_INT8 = 4,     /* MFMA backend, int8 products with int32 accumulation
+                                    instead of FP16 products; results are identical.
+                                    adct16_forward: the pixels centred to int8, the column
+                                    pass on base-64 hi/lo digit planes of the row-pass
+                                    result.  Fused call with a separable mask (none or zonal;
+                                    not with ADCT16_FLAG_EXPLICIT_COEF): N = G Xc G with
+                                    G = T^T diag(w m) T in int8, the intermediate Xc G on
+                                    signed base-256 hi/lo digit planes.  Zig-zag masks keep
+                                    the FP16 form (adct16_plan_info "fused_form") */
+  ADCT16_FLAG_DEADZONE_INTER = 8, /* deadzone quantiser rounding offset f = 1/6 (inter-coded
                                     residuals) instead of 1/3 (intra) */
+  ADCT16_FLAG_RESIDUAL_RANGE = 16 /* I16 input whose samples all lie in [-256, 255] (the
+                                    difference of two 8-bit samples, Section 5.3's residual
+                                    planes).  With the MFMA backend (or AUTO with
+                                    ADCT16_FLAG_AUTOTUNE), a uniform step q >= 8 or a
+                                    deadzone QP >= 22, and I16 out_dtype, the fused call
+                                    (with or without levels) runs on the matrix cores:
+                                    exact FP16 products with FP32 accumulation for the
+                                    forward and four integer partial inverses, combined per
+                                    pixel in float64; results as the VALU kernel's (levels
+                                    bit-exact, reconstructions equal except where the
+                                    float64 value lies within 1e-9 of a rounding tie).  The
+                                    kernel checks the range: an image with a sample outside
+                                    it gets SSE -1 and PSNR NaN, and its levels and
+                                    reconstruction are unspecified. */
 };
 
 /*
@@ -120,7 +139,8 @@ enum {
  *
  * in_dtype    ADCT16_U8 (8-bit images, Section 4) or ADCT16_I16 (prediction
  *             residuals, Section 5.3).  The MFMA backend runs the fused
- *             call for U8 input, a mask qmode and U8 out_dtype, and the
+ *             call for U8 input, a mask qmode and U8 out_dtype, or for I16
+ *             residuals as described at ADCT16_FLAG_RESIDUAL_RANGE, and the
  *             forward transform for U8 input to I32/I16 coefficients or
  *             I16 input to I32 coefficients; a plan with neither form is
  *             rejected (ADCT16_E_MODE).  The VALU backend takes every
@@ -199,6 +219,19 @@ adct16_status adct16_plan_num_blocks(adct16_plan plan, int64_t *num_blocks);
  *                       processes (keyed by device, dtypes, modes and the
  *                       batch's strip count). */
 adct16_status adct16_plan_info(adct16_plan plan, char *buf, int32_t buf_len);
+
+/* Measurement of the hot path (the roofline of the persistent kernel):
+ * after adct16_plan_time_fused(plan, n), the next n fused calls on `plan`
+ * (adct16_compress_and_measure, adct16_compress_and_measure_static) record a
+ * pair of HIP events on the call's stream around their persistent kernel
+ * only (not around the SSE / PSNR finishing kernel).  Calls captured into a
+ * HIP graph are not timed.  n = 0 stops timing.  Creates 2n events (host
+ * objects; E_NOMEM if that fails); n outside 0..65536 is ADCT16_E_SHAPE.
+ * adct16_plan_fused_times waits for the recorded calls, writes the first
+ * min(cap, recorded) kernel durations in milliseconds to ms, the number of
+ * recorded calls to *n_out, and starts a new window of n calls. */
+adct16_status adct16_plan_time_fused(adct16_plan plan, int32_t n_calls);
+adct16_status adct16_plan_fused_times(adct16_plan plan, float *ms, int32_t cap, int32_t *n_out);
 
 /* Section 4, forward: d_in (in_dtype) -> d_coef (coef_dtype, block-major).
  * Evaluates T by the 60-addition factorisation of Eq. (1) (VALU backend)
@@ -294,8 +327,8 @@ adct16_status adct16_compress_and_measure(adct16_plan plan, const void *d_in, vo
  * GPU share the array: calls that overlap in time on one GPU (other streams,
  * other threads) race and give undefined results; calls ordered on one
  * stream do not.  The plan's device must be current (ADCT16_E_DEVICE
- * otherwise).  A batch whose scratch exceeds 4 MiB is ADCT16_E_SHAPE (about
- * 4 bytes per task of the matrix-core kernel, 8 bytes per accumulator slot
+ * otherwise).  A batch whose scratch exceeds 4 MiB is ADCT16_E_SHAPE (8
+ * bytes per task of the matrix-core kernels, 8 bytes per accumulator slot
  * of the vector kernel: n_images x 64 slots up to 1024 images, x 8 up to
  * 16384).  Other errors as adct16_compress_and_measure. */
 adct16_status adct16_compress_and_measure_static(adct16_plan plan, const void *d_in, void *d_out,

@@ -30,6 +30,7 @@ FLAG_AUTOTUNE = 1
 FLAG_EXPLICIT_COEF = 2
 FLAG_MFMA_INT8 = 4
 FLAG_DEADZONE_INTER = 8
+FLAG_RESIDUAL_RANGE = 16
 # adct16_matrix
 MATRIX_APPROX, MATRIX_T, MATRIX_WHT, MATRIX_DCT = 0, 1, 2, 3
 
@@ -37,6 +38,7 @@ _TORCH_DTYPE_CODES = {"torch.uint8": U8, "torch.int16": I16, "torch.int32": I32,
 
 EXPORTED = [
     "adct16_plan_create", "adct16_plan_destroy", "adct16_plan_num_blocks", "adct16_plan_info",
+    "adct16_plan_time_fused", "adct16_plan_fused_times",
     "adct16_forward", "adct16_quantise", "adct16_inverse", "adct16_measure", "adct16_rate",
     "adct16_dct_compress_and_measure", "adct16_ssim",
     "adct16_compress_and_measure", "adct16_compress_and_measure_static", "adct16_dct_forward", "adct16_forward_1d", "adct16_inverse_1d",
@@ -83,6 +85,8 @@ def _load():
         "adct16_plan_destroy": [vp],
         "adct16_plan_num_blocks": [vp, ctypes.POINTER(i64)],
         "adct16_plan_info": [vp, ctypes.c_char_p, i32],
+        "adct16_plan_time_fused": [vp, i32],
+        "adct16_plan_fused_times": [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)],
         "adct16_forward": [vp, vp, vp, vp],
         "adct16_quantise": [vp, vp, vp, vp],
         "adct16_inverse": [vp, vp, vp, vp],
@@ -200,6 +204,18 @@ class Plan:
         buf = ctypes.create_string_buffer(1024)
         _check(lib().adct16_plan_info(self._plan, buf, len(buf)))
         return buf.value.decode()
+
+    def time_fused(self, n_calls: int):
+        """Record the persistent kernel's duration on the next n_calls fused calls."""
+        _check(lib().adct16_plan_time_fused(self._plan, n_calls))
+
+    def fused_times(self, cap: int = 65536) -> list[float]:
+        """Kernel durations (ms) of the calls recorded since time_fused (or
+        the previous read); waits for them."""
+        ms = (ctypes.c_float * max(cap, 1))()
+        n = ctypes.c_int32()
+        _check(lib().adct16_plan_fused_times(self._plan, ms, cap, ctypes.byref(n)))
+        return list(ms[:min(n.value, cap)])
 
     def forward(self, inp, coef, stream=None):
         _check(lib().adct16_forward(self._plan, _ptr(inp), _ptr(coef), _stream(stream)))

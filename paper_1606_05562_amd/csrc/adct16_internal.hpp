@@ -72,6 +72,12 @@ struct Tables {
   double sdiag[16];    // s_u = 1 / sqrt(n_u) of the plan's matrix
   signed char tmat[256];  // the plan's integer matrix, tmat[u * 16 + k] (T or Walsh-Hadamard)
   signed char wvec[16];   // inverse weights w_u = 48 / n_u
+  // Matrix-core residual round trip (T only): class of each row of T
+  // (0: norm 16, 1: first four rows of norm 12, 2: the other four, 3: norm 8)
+  // and the float64 factors of R0, R2, R3, R6 (step / 48, step / sqrt(128),
+  // step / sqrt(192), step / sqrt(96)).
+  signed char rcls[16];
+  double rcomb[4];
 };
 
 // The integer matrix of a plan: MAT_APPROX is T of the proposed transform,
@@ -99,6 +105,7 @@ struct Params {
   const RowTask* rows;  // the batch's strips in tasks, image by image, row by row
   int64_t n_rows;
   uint32_t* task_sse;   // per-task SSE partials (matrix-core fused kernel)
+  unsigned long long* task_sse64;  // the same buffer as 64-bit partials (matrix-core residual kernel)
   const int64_t* task_first;  // index of each image's first task (n_images + 1 entries)
   int32_t task_strips;  // longest run of the task table (4 or 16)
   int32_t pad1;
@@ -107,7 +114,7 @@ struct Params {
 // Launchers (return hipSuccess or the launch error).  `grid` is the number
 // of workgroups of kGroupThreads threads for the persistent strip kernels.
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
-hipError_t launch_fill_noise(void* p, int64_t bytes, bool i16, hipStream_t s);
+hipError_t launch_fill_noise(void* p, int64_t bytes, int kind, hipStream_t s);
 hipError_t launch_sse_finalize(const Params& P, unsigned long long* sse, hipStream_t s);
 hipError_t launch_task_sse_reduce(const Params& P, hipStream_t s);
 hipError_t launch_valu_forward(int mat, int in_kind, int coef_kind, const Params& P, int grid, hipStream_t s);
@@ -126,9 +133,12 @@ hipError_t launch_ssim(const Params& P, const int64_t* tile_begin, int64_t n_til
 hipError_t launch_mfma_forward(int coef_kind, bool nt, const Params& P, int grid, hipStream_t s);
 hipError_t launch_mfma_forward_i8(int coef_kind, bool nt, const Params& P, int grid, hipStream_t s);
 hipError_t launch_mfma_forward_i16(bool nt, const Params& P, int grid, hipStream_t s);
-hipError_t launch_mfma_fused(bool zigzag, bool collapse, int out_kind, bool nt, const Params& P, int grid,
+hipError_t launch_mfma_fused(bool zigzag, bool collapse, bool i8, int out_kind, bool nt, const Params& P, int grid,
                              hipStream_t s);
 hipError_t launch_dct_mfma(int in_kind, int precision, const Params& P, float* y, int grid,
                            hipStream_t s);
+hipError_t launch_mfma_resid(int mode, int qout_kind, int out_kind, bool nt, const Params& P, int grid,
+                             hipStream_t s);
+hipError_t launch_task_sse_reduce64(const Params& P, hipStream_t s);
 
 }  // namespace adct16

@@ -140,7 +140,8 @@ struct adct16_plan_s {
     int64_t n_rows = 0;
     int strips = 0;
   } tasks[2];
-  int task_sel = 0;  // table of the calls without level output
+  int task_sel = 0;     // table of the calls without level output
+  int task_sel_lv = 0;  // table of the calls with level output
   uint32_t* d_task_sse = nullptr;  // per-task SSE partials of the matrix-core fused kernel
   int64_t* d_ssim_tiles = nullptr;  // SSIM: first tile of each image (n_images + 1 entries)
   int64_t n_ssim_tiles = 0;
@@ -157,7 +158,12 @@ struct adct16_plan_s {
   // Fused calls that also write the retained coefficients or levels run
   // the vector kernel with its own launch shape.
   int grid_lv = 0;
+  int backend_lv = ADCT16_BACKEND_VALU;  // backend of the fused calls with level output
   std::string tuned_lv;
+  // Launch timing (adct16_plan_time_fused): event pairs recorded around the
+  // persistent kernel of the next prof_ev.size() / 2 fused calls.
+  std::vector<hipEvent_t> prof_ev;
+  int prof_used = 0;
 };
 
 struct adct16_graph_s {
@@ -192,7 +198,7 @@ adct16_status check_plan(adct16_plan p) {
 bool mfma_supported(const adct16_plan_s* p);
 
 // Device memory a fused call uses besides its inputs and outputs: the
-// per-task SSE partials of the matrix-core kernel, the per-image accumulator
+// per-task SSE partials of the matrix-core kernels (8 bytes per task), the per-image accumulator
 // slots of the vector kernel (zero on entry unless `clear_slots`), and the
 // per-image SSE when the caller passes none.
 struct Workspace {
@@ -206,9 +212,36 @@ Workspace plan_workspace(const adct16_plan_s* p) {
   return Workspace{p->d_task_sse, p->d_sse_ws, p->d_sse_out, false};
 }
 
+// The matrix-core fused kernel's number format: int8 products (flag
+// ADCT16_FLAG_MFMA_INT8) for separable masks without explicit coefficients,
+// FP16 products otherwise.
+bool fused_int8(const adct16_plan_s* p) {
+  return (p->d.flags & ADCT16_FLAG_MFMA_INT8) && p->d.qmode != ADCT16_Q_ZIGZAG &&
+         !(p->d.flags & ADCT16_FLAG_EXPLICIT_COEF);
+}
+
 // Whether a fused call runs the matrix-core kernel (else the vector kernel).
+bool resid_supported(const adct16_plan_s* p);
+
 bool fused_on_mfma(const adct16_plan_s* p, int backend, bool levels) {
-  return backend == ADCT16_BACKEND_MFMA && !levels && mfma_supported(p);
+  return backend == ADCT16_BACKEND_MFMA && mfma_supported(p) && (!levels || resid_supported(p));
+}
+
+// Event pair i brackets this call's fused kernel (i = -1: not timed).  Calls
+// captured into a graph are not timed.
+hipError_t prof_begin(adct16_plan_s* p, hipStream_t s, int& i) {
+  i = -1;
+  if (p->prof_used * 2 >= (int)p->prof_ev.size()) return hipSuccess;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess || cs != hipStreamCaptureStatusNone) return e;
+  e = hipEventRecord(p->prof_ev[2 * p->prof_used], s);
+  if (e == hipSuccess) i = p->prof_used++;
+  return e;
+}
+
+hipError_t prof_end(adct16_plan_s* p, hipStream_t s, int i) {
+  return i < 0 ? hipSuccess : hipEventRecord(p->prof_ev[2 * i + 1], s);
 }
 
 adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, const Workspace& ws,
@@ -237,10 +270,18 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, c
     // whole-cache-line rows: streaming (non-temporal) accesses pay off
     const bool nt = p->lines_aligned && (reinterpret_cast<uintptr_t>(d_in) & 127) == 0 &&
                     (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 127) == 0);
-    e = launch_mfma_fused(p->d.qmode == ADCT16_Q_ZIGZAG, !(p->d.flags & ADCT16_FLAG_EXPLICIT_COEF), ok, nt, P,
-                          grid, s);
+    int ti;
+    if ((e = prof_begin(p, s, ti)) != hipSuccess) return hip_fail(e, "timing event");
+    const bool resid = p->in_kind == IN_I16;
+    P.task_sse64 = reinterpret_cast<unsigned long long*>(ws.task_sse);
+    if (resid)
+      e = launch_mfma_resid(p->mode, qk, ok, nt, P, grid, s);
+    else
+      e = launch_mfma_fused(p->d.qmode == ADCT16_Q_ZIGZAG, !(p->d.flags & ADCT16_FLAG_EXPLICIT_COEF), fused_int8(p),
+                            ok, nt, P, grid, s);
     if (e != hipSuccess) return hip_fail(e, "fused kernel");
-    e = launch_task_sse_reduce(P, s);
+    if ((e = prof_end(p, s, ti)) != hipSuccess) return hip_fail(e, "timing event");
+    e = resid ? launch_task_sse_reduce64(P, s) : launch_task_sse_reduce(P, s);
     if (e != hipSuccess) return hip_fail(e, "SSE reduction kernel");
     return ADCT16_OK;
   }
@@ -249,18 +290,29 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, c
     e = launch_zero_u64(ws.sse_slots, P.n_images * P.sse_slots, s);
     if (e != hipSuccess) return hip_fail(e, "clearing kernel");
   }
+  int ti;
+  if ((e = prof_begin(p, s, ti)) != hipSuccess) return hip_fail(e, "timing event");
   e = launch_valu_fused(p->mat, p->in_kind, p->mode, qk, ok, P, grid, s);
   if (e != hipSuccess) return hip_fail(e, "fused kernel");
+  if ((e = prof_end(p, s, ti)) != hipSuccess) return hip_fail(e, "timing event");
   e = launch_sse_finalize(P, out_sse, s);  // also clears the slots
   if (e != hipSuccess) return hip_fail(e, "SSE / PSNR kernel");
   return ADCT16_OK;
 }
 
-// The matrix-core fused kernel covers 8-bit input with retention masks (the
-// quantisers run on the vector ALUs); the matrix-core forward covers 8-bit
-// input to int32 or centred int16 coefficients, and 16-bit input to int32.
+// The matrix-core fused kernels cover 8-bit input with retention masks, and
+// 16-bit residuals in [-256, 255] (declared by ADCT16_FLAG_RESIDUAL_RANGE)
+// with a quantiser step of at least 8 (levels output included); the
+// matrix-core forward covers 8-bit input to int32 or centred int16
+// coefficients, and 16-bit input to int32.
+bool resid_supported(const adct16_plan_s* p) {
+  return p->in_kind == IN_I16 && p->mat == MAT_APPROX && (p->d.flags & ADCT16_FLAG_RESIDUAL_RANGE) &&
+         p->out_kind == OUT_I16 &&
+         ((p->mode == MODE_UNIFORM && p->d.q >= 8) || (p->mode == MODE_DEADZONE && p->d.q >= 22));
+}
+
 bool mfma_supported(const adct16_plan_s* p) {
-  return p->in_kind == IN_U8 && p->mode == MODE_MASK && p->out_kind == OUT_U8;
+  return (p->in_kind == IN_U8 && p->mode == MODE_MASK && p->out_kind == OUT_U8) || resid_supported(p);
 }
 
 bool mfma_forward_supported(const adct16_plan_s* p) {
@@ -277,7 +329,9 @@ std::mutex g_tune_mu;
 std::string tune_key(const adct16_plan_s* p, const char* arch, bool levels) {
   std::ostringstream k;
   k << arch << "/cu" << p->cu_count << "/b" << p->d.backend << "/t" << p->mat << "/in" << p->in_kind << "/m" << p->mode << "/q" << p->d.qmode
-    << "/o" << p->out_kind << "/f" << (p->d.flags & ADCT16_FLAG_EXPLICIT_COEF) << "/lv" << (levels ? p->qcoef_kind : -1)
+    << "/o" << p->out_kind << "/f"
+    << (p->d.flags & (ADCT16_FLAG_EXPLICIT_COEF | ADCT16_FLAG_MFMA_INT8 | ADCT16_FLAG_RESIDUAL_RANGE))
+    << "/lv" << (levels ? p->qcoef_kind : -1)
     << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips) << "/v2";
   return k.str();
 }
@@ -351,7 +405,10 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
       (levels && hipMalloc(&w.dq, qbytes) != hipSuccess))
     return fail(ADCT16_E_NOMEM, "autotune scratch");
   hipError_t e = hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking);
-  if (e == hipSuccess) e = launch_fill_noise(w.din, (int64_t)bytes, p->in_kind == IN_I16, w.s);
+  // noise over the input's range: 8-bit, 16-bit in [-512, 511], or
+  // residuals in [-256, 255] (the matrix-core residual kernel's domain)
+  const int noise = p->in_kind == IN_U8 ? 0 : (p->d.flags & ADCT16_FLAG_RESIDUAL_RANGE) ? 2 : 1;
+  if (e == hipSuccess) e = launch_fill_noise(w.din, (int64_t)bytes, noise, w.s);
   if (e == hipSuccess) e = hipEventCreate(&w.e0);
   if (e == hipSuccess) e = hipEventCreate(&w.e1);
   if (e != hipSuccess) return hip_fail(e, "autotune set-up");
@@ -362,9 +419,10 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
   // (matrix-core candidates also choose the task size)
   struct Cand { int backend, wgpc, grid, tsel; float best; };
   std::vector<Cand> cands;
-  if (p->d.backend != ADCT16_BACKEND_MFMA || levels || !mfma_supported(p))
+  const bool mfma_ok = mfma_supported(p) && (!levels || resid_supported(p));
+  if (p->d.backend != ADCT16_BACKEND_MFMA || !mfma_ok)
     for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_VALU, wg, grid_for(p, wg), 0, 1e30f});
-  if (!levels && p->d.backend != ADCT16_BACKEND_VALU && mfma_supported(p))
+  if (p->d.backend != ADCT16_BACKEND_VALU && mfma_ok)
     for (int ts = 0; ts < 2; ++ts)
       for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_MFMA, wg, grid_for(p, wg), ts, 1e30f});
   void* const tout = p->out_kind == OUT_F32 ? nullptr : w.dout;
@@ -423,6 +481,8 @@ adct16_status autotune(adct16_plan_s* p, const char* arch) {
   st = tune_shape(p, arch, true, b, wg, ts, p->tuned_lv);
   if (st != ADCT16_OK) return st;
   p->grid_lv = grid_for(p, wg);
+  p->backend_lv = b;
+  p->task_sel_lv = ts;
   return ADCT16_OK;
 }
 
@@ -579,6 +639,20 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
     for (int k = 0; k < 16; ++k) t.tmat[u * 16 + k] = (signed char)tmat[u][k];
   }
   t.qoff = (d->flags & ADCT16_FLAG_DEADZONE_INTER) ? (float)(1.0 / 6.0) : (float)(1.0 / 3.0);
+  // matrix-core residual kernel: row classes of T (norm 16; the first and
+  // the other four rows of norm 12; norm 8) and the float64 factors of its
+  // four integer partial inverses
+  {
+    int seen12 = 0;
+    for (int u = 0; u < 16; ++u)
+      t.rcls[u] = (signed char)(norm[u] == 16 ? 0 : norm[u] == 8 ? 3 : (seen12++ < 4 ? 1 : 2));
+    const double step = uniform ? (double)d->q
+                                : deadzone ? std::ldexp((double)kDequantScale[d->q % 6], d->q / 6 - 6) : 1.0;
+    t.rcomb[0] = step / 48.0;
+    t.rcomb[1] = step / std::sqrt(128.0);
+    t.rcomb[2] = step / std::sqrt(192.0);
+    t.rcomb[3] = step / std::sqrt(96.0);
+  }
   // comparison transform and SSIM window
   for (int k = 0; k < 16; ++k)
     for (int m = 0; m < 16; ++m)
@@ -622,7 +696,7 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
             hipMalloc(&p->tasks[1].d_rows, sizeof(RowTask) * rows[1].size()) == hipSuccess &&
             hipMalloc(&p->tasks[0].d_first, sizeof(int64_t) * first[0].size()) == hipSuccess &&
             hipMalloc(&p->tasks[1].d_first, sizeof(int64_t) * first[1].size()) == hipSuccess &&
-            hipMalloc(&p->d_task_sse, sizeof(uint32_t) * rows[0].size()) == hipSuccess &&
+            hipMalloc(&p->d_task_sse, sizeof(unsigned long long) * rows[0].size()) == hipSuccess &&
             hipMalloc(&p->d_ssim_tiles, sizeof(int64_t) * ssim_tiles.size()) == hipSuccess &&
             hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size() * p->sse_slots) == hipSuccess &&
             hipMalloc(&p->d_sse_out, sizeof(unsigned long long) * images.size()) == hipSuccess;
@@ -652,11 +726,14 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   if (d->backend == ADCT16_BACKEND_MFMA && !mfma_supported(p) && !mfma_forward_supported(p)) {
     adct16_plan_destroy(p);
     return fail(ADCT16_E_MODE,
-                "MFMA backend supports U8 input with retention modes and U8 output (fused call), or U8 input to "
+                "MFMA backend supports U8 input with retention modes and U8 output, or I16 residuals with "
+                "ADCT16_FLAG_RESIDUAL_RANGE, a step of at least 8 and I16 output (fused call), or U8 input to "
                 "I32/I16 coefficients and I16 input to I32 coefficients (forward)");
   }
   p->grid_lv = p->grid;
+  p->task_sel_lv = p->task_sel;
   p->tuned_lv = "default";
+  p->backend_lv = d->backend == ADCT16_BACKEND_MFMA && resid_supported(p) ? ADCT16_BACKEND_MFMA : ADCT16_BACKEND_VALU;
   if (d->flags & ADCT16_FLAG_AUTOTUNE) {
     // a requested backend restricts the search to its launch shapes
     adct16_status st = autotune(p, prop.gcnArchName);
@@ -688,7 +765,40 @@ adct16_status adct16_plan_destroy(adct16_plan p) {
   if (p->d_ssim_tiles) (void)hipFree(p->d_ssim_tiles);
   if (p->d_sse_ws) (void)hipFree(p->d_sse_ws);
   if (p->d_sse_out) (void)hipFree(p->d_sse_out);
+  for (hipEvent_t ev : p->prof_ev) (void)hipEventDestroy(ev);
   delete p;
+  return ADCT16_OK;
+}
+
+adct16_status adct16_plan_time_fused(adct16_plan p, int32_t n_calls) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (n_calls < 0 || n_calls > (1 << 16)) return fail(ADCT16_E_SHAPE, "n_calls must be in 0..65536");
+  for (hipEvent_t ev : p->prof_ev) (void)hipEventDestroy(ev);
+  p->prof_ev.clear();
+  p->prof_used = 0;
+  for (int i = 0; i < 2 * n_calls; ++i) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) {
+      for (hipEvent_t e2 : p->prof_ev) (void)hipEventDestroy(e2);
+      p->prof_ev.clear();
+      return fail(ADCT16_E_NOMEM, "timing events");
+    }
+    p->prof_ev.push_back(ev);
+  }
+  return ADCT16_OK;
+}
+
+adct16_status adct16_plan_fused_times(adct16_plan p, float* ms, int32_t cap, int32_t* n_out) {
+  if (adct16_status st = check_plan(p)) return st;
+  if (!n_out || (cap > 0 && !ms)) return fail(ADCT16_E_NULL, "ms / n_out is NULL");
+  const int n = std::min<int>(p->prof_used, std::max(0, cap));
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = hipEventSynchronize(p->prof_ev[2 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], p->prof_ev[2 * i], p->prof_ev[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "timing event");
+  }
+  *n_out = p->prof_used;
+  p->prof_used = 0;
   return ADCT16_OK;
 }
 
@@ -707,10 +817,19 @@ adct16_status adct16_plan_info(adct16_plan p, char* buf, int32_t len) {
     << ", \"threads\": " << kGroupThreads << ", \"strips\": " << p->n_strips << ", \"blocks\": " << p->n_blocks
     << ", \"cus\": " << p->cu_count << ", \"rows_line_aligned\": " << (p->lines_aligned ? "true" : "false")
     << ", \"fused_backend\": \"" << (p->backend == ADCT16_BACKEND_MFMA && mfma_supported(p) ? "mfma" : "valu")
+    << "\", \"fused_form\": \""
+    << (p->backend == ADCT16_BACKEND_MFMA && mfma_supported(p)
+            ? (p->in_kind == IN_I16 ? "fp16-residual-classes"
+               : fused_int8(p)      ? "int8"
+               : (p->d.qmode == ADCT16_Q_ZIGZAG || (p->d.flags & ADCT16_FLAG_EXPLICIT_COEF)) ? "fp16-explicit"
+                                                                                             : "fp16-collapsed")
+            : "butterflies")
     << "\", \"forward_backend\": \""
     << (p->backend == ADCT16_BACKEND_MFMA && mfma_forward_supported(p) ? "mfma" : "valu") << "\""
     << ", \"task_strips\": " << p->tasks[p->task_sel].strips
-    << ", \"choice\": \"" << p->tuned << "\", \"levels_grid\": " << p->grid_lv
+    << ", \"choice\": \"" << p->tuned << "\", \"levels_backend\": \""
+    << (p->backend_lv == ADCT16_BACKEND_MFMA ? "mfma" : "valu") << "\", \"levels_grid\": " << p->grid_lv
+    << ", \"levels_task_strips\": " << p->tasks[p->task_sel_lv].strips
     << ", \"levels_choice\": \"" << p->tuned_lv << "\"}";
   const std::string s = o.str();
   if ((int32_t)s.size() + 1 > len) return fail(ADCT16_E_SHAPE, "buffer too small (%d needed)", (int)s.size() + 1);
@@ -836,7 +955,7 @@ adct16_status adct16_compress_and_measure(adct16_plan p, const void* d_in, void*
   if (d_out && p->out_kind == OUT_F32)
     return fail(ADCT16_E_STATE, "the fused call writes rounded reconstructions (out_dtype U8 or I16)");
   if (d_qcoef)
-    return compress_impl(p, ADCT16_BACKEND_VALU, p->grid_lv, p->task_sel, plan_workspace(p), d_in, d_out, d_qcoef,
+    return compress_impl(p, p->backend_lv, p->grid_lv, p->task_sel_lv, plan_workspace(p), d_in, d_out, d_qcoef,
                          d_sse, d_psnr, (hipStream_t)stream);
   return compress_impl(p, p->backend, p->grid, p->task_sel, plan_workspace(p), d_in, d_out, d_qcoef, d_sse, d_psnr,
                        (hipStream_t)stream);
@@ -854,14 +973,15 @@ adct16_status adct16_compress_and_measure_static(adct16_plan p, const void* d_in
   if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
     return fail(ADCT16_E_DEVICE, "the plan's device (%d) must be current (current: %d)", p->device, dev);
   const bool levels = d_qcoef != nullptr;
-  const int backend = levels ? ADCT16_BACKEND_VALU : p->backend;
+  const int backend = levels ? p->backend_lv : p->backend;
   const int grid = levels ? p->grid_lv : p->grid;
+  const int tsel = levels ? p->task_sel_lv : p->task_sel;
   // carve the call's workspace out of the array, 256-byte aligned pieces
   auto up = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
   uint64_t need = 0, o_task = 0, o_slots = 0, o_out = 0;
   if (fused_on_mfma(p, backend, levels)) {
     o_task = need;
-    need += up(sizeof(uint32_t) * (uint64_t)p->tasks[p->task_sel].n_rows);
+    need += up(sizeof(unsigned long long) * (uint64_t)p->tasks[tsel].n_rows);
     o_out = need;
     if (!d_sse) need += up(sizeof(unsigned long long) * p->images.size());
   } else {
@@ -875,7 +995,7 @@ adct16_status adct16_compress_and_measure_static(adct16_plan p, const void* d_in
   if (adct16_status st = static_scratch(dev, &base)) return st;
   const Workspace ws{reinterpret_cast<uint32_t*>(base + o_task), reinterpret_cast<unsigned long long*>(base + o_slots),
                      reinterpret_cast<unsigned long long*>(base + o_out), true};
-  return compress_impl(p, backend, grid, p->task_sel, ws, d_in, d_out, d_qcoef, d_sse, d_psnr, (hipStream_t)stream);
+  return compress_impl(p, backend, grid, tsel, ws, d_in, d_out, d_qcoef, d_sse, d_psnr, (hipStream_t)stream);
 }
 
 adct16_status adct16_dct_forward(adct16_plan p, const void* d_in, float* d_y, int32_t precision, void* stream) {

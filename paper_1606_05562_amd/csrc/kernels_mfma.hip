@@ -34,7 +34,10 @@
 // Operand layout (16x16xK, checked on the hardware): lane l = 16 g + q
 // holds row q of A and column q of B restricted to the g-th quarter of K;
 // the accumulator holds rows 4g..4g+3 of column q.
+#include <type_traits>
+
 #include "mfma_stages.hpp"
+#include "task_stream.hpp"
 
 namespace adct16 {
 
@@ -115,96 +118,70 @@ __device__ __forceinline__ void operands_to_rows(int* lds, int r, int c, int g, 
   wave_lds_sync();
 }
 
-// Streaming accesses: every byte of the batch is read once and written
-// once, so when the row segments are whole cache lines (128-byte aligned
-// pitches, offsets and buffers) the 16-byte row accesses carry the
-// non-temporal hint.  With unaligned rows a segment straddles two lines that
-// neighbouring strips share, and the hint would make them fetch it twice.
-typedef unsigned v4u __attribute__((ext_vector_type(4)));
-template <bool NT>
-__device__ __forceinline__ uint4 ld_row16(const uint8_t* p) {
-  if constexpr (NT) {
-    const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
-    return make_uint4(v.x, v.y, v.z, v.w);
-  } else {
-    return *reinterpret_cast<const uint4*>(p);
+// Both operand layouts of the int8 round trip from the same rows: x[b] =
+// dword g of row q of block b (the layout of the rounded output, for the
+// error), and for lane groups g < 2 xi[b] = dwords 2g, 2g + 1 of row q (the
+// stage-1 operand; zero for g >= 2).
+__device__ __forceinline__ void rows_to_operands_i8x(int* lds, int r, int c, int g, int q, const uint4 (&rows)[2],
+                                                     unsigned (&x)[kStripBlocks], uint2 (&xi)[kStripBlocks]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int o = (8 * h + r) * kStripBlocks + c;
+    lds[o] = (int)rows[h].x;
+    lds[128 + o] = (int)rows[h].y;
+    lds[256 + o] = (int)rows[h].z;
+    lds[384 + o] = (int)rows[h].w;
   }
-}
-template <bool NT>
-__device__ __forceinline__ void st_row16(uint8_t* p, const uint4& v) {
-  if constexpr (NT) {
-    const v4u w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<v4u*>(p));
-  } else {
-    *reinterpret_cast<uint4*>(p) = v;
+  wave_lds_sync();
+  const int4* p = reinterpret_cast<const int4*>(lds + g * 128 + q * kStripBlocks);
+  const int4 a = p[0], b = p[1];
+  x[0] = (unsigned)a.x; x[1] = (unsigned)a.y; x[2] = (unsigned)a.z; x[3] = (unsigned)a.w;
+  x[4] = (unsigned)b.x; x[5] = (unsigned)b.y; x[6] = (unsigned)b.z; x[7] = (unsigned)b.w;
+#pragma unroll
+  for (int k = 0; k < kStripBlocks; ++k) xi[k] = make_uint2(0u, 0u);
+  if (g < 2) {
+    const int4* p0 = reinterpret_cast<const int4*>(lds + (2 * g) * 128 + q * kStripBlocks);
+    const int4* p1 = reinterpret_cast<const int4*>(lds + (2 * g + 1) * 128 + q * kStripBlocks);
+    const int4 a0 = p0[0], a1 = p0[1], c0 = p1[0], c1 = p1[1];
+    const int lo[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+    const int hi[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+#pragma unroll
+    for (int k = 0; k < kStripBlocks; ++k) xi[k] = make_uint2((unsigned)lo[k], (unsigned)hi[k]);
   }
+  wave_lds_sync();
 }
 
-// The fields of an image that the fused kernel uses, held in scalars.
-struct ImgGeom {
-  int64_t offset;
-  int32_t h, w, pitch, bx, sx;
-  int64_t block_begin;
+// The per-lane constants and the per-strip work of the fused kernel in its
+// three forms: FP16 products (collapsed or explicit Z, zig-zag masks on Z)
+// or int8 products (collapsed, separable masks).
+template <bool ZIGZAG, bool COLLAPSE, bool I8>
+struct RoundTrip {
+  static_assert(!I8 || (COLLAPSE && !ZIGZAG), "the int8 form covers separable masks (collapsed)");
+  typename std::conditional<I8, I8Consts, MfmaConsts>::type k;
+  bool keepz[4];
+  __device__ __forceinline__ RoundTrip(int q, int g, const Tables* tb) {
+    if constexpr (I8) k = make_consts_i8(q, g, tb->rsep, tb);
+    else k = make_consts(q, g, tb->rsep, tb);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) keepz[v] = tb->wkeep[(4 * g + v) * 16 + q] != 0;
+  }
+  // rows (the strip's 8 rows x 128 bytes per half, see rows_to_operands) ->
+  // x (input pixels) and out (rounded reconstruction), dword g of row q of
+  // each block
+  __device__ __forceinline__ void run(int* lds, int r, int c, int g, int q, const uint4 (&rows)[2],
+                                      unsigned (&x)[kStripBlocks], unsigned (&out)[kStripBlocks]) const {
+    if constexpr (I8) {
+      uint2 xi[kStripBlocks];
+      rows_to_operands_i8x(lds, r, c, g, q, rows, x, xi);
+      constexpr int NB = ADCT16_MFMA_BATCH;
+#pragma unroll
+      for (int b0 = 0; b0 < kStripBlocks; b0 += NB) collapsed_blocks_i8<NB>(&xi[b0], &out[b0], k);
+    } else {
+      rows_to_operands(lds, r, c, g, q, rows, x);
+      roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
+    }
+  }
 };
-
-// One dword of block row q (columns 4g..4g+3), edge-extended.
-__device__ __forceinline__ unsigned load_dword_edge(const uint8_t* img, const ImgGeom& d, int y, int x0) {
-  const int64_t off = d.offset + (int64_t)y * d.pitch;
-  if (x0 + 3 < d.w) return *reinterpret_cast<const unsigned*>(img + off + x0);
-  unsigned r = 0;
-  for (int k = 0; k < 4; ++k) r |= (unsigned)img[off + min(x0 + k, d.w - 1)] << (8 * k);
-  return r;
-}
-
-// Task registers: lane k of a wavefront holds the table entry and the image
-// geometry of its task t0 + k W (the k-th of its next 64 tasks), gathered
-// with one set of vector loads; the task in use is read back with readlane.
-// The table latency is paid once per 64 tasks instead of once per task.
-struct TaskRegs {
-  int sy, run, off_lo, off_hi, h, w, pitch, bx, sx, bb_lo, bb_hi;
-};
-
-__device__ __forceinline__ TaskRegs gather_tasks(const ImageDesc* __restrict__ images,
-                                                 const RowTask* __restrict__ rows, int64_t t0, int64_t W,
-                                                 int64_t n, int lane) {
-  TaskRegs tr = {0, 0, 0, 0, 1, 1, 0, 0, 1, 0, 0};
-  const int64_t tk = t0 + (int64_t)lane * W;
-  if (tk < n) {
-    const RowTask e = rows[tk];
-    const ImageDesc* d = images + e.img;
-    const int64_t off = d->offset;
-    tr.sy = e.sy;
-    tr.run = e.run;
-    tr.off_lo = (int)(uint32_t)off;
-    tr.off_hi = (int)(off >> 32);
-    tr.h = d->h;
-    tr.w = d->w;
-    tr.pitch = d->pitch;
-    tr.bx = d->bx;
-    tr.sx = d->sx;
-    const int64_t bb = d->block_begin;
-    tr.bb_lo = (int)(uint32_t)bb;
-    tr.bb_hi = (int)(bb >> 32);
-  }
-  // complete the gather here, so that reading a task (every few strips)
-  // never waits on memory; vmcnt(0), other counters unchanged
-  __builtin_amdgcn_s_waitcnt(0x0F70);
-  return tr;
-}
-
-__device__ __forceinline__ ImgGeom task_geom(const TaskRegs& tr, int k) {
-  ImgGeom m;
-  m.offset = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(tr.off_hi, k) << 32) |
-                       (uint32_t)__builtin_amdgcn_readlane(tr.off_lo, k));
-  m.h = __builtin_amdgcn_readlane(tr.h, k);
-  m.w = __builtin_amdgcn_readlane(tr.w, k);
-  m.pitch = __builtin_amdgcn_readlane(tr.pitch, k);
-  m.bx = __builtin_amdgcn_readlane(tr.bx, k);
-  m.sx = __builtin_amdgcn_readlane(tr.sx, k);
-  m.block_begin = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(tr.bb_hi, k) << 32) |
-                            (uint32_t)__builtin_amdgcn_readlane(tr.bb_lo, k));
-  return m;
-}
 
 // Work distribution: wavefront w of W takes tasks w, w + W, w + 2W, ... of
 // the batch (the task table lists equal runs of at most 4 or 16 strips of
@@ -216,16 +193,13 @@ __device__ __forceinline__ ImgGeom task_geom(const TaskRegs& tr, int k) {
 // strips are unconditional, and each branch ends with an explicit wait for
 // everything but its own stores, so that the loads of the next strip never
 // wait for the stores of the previous one.
-template <bool ZIGZAG, bool COLLAPSE, int OUT, bool NT>
+template <bool ZIGZAG, bool COLLAPSE, int OUT, bool NT, bool I8>
 __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fused(
     Params P, const ImageDesc* __restrict__ images, const RowTask* __restrict__ rows) {
   __shared__ int lds_all[kWavesPerGroup * 512];
   int* lds = lds_all + (threadIdx.x >> 6) * 512;
   const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4, r = lane >> 3, c = lane & 7;
-  const MfmaConsts k = make_consts(q, g, P.tables->rsep, P.tables);
-  bool keepz[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) keepz[v] = P.tables->wkeep[(4 * g + v) * 16 + q] != 0;
+  const RoundTrip<ZIGZAG, COLLAPSE, I8> rt(q, g, P.tables);
   const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
   uint8_t* outp = reinterpret_cast<uint8_t*>(P.out);
   const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
@@ -296,8 +270,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
     if (interior(d, sy, sxi)) {
       prefetch();
       unsigned x[kStripBlocks], out[kStripBlocks];
-      rows_to_operands(lds, r, c, g, q, cr, x);
-      roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
+      rt.run(lds, r, c, g, q, cr, x, out);
       if constexpr (OUT == OUT_U8) {
         uint4 orow[2];
         operands_to_rows(lds, r, c, g, q, out, orow);
@@ -331,8 +304,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
         er[1] = extend_bytes(er[1], nvalid);
       }
       unsigned x[kStripBlocks], out[kStripBlocks];
-      rows_to_operands(lds, r, c, g, q, er, x);
-      roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
+      rt.run(lds, r, c, g, q, er, x, out);
       if constexpr (OUT == OUT_U8) {
         uint4 orow[2];
         operands_to_rows(lds, r, c, g, q, out, orow);
@@ -394,12 +366,6 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
 //                lane 16g + q ends with Z[q][4g..4g+3].
 //   DC           Z = Zc + 32768 at (0, 0) for int32 output (accumulator
 //                start); the centred int16 form is Zc itself.
-typedef int i4v __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ i4v mma_i8(uint2 a, uint2 b, i4v c) {
-  const long av = (long)(((uint64_t)a.y << 32) | a.x), bv = (long)(((uint64_t)b.y << 32) | b.x);
-  return __builtin_amdgcn_mfma_i32_16x16x32_i8(av, bv, c, 0, 0, 0);
-}
 
 // Bytes 0 of four int32 values, in order, as one dword.
 __device__ __forceinline__ unsigned pack_low_bytes(int a, int b, int c, int d) {
@@ -877,24 +843,29 @@ hipError_t launch_mfma_forward(int coef_kind, bool nt, const Params& P, int grid
 }
 
 template <bool NT>
-hipError_t launch_mfma_fused_nt(bool zigzag, bool collapse, int out_kind, const Params& P, int grid, hipStream_t s) {
-  if (zigzag) {
-    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_U8, NT>), grid, s, P, P.images, P.rows);
-    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_NONE, NT>), grid, s, P, P.images, P.rows);
+hipError_t launch_mfma_fused_nt(bool zigzag, bool collapse, bool i8, int out_kind, const Params& P, int grid,
+                                hipStream_t s) {
+  if (i8) {
+    if (zigzag || !collapse) return hipErrorInvalidValue;
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_U8, NT, true>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_NONE, NT, true>), grid, s, P, P.images, P.rows);
+  } else if (zigzag) {
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_U8, NT, false>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<true, false, OUT_NONE, NT, false>), grid, s, P, P.images, P.rows);
   } else if (collapse) {
-    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_U8, NT>), grid, s, P, P.images, P.rows);
-    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_NONE, NT>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_U8, NT, false>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, true, OUT_NONE, NT, false>), grid, s, P, P.images, P.rows);
   } else {
-    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_U8, NT>), grid, s, P, P.images, P.rows);
-    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_NONE, NT>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_U8) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_U8, NT, false>), grid, s, P, P.images, P.rows);
+    if (out_kind == OUT_NONE) ADCT16_MLAUNCH((k_mfma_fused<false, false, OUT_NONE, NT, false>), grid, s, P, P.images, P.rows);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma_fused(bool zigzag, bool collapse, int out_kind, bool nt, const Params& P, int grid,
+hipError_t launch_mfma_fused(bool zigzag, bool collapse, bool i8, int out_kind, bool nt, const Params& P, int grid,
                              hipStream_t s) {
-  return nt ? launch_mfma_fused_nt<true>(zigzag, collapse, out_kind, P, grid, s)
-            : launch_mfma_fused_nt<false>(zigzag, collapse, out_kind, P, grid, s);
+  return nt ? launch_mfma_fused_nt<true>(zigzag, collapse, i8, out_kind, P, grid, s)
+            : launch_mfma_fused_nt<false>(zigzag, collapse, i8, out_kind, P, grid, s);
 }
 
 hipError_t launch_dct_mfma(int in_kind, int precision, const Params& P, float* y, int grid, hipStream_t s) {

@@ -878,7 +878,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_measure(Params P) {
 // its power draw, which depends on the data: a constant input would favour
 // launch shapes that are slow on real data).  Bytes: the full 8-bit range;
 // 16-bit samples: [-512, 511], the range of prediction residuals.
-__global__ void k_fill_noise(uint32_t* p, int64_t n, int i16) {
+// Hashed noise for the autotuner's scratch input: kind 0 any bytes, 1 int16
+// pairs in [-512, 511], 2 int16 pairs in [-256, 255].
+__global__ void k_fill_noise(uint32_t* p, int64_t n, int kind) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     uint32_t h = (uint32_t)i * 0x9E3779B1u;
     h ^= h >> 15;
@@ -886,7 +888,9 @@ __global__ void k_fill_noise(uint32_t* p, int64_t n, int i16) {
     h ^= h >> 13;
     h *= 0xC2B2AE3Du;
     h ^= h >> 16;
-    p[i] = i16 ? (((h & 0x3ffu) - 512u) & 0xffffu) | ((((h >> 16) & 0x3ffu) - 512u) << 16) : h;
+    if (kind == 1) h = (((h & 0x3ffu) - 512u) & 0xffffu) | ((((h >> 16) & 0x3ffu) - 512u) << 16);
+    if (kind == 2) h = (((h & 0x1ffu) - 256u) & 0xffffu) | ((((h >> 16) & 0x1ffu) - 256u) << 16);
+    p[i] = h;
   }
 }
 
@@ -1000,10 +1004,10 @@ __global__ __launch_bounds__(256) void k_1d(const int32_t* __restrict__ x, int32
     return hipGetLastError();                                                 \
   } while (0)
 
-hipError_t launch_fill_noise(void* p, int64_t bytes, bool i16, hipStream_t s) {
+hipError_t launch_fill_noise(void* p, int64_t bytes, int kind, hipStream_t s) {
   const int64_t n = bytes / 4;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_fill_noise, dim3(grid), dim3(256), 0, s, reinterpret_cast<uint32_t*>(p), n, i16 ? 1 : 0);
+  hipLaunchKernelGGL(k_fill_noise, dim3(grid), dim3(256), 0, s, reinterpret_cast<uint32_t*>(p), n, kind);
   return hipGetLastError();
 }
 

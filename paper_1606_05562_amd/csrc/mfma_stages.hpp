@@ -162,6 +162,104 @@ __device__ __forceinline__ void inv_blocks(f4 (&z)[NB], unsigned* out, const Mfm
   stage4_round<NB>(z, out, k);
 }
 
+// ---------------------------------------------------------------------------
+// The round trip as int8 products with int32 accumulation (separable masks).
+// With G = T^T diag(w m) T (symmetric, |G| <= 48 for every r x r mask, so
+// int8) the exact numerator is N = G Xc G for the centred block Xc = X - 128
+// (int8):
+//
+//   stage 1  V   = Xc G               |V| <= 128 max_n sum_j |G[j][n]| = 13312
+//   digits   V   = 256 s1 + s0, s0 = the low byte of V as int8 in
+//            [-128, 127], s1 = (V + 128) >> 8 in [-52, 52]
+//   stage 2  N^T = s0^T G + 256 s1^T G          (two products, int32)
+//
+// Every product and sum is an integer below 2^31: exact.  Stage 1 carries
+// the 16 pixels of a row in the K slots of lane groups 0 and 1 (the other 16
+// slots zero); stage 2 carries one digit of V[4g..4g+3][q] in slots 0..3 of
+// lane group g against G[4g..4g+3][q] (slots 4..7 zero), so that lane
+// 16g + q ends with N[q][4g..4g+3], four consecutive pixels of row q.
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ i4v mma_i8(uint2 a, uint2 b, i4v c) {
+  const long av = (long)(((uint64_t)a.y << 32) | a.x), bv = (long)(((uint64_t)b.y << 32) | b.x);
+  return __builtin_amdgcn_mfma_i32_16x16x32_i8(av, bv, c, 0, 0, 0);
+}
+
+struct I8Consts {
+  uint2 g1;   // stage-1 B: G[8g..8g+7][q] for g < 2, zero otherwise
+  uint2 g2;   // stage-2 B: G[4g..4g+3][q] in slots 0..3, zero in slots 4..7
+  float c;    // rounding: fl32(8/9) 2^-11 (pixel = fma(N, c, 128 + 2^-12), as round_pack)
+};
+
+__device__ __forceinline__ I8Consts make_consts_i8(int q, int g, int r_sep, const Tables* tb) {
+  const signed char* tm = tb->tmat;
+  const signed char* kW = tb->wvec;
+  auto gent = [&](int a, int b) {  // G[a][b]
+    int acc = 0;
+    for (int u = 0; u < r_sep; ++u) acc += kW[u] * tm[u * 16 + a] * tm[u * 16 + b];
+    return acc;
+  };
+  auto bytes4 = [&](int k0) {
+    unsigned r = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r |= (unsigned)(uint8_t)(signed char)gent(k0 + j, q) << (8 * j);
+    return r;
+  };
+  I8Consts k;
+  k.g1 = g < 2 ? make_uint2(bytes4(8 * g), bytes4(8 * g + 4)) : make_uint2(0u, 0u);
+  k.g2 = make_uint2(bytes4(4 * g), 0u);
+  k.c = (8.0f / 9.0f) * (1.0f / 2048.0f);
+  return k;
+}
+
+// Bytes `b` (0 or 1) of four int32 values, in order, as one dword.
+__device__ __forceinline__ unsigned gather_byte(int v0, int v1, int v2, int v3, unsigned sel) {
+  const unsigned lo = __builtin_amdgcn_perm((unsigned)v1, (unsigned)v0, sel);
+  const unsigned hi = __builtin_amdgcn_perm((unsigned)v3, (unsigned)v2, sel);
+  return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+}
+
+// pixel = clamp(floor(N / 2304 + 1/2) + 128, 0, 255) for integer N: the
+// float32 conversion is exact (|N| < 2^24) and fma(N, fl32(8/9) 2^-11, off)
+// equals round_pack's fma(N 2^-11, fl32(8/9), off) bit for bit (the factor
+// 2^-11 only moves the exponent).
+__device__ __forceinline__ unsigned round_pack_i(i4v n, float c) {
+  constexpr float off = 128.0f + 1.0f / 4096.0f;
+  unsigned r = 0;
+  r = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_fmaf((float)n[0], c, off), 0, r);
+  r = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_fmaf((float)n[1], c, off), 1, r);
+  r = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_fmaf((float)n[2], c, off), 2, r);
+  r = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_fmaf((float)n[3], c, off), 3, r);
+  return r;
+}
+
+// NB blocks from their stage-1 operands xi (raw pixel bytes of row q,
+// columns 8g..8g+7, in lanes of groups 0 and 1) to four rounded pixels of
+// row q per lane (out[b], the layout of round_pack).
+template <int NB>
+__device__ __forceinline__ void collapsed_blocks_i8(const uint2* xi, unsigned* out, const I8Consts& k) {
+  const i4v zero = {0, 0, 0, 0};
+  i4v v[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)  // centred: flipping the top bit of a byte subtracts 128
+    v[b] = mma_i8(make_uint2(xi[b].x ^ 0x80808080u, xi[b].y ^ 0x80808080u), k.g1, zero);
+  i4v n0[NB], n1[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const unsigned d0 = gather_byte(v[b][0], v[b][1], v[b][2], v[b][3], 0x0c0c0400u);
+    const unsigned d1 = gather_byte(v[b][0] + 128, v[b][1] + 128, v[b][2] + 128, v[b][3] + 128, 0x0c0c0501u);
+    n0[b] = mma_i8(make_uint2(d0, 0u), k.g2, zero);
+    n1[b] = mma_i8(make_uint2(d1, 0u), k.g2, zero);
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    i4v n;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) n[j] = (n1[b][j] << 8) + n0[b][j];
+    out[b] = round_pack_i(n, k.c);
+  }
+}
+
 // Separable masks, NB blocks: forward row pass, then U^T = P^T G^T in one
 // contraction (the forward column pass, the retention and the inverse column
 // pass together: T^T diag(w m) T P = T^T (w .* m .* T P)), then stage 4 and

@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 def _args(workload, frames, **kw):
     a = dict(gpus=1, steps=2, warmup=1, workload=workload, r=8, backend="auto", frames=frames,
-             no_cpu_baseline=True, no_variants=False, cpu_frames=1, calibrate_copy=False, q=None, qp=None)
+             no_cpu_baseline=True, no_variants=False, cpu_frames=1, calibrate_copy=False, q=None, qp=None,
+             no_c2=True)
     a.update(kw)
     return argparse.Namespace(**a)
 
@@ -24,7 +25,7 @@ def _run(workload, frames, **kw):
     import torch
 
     import paper_1606_05562_amd as A
-    fn = {"luma": bench.bench_luma, "uhd": bench.bench_uhd, "ragged": bench.bench_ragged,
+    fn = {"target": bench.bench_target, "luma": bench.bench_luma, "ragged": bench.bench_ragged,
           "residual": bench.bench_residual, "rd": bench.bench_rd, "sweep": bench.bench_sweep,
           "vector": bench.bench_vector}[workload]
     res = fn(_args(workload, frames, **kw), A, torch)
@@ -39,22 +40,35 @@ def _positive(v):
     return isinstance(v, (int, float)) and math.isfinite(v) and v > 0
 
 
-def test_bench_luma_small():
-    line = _run("luma", 2, no_cpu_baseline=False)
+def _check_frames_line(line, steps=2):
     assert _positive(line["value"])
     r = line["roofline"]
-    for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+    for key in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel_ms_mean", "kernel_ms_median"):
         assert key in r, key
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
+    # the persistent kernel of every timed step, and no longer than the step
+    assert r["kernel_launches"] == steps
+    assert 0 < r["kernel_ms_mean"] <= line["ms_per_step"] * 1.001
+    assert line["parity"]["ok"] is True
+    assert isinstance(line["config"]["seed"], int) and "form" in line["config"]
+
+
+def test_bench_luma_small():
+    line = _run("luma", 2, no_cpu_baseline=False)
+    _check_frames_line(line)
     cb = line["cpu_baseline"]
     assert cb["kind"] == "oracle" and _positive(cb["value"]) and cb["cores"] >= 1
+    assert _positive(cb["single_thread"]["value"]) and cb["single_thread"]["cores"] == 1
+    assert cb["cpu_model"] and cb["host_nproc"] >= 1
     assert all(_positive(v) for v in line["variants"].values())
 
 
-def test_bench_uhd_small():
-    line = _run("uhd", 1)
-    assert _positive(line["value"]) and line["roofline"]["bound"] == "hbm"
+def test_bench_target_small():
+    line = _run("target", 1)
+    _check_frames_line(line)
+    assert line["config"]["width"] == 3840 and line["config"]["height"] == 2160
+    assert all(_positive(v) for v in line["variants"].values())
 
 
 def test_bench_ragged_small():

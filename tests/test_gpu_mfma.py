@@ -103,6 +103,112 @@ def test_mfma_equals_adder_kernel_on_extremes(batch_worst, qmode, r, explicit):
     assert np.array_equal(a[0][0], want) and a[1][0] == s
 
 
+# ----------------------------------------------------------------------------
+# The round trip as int8 products (flag MFMA_INT8, separable masks):
+# N = G Xc G with G = T^T diag(w m) T, the intermediate Xc G on signed
+# base-256 digit planes.
+
+INT8_CASES = [(1, r) for r in (1, 2, 3, 5, 8, 9, 12, 16)] + [(0, 16)]
+
+
+@pytest.mark.parametrize("qmode,r", INT8_CASES)
+def test_mfma_int8_fused_bit_exact(batch_u8, qmode, r):
+    keep = {0: codec.mask_none(), 1: codec.mask_zonal(r)}[qmode]
+    plan = batch_u8.plan(coef_dtype=A().I32, qmode=qmode, r=r, backend=A().BACKEND_MFMA, flags=A().FLAG_MFMA_INT8)
+    import json
+    assert json.loads(plan.info())["fused_form"] == "int8"
+    recs, sse, psnr = _fused(batch_u8, A().BACKEND_MFMA, qmode, r, A().FLAG_MFMA_INT8)
+    for i, (got, im) in enumerate(zip(recs, batch_u8.images)):
+        want, s, p = codec.compress_kept(im, keep)
+        assert np.array_equal(got, want), f"image {i}"
+        assert sse[i] == s
+        assert (math.isinf(p) and math.isinf(psnr[i])) or abs(psnr[i] - p) <= 1e-3
+
+
+@pytest.fixture(scope="module")
+def batch_int8_worst():
+    """The extreme blocks of batch_worst plus, for every r x r mask and every
+    column n of G_r = T^T diag(w m_r) T, the block whose rows all follow the
+    sign pattern of G_r[:, n] (and its complement): these reach the largest
+    |Xc G| = 128 sum_j |G_r[j][n]| (13312 at most)."""
+    t = tf.T.astype(np.int64)
+    w = tf.inverse_weights(tf.T).astype(np.int64)
+    pats = []
+    for r in range(1, 17):
+        g = t.T @ np.diag(w * (np.arange(16) < r)) @ t
+        for n in range(16):
+            row = np.where(g[:, n] > 0, 255, 0).astype(np.uint8)
+            pats.append(np.tile(row, (16, 1)))
+            pats.append(255 - np.tile(row, (16, 1)))
+    rnd = random_blocks_u8(BASE_SEED + 11, 1024)
+    tp = [np.where(np.outer(t[u], t[v]) > 0, 255, 0).astype(np.uint8) for u in range(16) for v in range(16)]
+    tp += [255 - p for p in tp]
+    blocks = np.concatenate([rnd, np.stack(tp), np.stack(pats)])  # 1536 + 512 blocks
+    img = blocks.reshape(32, 64, 16, 16).transpose(0, 2, 1, 3).reshape(32 * 16, 64 * 16)
+    return Batch([img])
+
+
+@pytest.mark.parametrize("qmode,r", [(1, 1), (1, 3), (1, 8), (1, 13), (1, 16), (0, 16)])
+def test_mfma_int8_equals_adder_kernel_on_extremes(batch_int8_worst, qmode, r):
+    a = _fused(batch_int8_worst, A().BACKEND_MFMA, qmode, r, A().FLAG_MFMA_INT8)
+    b = _fused(batch_int8_worst, A().BACKEND_VALU, qmode, r)
+    assert np.array_equal(a[0][0], b[0][0]) and np.array_equal(a[1], b[1])
+    keep = {0: codec.mask_none(), 1: codec.mask_zonal(r)}[qmode]
+    want, s, _ = codec.compress_kept(batch_int8_worst.images[0], keep)
+    assert np.array_equal(a[0][0], want) and a[1][0] == s
+
+
+@pytest.mark.parametrize("align", [16, 128])
+def test_mfma_int8_ragged_and_wht(align):
+    # ragged edges (both task tables' edge strips), and the Walsh-Hadamard
+    # matrix through the same int8 kernel against the adder kernel
+    rng = np.random.default_rng(23)
+    sizes = [(int(x), int(y)) for x, y in rng.integers(16, 300, size=(6, 2))] + [(272, 384), (33, 2050)]
+    ims = [mixed_image(BASE_SEED + 4, k, h, w) for k, (h, w) in enumerate(sizes)]
+    b = Batch(ims, align)
+    recs, sse, _ = _fused(b, A().BACKEND_MFMA, A().Q_ZONAL, 6, A().FLAG_MFMA_INT8)
+    for i, (got, im) in enumerate(zip(recs, ims)):
+        want, s, _ = codec.compress_kept(im, codec.mask_zonal(6))
+        assert np.array_equal(got, want) and sse[i] == s, f"image {i} {sizes[i]}"
+    T = torch()
+    outs = []
+    for be, fl in ((A().BACKEND_MFMA, A().FLAG_MFMA_INT8), (A().BACKEND_VALU, 0)):
+        plan = b.plan(coef_dtype=A().I32, qmode=A().Q_ZONAL, r=5, backend=be, flags=fl, matrix=A().MATRIX_WHT)
+        out = b.empty_like_images(np.uint8, 1)
+        sse2 = T.zeros(len(ims), dtype=T.int64, device="cuda")
+        plan.compress_and_measure(b.dev, out, None, sse2, None)
+        T.cuda.synchronize()
+        outs.append((out.cpu().numpy(), sse2.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_mfma_int8_full_size():
+    """The 256-frame 1920x1088 batch at r = 8 through the int8 round trip:
+    sampled frames against the oracle, every pixel and SSE against the FP16
+    matrix-core form."""
+    T = torch()
+    mod = A()
+    n, h, w = 256, 1088, 1920
+    frames = luma_batch(BASE_SEED + 2, n, h, w)
+    dev = T.from_numpy(frames.reshape(-1)).cuda()
+    offs = [i * h * w for i in range(n)]
+    res = []
+    for fl in (mod.FLAG_MFMA_INT8, 0):
+        plan = mod.Plan([h] * n, [w] * n, [w] * n, offs, in_dtype=mod.U8, coef_dtype=mod.I32, qmode=mod.Q_ZONAL,
+                        r=8, backend=mod.BACKEND_MFMA, flags=fl)
+        out = T.empty_like(dev)
+        sse = T.zeros(n, dtype=T.int64, device="cuda")
+        plan.compress_and_measure(dev, out, None, sse, None)
+        T.cuda.synchronize()
+        res.append((out, sse))
+    out, sse = res[0]
+    for t in (1, 254):
+        got = out[t * h * w:(t + 1) * h * w].cpu().numpy().reshape(h, w)
+        want, s, _ = codec.compress_kept(frames[t], codec.mask_zonal(8))
+        assert np.array_equal(got, want) and int(sse[t]) == s
+    assert T.equal(out, res[1][0]) and T.equal(sse, res[1][1])
+
+
 @pytest.mark.parametrize("int8", [False, True])
 def test_mfma_forward_extremes(batch_worst, int8):
     # sign patterns of the rows of T reach |P| = 2048 and the extreme Z

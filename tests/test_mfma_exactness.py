@@ -60,3 +60,30 @@ def test_final_rounding_is_exact():
     got = np.clip(np.rint(t), 0, 255).astype(np.int64)      # cvt_pk_u8: nearest-even, saturating
     want = np.clip(np.floor_divide(n + 1152, 2304) + 128, 0, 255)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("name,mat", [("T", tf.T), ("WHT", tf.wht())])
+def test_int8_round_trip_ranges(name, mat):
+    """The int8 round trip (N = G Xc G, G = T^T diag(w m) T for r x r masks)
+    needs G in int8, |Xc G| small enough for two signed base-256 digits
+    (top digit in int8), and every int32 sum exact."""
+    T = mat.astype(np.int64)
+    w = tf.inverse_weights(mat).astype(np.int64)
+    for r in range(1, 17):
+        g = T.T @ np.diag(w * (np.arange(16) < r)) @ T
+        assert np.abs(g).max() <= 48
+        vmax = 128 * np.abs(g).sum(axis=0).max()          # |Xc G| over the pixel box
+        assert vmax <= 13312
+        assert (vmax + 128) >> 8 <= 127 and (-vmax + 128) >> 8 >= -128
+        # digit products |G^T s| <= 128 sum |G|; N = s0 G + 256 s1 G below 2^31
+        assert 128 * np.abs(g).sum(axis=0).max() * 257 < 2**31
+        assert _box_max(np.einsum("ia,bj->ijab", g, g)) <= 1648452   # |N|: the proven rounding range
+
+
+def test_int8_digits_reassemble():
+    rng = np.random.default_rng(3)
+    v = np.concatenate([np.arange(-13312, 13313), rng.integers(-13312, 13313, 1000)])
+    s0 = ((v & 255) ^ 128) - 128       # the low byte read as int8
+    s1 = (v + 128) >> 8                # byte 1 of v + 128
+    assert np.array_equal(256 * s1 + s0, v)
+    assert s0.min() >= -128 and s0.max() <= 127 and s1.min() >= -128 and s1.max() <= 127
