@@ -72,7 +72,10 @@ def _parse():
 # Device-side sources each fused kernel is compiled from (host API code
 # excluded): counters taken on one kernel stay valid while these are unchanged.
 KERNEL_SOURCES = {
-    "k_mfma_fused": ["adct16_internal.hpp", "device_common.hpp", "kernels_mfma.hip", "mfma_stages.hpp"],
+    "k_mfma_fused": ["adct16_internal.hpp", "device_common.hpp", "kernels_mfma.hip", "mfma_stages.hpp",
+                     "task_stream.hpp"],
+    "k_mfma_resid": ["adct16_internal.hpp", "device_common.hpp", "kernels_resid.hip", "mfma_stages.hpp",
+                     "task_stream.hpp"],
     "k_fused": ["adct16_internal.hpp", "device_common.hpp", "kernels_valu.hip"],
 }
 
@@ -437,45 +440,73 @@ def _luma_variants(args, A, torch, pt, frames):
 
 
 def bench_ragged(args, A, torch):
-    """64 uint8 images, sides uniform in 64..3840 rounded up to 16, mixed
-    content; one fused forward -> zonal r -> inverse -> per-image PSNR."""
+    """C4: 64 uint8 images, sides uniform in 64..3840 rounded up to 16, mixed
+    content; one fused forward -> zonal r -> inverse -> per-image PSNR
+    launch.  Two layouts of the same images: rows padded to whole 128-byte
+    cache lines (the value), and the natural packing (pitch = width rounded
+    up to 16, images 16-byte aligned)."""
+    from oracle import codec
     from synth import BASE_SEED, pack_images, ragged_batch
-    ims = ragged_batch(BASE_SEED + 4, args.frames or 64)
-    # rows padded to whole 128-byte cache lines (the batch layout is ours to choose)
-    buf, hs, ws, ps, offs = pack_images(ims, align_elems=128, pitch_multiple=128)
-    dev = torch.from_numpy(buf).cuda()
-    out = torch.empty_like(dev)
+    seed = BASE_SEED + 4
+    ims = ragged_batch(seed, args.frames or 64)
     n = len(ims)
-    sse = torch.zeros(n, dtype=torch.int64, device="cuda")
-    psnr = torch.zeros(n, dtype=torch.float64, device="cuda")
     backend = {"auto": A.BACKEND_AUTO, "valu": A.BACKEND_VALU, "mfma": A.BACKEND_MFMA}[args.backend]
-    plan = A.Plan(hs, ws, ps, offs, in_dtype=A.U8, coef_dtype=A.I32, qmode=A.Q_ZONAL, r=args.r,
-                  backend=backend, flags=A.FLAG_AUTOTUNE)
     stream = torch.cuda.current_stream()
-    step = lambda: plan.compress_and_measure(dev, out, None, sse, psnr)
-    for _ in range(args.warmup):
-        step()
-    ms = _events_ms(step, args.steps, stream)
-    npx = int(sum(h * w for h, w in zip(hs, ws)))
-    res = {"metric": "Gpixel/s 2D fwd+quant+inv 16x16, ragged batch", "value": round(npx / (ms * 1e-3) / 1e9, 4),
-           "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "u8", "data": "synthetic",
-           "config": {"workload": f"{n} uint8 images, sides U[64,3840] rounded to 16, "
-                                  f"{npx / 1e6:.1f} Mpx; zonal r={args.r}", "plan": json.loads(plan.info())},
-           "roofline": {"bound": "hbm", "achieved": round(2 * npx / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(2 * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
-    if not args.no_variants:
-        v = {}
-        for name, be in (("valu", A.BACKEND_VALU), ("mfma", A.BACKEND_MFMA)):
-            p2 = A.Plan(hs, ws, ps, offs, in_dtype=A.U8, coef_dtype=A.I32, qmode=A.Q_ZONAL, r=args.r,
-                        backend=be, flags=A.FLAG_AUTOTUNE)
-            f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)
-            f()
-            t = _events_ms(f, args.steps, stream)
-            v[f"{name}_gpix_s"] = round(npx / (t * 1e-3) / 1e9, 4)
-            v[f"{name}_plan"] = json.loads(p2.info())
-        res["variants"] = v
-    return res
+    npx = int(sum(im.size for im in ims))
+    layouts = {}
+    for name, align in (("lines128", 128), ("packed16", 16)):
+        buf, hs, ws, ps, offs = pack_images(ims, align_elems=align, pitch_multiple=align)
+        dev = torch.from_numpy(buf).cuda()
+        out = torch.empty_like(dev)
+        sse = torch.zeros(n, dtype=torch.int64, device="cuda")
+        psnr = torch.zeros(n, dtype=torch.float64, device="cuda")
+        plan = A.Plan(hs, ws, ps, offs, in_dtype=A.U8, coef_dtype=A.I32, qmode=A.Q_ZONAL, r=args.r,
+                      backend=backend, flags=A.FLAG_AUTOTUNE)
+        step = lambda: plan.compress_and_measure(dev, out, None, sse, psnr)
+        ms, kt = _timed_fused(plan, step, args.steps, args.warmup, stream, torch)
+        kmean = float(np.mean(kt))
+        # sampled parity: the largest and the smallest image against the oracle
+        big, small = int(np.argmax([im.size for im in ims])), int(np.argmin([im.size for im in ims]))
+        oc = out.cpu().numpy()
+        ok = True
+        for i in (big, small):
+            h, w = ims[i].shape
+            got = oc[offs[i]:offs[i] + h * ps[i]].reshape(h, ps[i])[:, :w]
+            want, sw, _ = codec.compress_kept(ims[i], codec.mask_zonal(args.r))
+            ok &= bool(np.array_equal(got, want)) and int(sse[i]) == sw
+        layouts[name] = {"gpix_s": round(npx / (ms * 1e-3) / 1e9, 4), "ms_per_step": round(ms, 4),
+                         "kernel_ms_mean": round(kmean, 4),
+                         "kernel_frac": round(2 * npx / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "bytes": int(buf.nbytes), "plan": json.loads(plan.info()),
+                         "parity": {"images": [big, small], "ok": ok,
+                                    "bar": "reconstruction and SSE bit-exact against the oracle"}}
+        if name == "lines128" and not args.no_variants:
+            v = {}
+            for vname, be in (("valu", A.BACKEND_VALU), ("mfma", A.BACKEND_MFMA),
+                              ("mfma_int8", A.BACKEND_MFMA)):
+                p2 = A.Plan(hs, ws, ps, offs, in_dtype=A.U8, coef_dtype=A.I32, qmode=A.Q_ZONAL, r=args.r,
+                            backend=be, flags=A.FLAG_AUTOTUNE | (A.FLAG_MFMA_INT8 if vname == "mfma_int8" else 0))
+                f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)
+                f()
+                t = _events_ms(f, args.steps, stream)
+                v[f"{vname}_gpix_s"] = round(npx / (t * 1e-3) / 1e9, 4)
+                v[f"{vname}_plan"] = json.loads(p2.info())
+            layouts[name]["variants"] = v
+        del dev, out
+    head = layouts["lines128"]
+    kfrac = head["kernel_frac"]
+    return {"metric": "Gpixel/s 2D fwd+quant+inv 16x16, ragged batch", "value": head["gpix_s"],
+            "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": _arith(head["plan"]), "data": "synthetic",
+            "config": {"workload": f"{n} uint8 images, sides U[64,3840] rounded to 16, {npx / 1e6:.1f} Mpx; "
+                                   f"zonal r={args.r}; value for rows padded to 128-byte lines", "seed": seed,
+                       "layouts": layouts},
+            "roofline": {"bound": "hbm", "achieved": round(kfrac * HBM_PEAK_GBS, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": kfrac, "traffic": None, "algorithmic_bytes": 2 * npx,
+                         "kernel_ms_mean": head["kernel_ms_mean"],
+                         "timing": "HIP events around the persistent kernel of every timed step"},
+            "parity": head["parity"]}
 
 
 def _residual_planes(seed, nf):
@@ -492,109 +523,166 @@ def _residual_planes(seed, nf):
     return [p for fr in out for p in fr]
 
 
+RESID_FORMS = {  # name -> (backend, flags): the matrix-core kernel needs the declared sample range
+    "mfma": ("BACKEND_MFMA", "FLAG_RESIDUAL_RANGE"),
+    "valu": ("BACKEND_VALU", None),
+}
+
+
+def _resid_plan(A, hs, ws, ps, offs, q, form, qmode=None, extra_flags=0):
+    be, fl = RESID_FORMS[form]
+    flags = A.FLAG_AUTOTUNE | extra_flags | (getattr(A, fl) if fl else 0)
+    return A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, qmode=qmode if qmode is not None else A.Q_UNIFORM,
+                  q=q, qcoef_dtype=A.I16, out_dtype=A.I16, backend=getattr(A, be), flags=flags)
+
+
+def _resid_parity(planes, hs, ws, ps, offs, rec, lv, sse, plan, q):
+    """Frame 0's three planes against the oracle (outside the timed region):
+    levels bit-exact, reconstruction equal except within 1e-9 of a rounding
+    tie, SSE exact for the returned reconstruction."""
+    from oracle import codec
+    rc = rec.cpu().numpy()
+    lvs = lv.cpu().numpy().reshape(-1, 16, 16)
+    ss = sse.cpu().numpy()
+    ok = True
+    blk = 0
+    for i in range(3):
+        im = planes[i]
+        h, w = im.shape
+        nb = ((h + 15) // 16) * ((w + 15) // 16)
+        want = codec.quantise_uniform(codec.forward_image(im), q)
+        ok &= bool(np.array_equal(lvs[blk:blk + nb].astype(np.int64), want))
+        got = rc[offs[i]:offs[i] + h * ps[i]].reshape(h, ps[i])[:, :w]
+        real = codec.reconstruct_uniform(want, q, h, w, rounded=False)
+        rnd = np.clip(np.floor(real + 0.5), -32768, 32767)
+        bad = got.astype(np.int64) != rnd.astype(np.int64)
+        ok &= bool(np.all(np.abs(real - np.floor(real) - 0.5)[bad] < 1e-9))
+        ok &= int(ss[i]) == codec.sse(im, got)
+        blk += nb
+    return {"frames": [0], "planes": 3, "ok": ok,
+            "bar": "levels bit-exact; reconstruction equal except within 1e-9 of a rounding tie; SSE exact"}
+
+
 def bench_residual(args, A, torch):
-    """4:2:0 int16 residual frames (Y 3840x2160, U/V 1920x1080); uniform
-    quantiser q in {8, 16, 32}; per frame one fused call (levels and
-    reconstruction written, per-plane PSNR) replayed from a HIP graph."""
+    """C5: 4:2:0 int16 residual frames (Y 3840x2160, U/V 1920x1080), uniform
+    quantiser q in {8, 16, 32}; levels and reconstruction written, per-plane
+    SSE and PSNR.  Each step: one fused call per frame, replayed from that
+    frame's HIP graph.  Also the whole stream in one launch.  The matrix-core
+    kernel and the vector kernel on the same frames."""
     from synth import BASE_SEED, pack_images
     nf = args.frames or 120
-    planes = _residual_planes(BASE_SEED + 5, nf)
+    seed = BASE_SEED + 5
+    planes = _residual_planes(seed, nf)
     per = len(planes) // nf
-    # one packed buffer per frame so that each frame has its own graph
-    bufs = [pack_images(planes[i * per:(i + 1) * per]) for i in range(nf)]
     npx = sum(p.size for p in planes)
     stream = torch.cuda.current_stream()
-    out = {}
     qs = (args.q,) if args.q else (8, 16, 32)
-    rq = 16 if 16 in qs else qs[0]  # the step the roofline is quoted at
+    rq = 16 if 16 in qs else qs[0]  # the step the headline and roofline are quoted at
+    forms = ("mfma", "valu")
+    # one packed buffer per frame (each frame its own graph), and the whole stream
+    bufs = [pack_images(planes[i * per:(i + 1) * per], align_elems=64, pitch_multiple=64) for i in range(nf)]
+    big = pack_images(planes, align_elems=64, pitch_multiple=64)
+    out, roof, parity = {}, None, None
+    reps = max(10, args.steps)
     for q in qs:
-        graphs, keep = [], []
-        for buf, hs, ws, ps, offs in bufs:
+        for form in forms:
+            # per-frame graphs
+            keep, graphs = [], []
+            for buf, hs, ws, ps, offs in bufs:
+                dev = torch.from_numpy(buf).cuda()
+                rec = torch.empty_like(dev)
+                plan = _resid_plan(A, hs, ws, ps, offs, q, form)
+                lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
+                sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
+                psnr = torch.zeros(len(hs), dtype=torch.float64, device="cuda")
+                graphs.append(plan.graph(dev, rec, lv, sse, psnr))
+                keep.append((plan, dev, rec, lv, sse, psnr))
+            run = lambda: [g.launch() for g in graphs]
+            for _ in range(max(3, args.warmup)):
+                run()
+            ms = _events_ms(run, reps, stream)
+            out[f"q{q}_{form}_graphs_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
+            out[f"q{q}_{form}_psnr_y0_db"] = round(float(keep[0][5][0]), 4)
+            out[f"q{q}_{form}_plan"] = json.loads(keep[0][0].info())
+            if form == "mfma" and q == rq:
+                b0 = bufs[0]
+                parity = _resid_parity(planes[:per], *b0[1:], keep[0][2], keep[0][3], keep[0][4], keep[0][0], q)
+            del graphs, keep
+            # the whole stream in one launch
+            buf, hs, ws, ps, offs = big
             dev = torch.from_numpy(buf).cuda()
             rec = torch.empty_like(dev)
-            plan = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, qmode=A.Q_UNIFORM, q=q,
-                          qcoef_dtype=A.I16, out_dtype=A.I16, flags=A.FLAG_AUTOTUNE)
+            plan = _resid_plan(A, hs, ws, ps, offs, q, form)
             lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
             sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
             psnr = torch.zeros(len(hs), dtype=torch.float64, device="cuda")
-            graphs.append(plan.graph(dev, rec, lv, sse, psnr))
-            keep.append((plan, dev, rec, lv, sse, psnr))
-        run = lambda: [g.launch() for g in graphs]
-        for _ in range(max(3, args.warmup)):
-            run()
-        ms = _events_ms(run, max(10, args.steps), stream)
-        out[f"q{q}_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
-        out[f"q{q}_psnr_y_db"] = round(float(keep[0][5][0]), 4)
-        del graphs, keep
-        # the whole stream as one batch (one plan, one launch)
-        buf, hs, ws, ps, offs = pack_images(planes)
-        dev = torch.from_numpy(buf).cuda()
-        rec = torch.empty_like(dev)
-        plan = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, qmode=A.Q_UNIFORM, q=q,
-                      qcoef_dtype=A.I16, out_dtype=A.I16, flags=A.FLAG_AUTOTUNE)
-        lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
-        sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
-        psnr = torch.zeros(len(hs), dtype=torch.float64, device="cuda")
-        f = lambda: plan.compress_and_measure(dev, rec, lv, sse, psnr)
-        for _ in range(max(3, args.warmup)):
-            f()
-        ms = _events_ms(f, max(10, args.steps), stream)
-        out[f"q{q}_one_launch_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
-        out[f"q{q}_one_launch_plan"] = json.loads(plan.info())
-        if q == rq:
-            # algorithmic bytes of the one-launch call: the int16 samples read
-            # once, the int16 reconstruction and the int16 levels (256 per
-            # block, padded blocks included) written once
+            f = lambda: plan.compress_and_measure(dev, rec, lv, sse, psnr)
+            ms, kt = _timed_fused(plan, f, reps, max(3, args.warmup), stream, torch)
+            out[f"q{q}_{form}_one_launch_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
+            # algorithmic bytes: the int16 samples read once, the int16
+            # reconstruction and the int16 levels (256 per block, padded blocks
+            # included) written once
             alg = 4 * npx + 2 * 256 * plan.num_blocks
-            gbs = alg / (ms * 1e-3) / 1e9
-            kname = "k_fused<approx, int16 in, uniform, int16 levels, int16 out>"
-            wl = {"frames": nf, "q": q}
-            traffic = _traffic(kname, RES_COUNTERS, wl)
-            roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic / 1e9, 4) if traffic else None,
-                    "traffic_unit": "GB per launch", "algorithmic_bytes": alg, "kernel": kname,
-                    "kernel_ms": round(ms, 4), "timing": "HIP events around the one-launch call (fused kernel "
-                                                        f"and the per-image SSE finalise), q = {q}",
-                    "compute": _compute(kname, ms * 1e-3, RES_SQ_COUNTERS, wl)}
-            if args.calibrate_copy:
-                # plain copy kernel of the input buffer (HBM counter scaling)
-                torch.cuda.synchronize()
-                rec.copy_(dev)
-                torch.cuda.synchronize()
-                f()
-                torch.cuda.synchronize()
-                roof["calibration_copy_bytes"] = dev.nbytes
-        del dev, rec, lv
+            kmean = float(np.mean(kt))
+            out[f"q{q}_{form}_one_launch_kernel_frac"] = round(alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            if form == "mfma" and q == rq:
+                info = json.loads(plan.info())
+                kname = ("k_mfma_resid<uniform, int16 levels, int16 out>" if info["levels_backend"] == "mfma"
+                         else "k_fused<approx, int16 in, uniform, int16 levels, int16 out>")
+                gbs = alg / (kmean * 1e-3) / 1e9
+                wl = {"frames": nf, "q": q}
+                traffic = _traffic(kname, RES_COUNTERS, wl)
+                roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic / 1e9, 4) if traffic else None,
+                        "traffic_unit": "GB per launch", "algorithmic_bytes": alg, "kernel": kname,
+                        "kernel_ms_mean": round(kmean, 4), "kernel_ms_median": round(float(np.median(kt)), 4),
+                        "kernel_launches": len(kt),
+                        "timing": "HIP events around the persistent kernel of every timed one-launch call "
+                                  f"(adct16_plan_time_fused), q = {q}",
+                        "compute": _compute(kname, kmean * 1e-3, RES_SQ_COUNTERS, wl), "plan": info}
+                if args.calibrate_copy:
+                    # plain copy kernel of the input buffer (HBM counter scaling)
+                    torch.cuda.synchronize()
+                    rec.copy_(dev)
+                    torch.cuda.synchronize()
+                    roof["calibration_copy_bytes"] = dev.nbytes
+            del dev, rec, lv
     # forward only, the whole stream in one launch: vector ALUs against the
     # int8 matrix-core form (three base-64 digits per value), 2 + 4 B/sample
-    buf, hs, ws, ps, offs = pack_images(planes)
-    dev = torch.from_numpy(buf).cuda()
-    for name, be in (("valu", A.BACKEND_VALU), ("mfma_int8", A.BACKEND_MFMA)):
-        pf = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, out_dtype=A.I16, backend=be)
-        coef = torch.empty(pf.num_blocks * 256, dtype=torch.int32, device="cuda")
-        f = lambda: pf.forward(dev, coef)
-        for _ in range(max(3, args.warmup)):
-            f()
-        ms = _events_ms(f, max(10, args.steps), stream)
-        out[f"forward_{name}_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
-        out[f"forward_{name}_gbs"] = round(6 * npx / (ms * 1e-3) / 1e9, 1)
-        del coef
-    del dev
+    if not args.no_variants:
+        buf, hs, ws, ps, offs = big
+        dev = torch.from_numpy(buf).cuda()
+        for name, be in (("valu", A.BACKEND_VALU), ("mfma_int8", A.BACKEND_MFMA)):
+            pf = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, out_dtype=A.I16, backend=be)
+            coef = torch.empty(pf.num_blocks * 256, dtype=torch.int32, device="cuda")
+            f = lambda: pf.forward(dev, coef)
+            for _ in range(max(3, args.warmup)):
+                f()
+            ms = _events_ms(f, reps, stream)
+            out[f"forward_{name}_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
+            out[f"forward_{name}_gbs"] = round(6 * npx / (ms * 1e-3) / 1e9, 1)
+            del coef
+        del dev
+    head = out[f"q{rq}_mfma_graphs_gsample_s"]
     return {"metric": "Gsample/s 2D fwd+quant+inv 16x16, 4:2:0 int16 residual stream, graph per frame",
-            "value": out[f"q{rq}_gsample_s"], "unit": "Gsample/s", "n_gpus": 1, "steps": args.steps,
-            "dtype": "i16/f32/f64", "data": "synthetic", "higher_is_better": True,
-            "config": {"workload": f"{nf} frames 3840x2160 4:2:0 int16 residuals (AR(1) frames, per-block "
-                                   f"motion +-8), uniform q in {{{','.join(map(str, qs))}}} (value at q = {rq}), levels + "
-                                   "reconstruction written",
-                       "per_q": out},
-            "roofline": roof}
+            "value": head, "unit": "Gsample/s", "n_gpus": 1, "steps": reps, "warmup": max(3, args.warmup),
+            "ms_per_step": round(npx / (head * 1e9) * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "fp16 x fp16 -> fp32 MFMA (exact integers) + fp32 quantiser + fp64 combination",
+            "data": "synthetic",
+            "config": {"workload": f"{nf} frames 3840x2160 4:2:0 int16 residuals (AR(1) frames, per-block motion "
+                                   f"+-8), uniform q in {{{','.join(map(str, qs))}}} (value at q = {rq}, matrix-core "
+                                   "kernel, one HIP graph per frame), levels + reconstruction written, per-plane PSNR",
+                       "frames": nf, "seed": seed, "per_q": out},
+            "roofline": roof, "parity": parity}
 
 
 def bench_rd(args, A, torch):
     """Rate-distortion points of the deadzone quantiser on the 4:2:0 int16
     residual stream: for QP in {22, 27, 32, 37} (inter offset 1/6), one fused
-    launch over all frames (levels and reconstruction written, per-plane SSE),
-    then the signed Exp-Golomb rate proxy of the levels."""
+    launch over all frames (levels and reconstruction written, per-plane SSE)
+    on the matrix cores and on the vector ALUs, then the signed Exp-Golomb
+    rate proxy of the levels."""
     from synth import BASE_SEED, pack_images
     nf = args.frames or 120
     planes = _residual_planes(BASE_SEED + 5, nf)
@@ -606,51 +694,61 @@ def bench_rd(args, A, torch):
     points = []
     qps = (args.qp,) if args.qp else (22, 27, 32, 37)
     rqp = 27 if 27 in qps else qps[0]  # the point the roofline is quoted at
+    reps = max(2, args.steps // 4)
+    roof = None
     for qp in qps:
-        plan = A.Plan(hs, ws, ps, offs, in_dtype=A.I16, coef_dtype=A.I32, qmode=A.Q_DEADZONE, q=qp,
-                      qcoef_dtype=A.I16, out_dtype=A.I16, flags=A.FLAG_AUTOTUNE | A.FLAG_DEADZONE_INTER)
-        lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
-        sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
-        bits = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
-        f = lambda: plan.compress_and_measure(dev, rec, lv, sse, None)
-        f()
-        ms = _events_ms(f, max(2, args.steps // 4), stream)
-        plan.rate(lv, bits)
-        torch.cuda.synchronize()
-        y = slice(0, None, 3)  # luma planes
-        s_y = int(sse[y].sum())
-        n_y = sum(hs[i] * ws[i] for i in range(0, len(hs), 3))
-        points.append({"qp": qp, "bits_per_sample": round(int(bits.sum()) / npx, 5),
-                       "psnr_y_db": round(10 * np.log10(65025.0 * n_y / s_y), 4) if s_y else None,
-                       "gsample_s": round(npx / (ms * 1e-3) / 1e9, 4), "plan": json.loads(plan.info())})
-        if qp == rqp:
-            # samples read, reconstruction and levels (256 per block) written
-            alg = 4 * npx + 2 * 256 * plan.num_blocks
-            gbs = alg / (ms * 1e-3) / 1e9
-            kname = "k_fused<approx, int16 in, deadzone, int16 levels, int16 out>"
-            wl = {"frames": nf, "qp": qp}
-            traffic = _traffic(kname, RD_COUNTERS, wl)
-            roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic / 1e9, 4) if traffic else None,
-                    "traffic_unit": "GB per launch", "algorithmic_bytes": alg, "kernel": kname,
-                    "kernel_ms": round(ms, 4),
-                    "timing": "HIP events around the one-launch call (fused kernel and the per-image SSE "
-                              f"finalise), QP {qp}",
-                    "compute": _compute(kname, ms * 1e-3, RD_SQ_COUNTERS, wl)}
-            if args.calibrate_copy:
-                # plain copy kernel of the input buffer (HBM counter scaling)
-                torch.cuda.synchronize()
-                rec.copy_(dev)
-                torch.cuda.synchronize()
-                f()
-                torch.cuda.synchronize()
-                roof["calibration_copy_bytes"] = dev.nbytes
+        pt = {"qp": qp}
+        for form in ("mfma", "valu"):
+            plan = _resid_plan(A, hs, ws, ps, offs, qp, form, qmode=A.Q_DEADZONE, extra_flags=A.FLAG_DEADZONE_INTER)
+            lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
+            sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
+            bits = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
+            f = lambda: plan.compress_and_measure(dev, rec, lv, sse, None)
+            ms, kt = _timed_fused(plan, f, reps, 1, stream, torch)
+            plan.rate(lv, bits)
+            torch.cuda.synchronize()
+            pt[f"{form}_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
+            pt[f"{form}_plan"] = json.loads(plan.info())
+            if form == "mfma":
+                y = slice(0, None, 3)  # luma planes
+                s_y = int(sse[y].sum())
+                n_y = sum(hs[i] * ws[i] for i in range(0, len(hs), 3))
+                pt["bits_per_sample"] = round(int(bits.sum()) / npx, 5)
+                pt["psnr_y_db"] = round(10 * np.log10(65025.0 * n_y / s_y), 4) if s_y else None
+            if form == "mfma" and qp == rqp:
+                # samples read, reconstruction and levels (256 per block) written
+                alg = 4 * npx + 2 * 256 * plan.num_blocks
+                kmean = float(np.mean(kt))
+                gbs = alg / (kmean * 1e-3) / 1e9
+                kname = ("k_mfma_resid<deadzone, int16 levels, int16 out>" if pt["mfma_plan"]["levels_backend"] == "mfma"
+                         else "k_fused<approx, int16 in, deadzone, int16 levels, int16 out>")
+                wl = {"frames": nf, "qp": qp}
+                traffic = _traffic(kname, RD_COUNTERS, wl)
+                roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic / 1e9, 4) if traffic else None,
+                        "traffic_unit": "GB per launch", "algorithmic_bytes": alg, "kernel": kname,
+                        "kernel_ms_mean": round(kmean, 4), "kernel_ms_median": round(float(np.median(kt)), 4),
+                        "kernel_launches": len(kt),
+                        "timing": "HIP events around the persistent kernel of every timed call "
+                                  f"(adct16_plan_time_fused), QP {qp}",
+                        "compute": _compute(kname, kmean * 1e-3, RD_SQ_COUNTERS, wl)}
+                if args.calibrate_copy:
+                    # plain copy kernel of the input buffer (HBM counter scaling)
+                    torch.cuda.synchronize()
+                    rec.copy_(dev)
+                    torch.cuda.synchronize()
+                    roof["calibration_copy_bytes"] = dev.nbytes
+            del lv
+        points.append(pt)
+    head = points[qps.index(rqp)]["mfma_gsample_s"]
     return {"metric": "Gsample/s 2D fwd+deadzone quant+inv 16x16 with rate proxy, 4:2:0 int16 residual stream",
-            "value": points[qps.index(rqp)]["gsample_s"], "unit": "Gsample/s", "n_gpus": 1, "steps": args.steps,
-            "dtype": "i16/f32/f64", "data": "synthetic", "higher_is_better": True,
+            "value": head, "unit": "Gsample/s", "n_gpus": 1, "steps": reps, "higher_is_better": True,
+            "dtype": "fp16 x fp16 -> fp32 MFMA (exact integers) + fp32 quantiser + fp64 combination",
+            "data": "synthetic",
             "config": {"workload": f"{nf} frames 3840x2160 4:2:0 int16 residuals, deadzone quantiser "
-                                   f"(inter offset 1/6), QP {'/'.join(map(str, qps))} (value at QP {rqp}), levels + reconstruction written",
-                       "rd_curve": points},
+                                   f"(inter offset 1/6), QP {'/'.join(map(str, qps))} (value at QP {rqp}, matrix-core "
+                                   "kernel, one launch), levels + reconstruction written",
+                       "frames": nf, "seed": BASE_SEED + 5, "rd_curve": points},
             "roofline": roof}
 
 

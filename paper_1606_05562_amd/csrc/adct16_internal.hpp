@@ -78,6 +78,14 @@ struct Tables {
   // step / sqrt(192), step / sqrt(96)).
   signed char rcls[16];
   double rcomb[4];
+  // ... and its per-lane constant operands, built on the host: entry
+  // [i][lane] is dword group i (4 dwords) of lane 16 g + q, in the order
+  // T[q][4g..4g+3] (2 dwords, fp16), the accumulator start, the quantiser
+  // multipliers M[q][4g..4g+3], the four first-pass B operands (2 dwords
+  // each) and the seven second-pass B operands (4 dwords each), 43 dwords
+  // padded to 44.
+  static constexpr int kResConstGroups = 11;
+  uint32_t rconst[kResConstGroups][64][4];
 };
 
 // The integer matrix of a plan: MAT_APPROX is T of the proposed transform,

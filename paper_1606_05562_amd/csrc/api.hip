@@ -94,6 +94,69 @@ int esize(int dt) {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// fp16 bits of an integer of magnitude at most 2048 (exact).
+uint32_t f16_of_int(int v) {
+  if (v == 0) return 0;
+  const uint32_t sign = v < 0 ? 0x8000u : 0u;
+  const uint32_t a = (uint32_t)(v < 0 ? -v : v);
+  const int e = 31 - __builtin_clz(a);
+  return sign | ((uint32_t)(e + 15) << 10) | ((a << (10 - e)) & 0x3ffu);
+}
+
+uint32_t f16_pair(int lo, int hi) { return f16_of_int(lo) | (f16_of_int(hi) << 16); }
+
+// Coefficient of the first-pass class c's row u in the residual kernel's
+// output R_k: k = 0 pairs rows of equal norm (weight w_u = 48 / n_u),
+// k = 1, 2, 3 the norm pairs (16, 8), (16, 12), (12, 8).  Classes: 0 norm
+// 16, 1 and 2 norm 12, 3 norm 8.
+int resid_coef(int k, int cu, int c, int wu) {
+  auto base = [](int x) { return x == 2 ? 1 : x; };
+  const int a = base(cu), b = base(c);
+  switch (k) {
+    case 0: return a == b ? wu : 0;
+    case 1: return (a == 0 && b == 3) || (a == 3 && b == 0);
+    case 2: return (a == 0 && b == 1) || (a == 1 && b == 0);
+    default: return (a == 1 && b == 3) || (a == 3 && b == 1);
+  }
+}
+
+// Per-lane constant operands of the matrix-core residual kernel (the layout
+// of Tables::rconst): lane 16 g + q holds T[q][4g..4g+3], the accumulator
+// start, M[q][4g..4g+3], the first-pass B operands [class(4g+v) == c]
+// T[4g+v][q] and the second-pass B operands coef_k(class(u), c) T[u][q] for
+// u = 4g..4g+3 and the two classes of each product.
+void resid_lane_consts(Tables& t) {
+  auto T = [&](int u, int k) { return (int)t.tmat[u * 16 + k]; };
+  const int prod_k[7] = {0, 0, 1, 2, 2, 3, 3};
+  const int prod_p[7] = {0, 1, 0, 0, 1, 0, 1};
+  for (int lane = 0; lane < 64; ++lane) {
+    const int q = lane & 15, g = lane >> 4;
+    uint32_t w[4 * Tables::kResConstGroups] = {};
+    w[0] = f16_pair(T(q, 4 * g), T(q, 4 * g + 1));
+    w[1] = f16_pair(T(q, 4 * g + 2), T(q, 4 * g + 3));
+    const float c1 = q == 0 ? -20480.0f : 0.0f;
+    memcpy(&w[2], &c1, 4);
+    for (int v = 0; v < 4; ++v) memcpy(&w[3 + v], &t.qmul[q * 16 + 4 * g + v], 4);
+    for (int c = 0; c < 4; ++c) {
+      int y[4];
+      for (int v = 0; v < 4; ++v) y[v] = t.rcls[4 * g + v] == c ? T(4 * g + v, q) : 0;
+      w[7 + 2 * c] = f16_pair(y[0], y[1]);
+      w[8 + 2 * c] = f16_pair(y[2], y[3]);
+    }
+    for (int i = 0; i < 7; ++i) {
+      const int ca = prod_p[i] == 0 ? 0 : 1, cb = prod_p[i] == 0 ? 3 : 2;
+      int h[8];
+      for (int v = 0; v < 4; ++v) {
+        const int u = 4 * g + v;
+        h[v] = resid_coef(prod_k[i], t.rcls[u], ca, t.wvec[u]) * T(u, q);
+        h[4 + v] = resid_coef(prod_k[i], t.rcls[u], cb, t.wvec[u]) * T(u, q);
+      }
+      for (int j = 0; j < 4; ++j) w[15 + 4 * i + j] = f16_pair(h[2 * j], h[2 * j + 1]);
+    }
+    for (int j = 0; j < 4 * Tables::kResConstGroups; ++j) t.rconst[j / 4][lane][j % 4] = w[j];
+  }
+}
+
 }  // namespace
 
 // Scratch of adct16_compress_and_measure_static: every GPU the library runs
@@ -652,6 +715,7 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
     t.rcomb[1] = step / std::sqrt(128.0);
     t.rcomb[2] = step / std::sqrt(192.0);
     t.rcomb[3] = step / std::sqrt(96.0);
+    resid_lane_consts(t);
   }
   // comparison transform and SSIM window
   for (int k = 0; k < 16; ++k)

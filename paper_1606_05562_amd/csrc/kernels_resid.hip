@@ -81,60 +81,27 @@ struct ResidConsts {
   uint4 rb[7];    // I2 B: R0 p0, R0 p1, R2 p0, R3 p0, R3 p1, R6 p0, R6 p1
 };
 
-// Base class of a row class (0: norm 16, 1 and 2: norm 12, 3: norm 8).
-__device__ __forceinline__ int norm_class(int c) { return c == 2 ? 1 : c; }
-
-// Coefficient of Y_c row u in R_k (k = 0: equal norms, 1: (16, 8),
-// 2: (16, 12), 3: (12, 8)).
-__device__ __forceinline__ int rcoef(int k, int cu, int c, int wu) {
-  const int a = norm_class(cu), b = norm_class(c);
-  switch (k) {
-    case 0: return a == b ? wu : 0;
-    case 1: return (a == 0 && b == 3) || (a == 3 && b == 0);
-    case 2: return (a == 0 && b == 1) || (a == 1 && b == 0);
-    default: return (a == 1 && b == 3) || (a == 3 && b == 1);
+// The per-lane constants, read from the plan's table (built on the host:
+// resid_lane_consts in api.hip), 11 coalesced 16-byte loads per lane.
+__device__ __forceinline__ ResidConsts load_resid_consts(int lane, const Tables* tb) {
+  uint32_t w[4 * Tables::kResConstGroups];
+#pragma unroll
+  for (int i = 0; i < Tables::kResConstGroups; ++i) {
+    const uint4 v = *reinterpret_cast<const uint4*>(tb->rconst[i][lane]);
+    w[4 * i] = v.x;
+    w[4 * i + 1] = v.y;
+    w[4 * i + 2] = v.z;
+    w[4 * i + 3] = v.w;
   }
-}
-
-__device__ __forceinline__ ResidConsts make_resid_consts(int q, int g, const Tables* tb) {
-  const signed char* tm = tb->tmat;
-  auto kT = [tm](int u, int kk) { return (int)tm[u * 16 + kk]; };
   ResidConsts k;
-  float t[4];
+  k.tq = make_uint2(w[0], w[1]);
+  k.c1 = __builtin_bit_cast(float, w[2]);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    t[v] = (float)kT(q, 4 * g + v);
-    k.m[v] = tb->qmul[q * 16 + 4 * g + v];
-  }
-  k.tq = make_uint2(pack_h(t[0], t[1]), pack_h(t[2], t[3]));
-  k.c1 = q == 0 ? -20480.0f : 0.0f;
-  int cls[4], wu[4];
+  for (int v = 0; v < 4; ++v) k.m[v] = __builtin_bit_cast(float, w[3 + v]);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    cls[v] = tb->rcls[4 * g + v];
-    wu[v] = tb->wvec[4 * g + v];
-  }
+  for (int c = 0; c < 4; ++c) k.yb[c] = make_uint2(w[7 + 2 * c], w[8 + 2 * c]);
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    float y[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) y[v] = cls[v] == c ? (float)kT(4 * g + v, q) : 0.0f;
-    k.yb[c] = make_uint2(pack_h(y[0], y[1]), pack_h(y[2], y[3]));
-  }
-  const int prod_k[7] = {0, 0, 1, 2, 2, 3, 3};
-  const int prod_p[7] = {0, 1, 0, 0, 1, 0, 1};
-#pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    const int ca = prod_p[i] == 0 ? 0 : 1, cb = prod_p[i] == 0 ? 3 : 2;
-    float h[8];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int u = 4 * g + v;
-      h[v] = (float)(rcoef(prod_k[i], cls[v], ca, wu[v]) * kT(u, q));
-      h[4 + v] = (float)(rcoef(prod_k[i], cls[v], cb, wu[v]) * kT(u, q));
-    }
-    k.rb[i] = make_uint4(pack_h(h[0], h[1]), pack_h(h[2], h[3]), pack_h(h[4], h[5]), pack_h(h[6], h[7]));
-  }
+  for (int i = 0; i < 7; ++i) k.rb[i] = make_uint4(w[15 + 4 * i], w[16 + 4 * i], w[17 + 4 * i], w[18 + 4 * i]);
   return k;
 }
 
@@ -324,7 +291,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_RESID_MIN_WG) void k_mfma_res
   int* lds = lds_all + (threadIdx.x >> 6) * kWaveDw;
   int* lvl = lds + kResWaveLds;  // level staging (interior strips)
   const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4, rr = lane >> 4, cc = lane & 15;
-  const ResidConsts k = make_resid_consts(q, g, P.tables);
+  const ResidConsts k = load_resid_consts(lane, P.tables);
   const double cmb[4] = {P.tables->rcomb[0], P.tables->rcomb[1], P.tables->rcomb[2], P.tables->rcomb[3]};
   const float f = P.tables->qoff;
   const int16_t* in = reinterpret_cast<const int16_t*>(P.in);
@@ -357,10 +324,18 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_RESID_MIN_WG) void k_mfma_res
 #pragma unroll
     for (int i = 0; i < 4; ++i) v[i] = ld_row16<NT>(reinterpret_cast<const uint8_t*>(in + lane_src(dd, ssy, ssxi, i)));
   };
-  // LDS rows of a strip: lane (rr, cc) writes its 16 bytes of rows 4i + rr
-  auto rows_to_lds = [&](const uint4 (&v)[4]) {
+  // LDS rows of a strip: lane (rr, cc) writes its 16 bytes of rows 4i + rr.
+  // Called right after an explicit vmcnt(0): the empty asm statements mark
+  // the loaded registers as redefined there, so that the compiler's wait
+  // tracking no longer holds their loads pending (it would otherwise wait
+  // on them, and in hardware on every later store, where the registers are
+  // next reused).
+  auto rows_to_lds = [&](uint4 (&v)[4]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) *reinterpret_cast<uint4*>(lds + (4 * i + rr) * kResRow + 4 * cc) = v[i];
+    for (int i = 0; i < 4; ++i) {
+      asm volatile("" : "+v"(v[i].x), "+v"(v[i].y), "+v"(v[i].z), "+v"(v[i].w));
+      *reinterpret_cast<uint4*>(lds + (4 * i + rr) * kResRow + 4 * cc) = v[i];
+    }
   };
   uint4 nr[4];
   load4(d, sy, sxi, nr);
@@ -444,16 +419,20 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_RESID_MIN_WG) void k_mfma_res
         }
       }
     }
-    if constexpr (!EDGE) {
-      // All of the strip's stores at its end.  The explicit vmcnt(0) first
-      // completes the next strip's row loads (issued when this strip began,
-      // so it costs little) together with the previous strip's stores, and
-      // those rows go to LDS right after it, before any store: the
-      // compiler's own count ignores stores, and would make the first use of
-      // a loaded register after a store wait for every store.
-      __builtin_amdgcn_s_waitcnt(0x0F70);
-      wave_lds_sync();
-      uint4 orow[4], lw[kStripBlocks];
+  };
+  // The end of a strip of either kind.  The explicit vmcnt(0) completes the
+  // next strip's row loads (issued when this strip began, so it costs
+  // little) together with the previous strip's stores, and those rows go to
+  // LDS right after it, before any store.  It sits on the one path that both
+  // strip kinds share: the compiler's own count ignores stores, so a path
+  // around it would leave the row loads pending at the loop head and make
+  // the next strip wait there for every store of this one.  An interior
+  // strip stores its reconstruction and levels here, from LDS.
+  auto strip_end = [&](bool inner, int64_t rowblk) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    wave_lds_sync();
+    uint4 orow[4], lw[kStripBlocks];
+    if (inner) {
       if constexpr (OUT == OUT_I16) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) orow[i] = *reinterpret_cast<const uint4*>(lds + (4 * i + rr) * kResRow + 4 * cc);
@@ -463,7 +442,9 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_RESID_MIN_WG) void k_mfma_res
         for (int b = 0; b < kStripBlocks; ++b) lw[b] = read_levels<QOUT>(lvl, b, q, g);
       }
       wave_lds_sync();
-      rows_to_lds(nr);
+    }
+    rows_to_lds(nr);
+    if (inner) {
       if constexpr (OUT == OUT_I16) {
         const int64_t o = d.offset + (int64_t)(sy * 16 + rr) * d.pitch + sxi * (16 * kStripBlocks) + 8 * cc;
 #pragma unroll
@@ -500,15 +481,13 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_RESID_MIN_WG) void k_mfma_res
     // the next strip's rows requested (this strip's are in LDS)
     load4(nd, nsy, nsxi, nr);
     const int64_t rowblk = d.block_begin + (int64_t)sy * d.bx + sxi * kStripBlocks;
-    if (interior(d, sy, sxi)) {
+    const bool inner = interior(d, sy, sxi);
+    if (inner) {
       strip(std::integral_constant<bool, false>(), rowblk, kStripBlocks);
     } else {
       strip(std::integral_constant<bool, true>(), rowblk, min(kStripBlocks, d.bx - sxi * kStripBlocks));
-      // the next strip's rows replace this strip's in LDS
-      __builtin_amdgcn_s_waitcnt(0x0F70);
-      wave_lds_sync();
-      rows_to_lds(nr);
     }
+    strip_end(inner, rowblk);
     wave_lds_sync();
     if (task_end) {
       const unsigned long long task_sum = wave_sum_u64(lane_sse);

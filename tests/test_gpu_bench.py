@@ -74,24 +74,36 @@ def test_bench_target_small():
 def test_bench_ragged_small():
     line = _run("ragged", 4)
     assert _positive(line["value"]) and line["roofline"]["bound"] == "hbm"
+    lay = line["config"]["layouts"]
+    assert set(lay) == {"lines128", "packed16"}
+    assert lay["lines128"]["plan"]["rows_line_aligned"] is True
+    assert all(_positive(x["gpix_s"]) and x["parity"]["ok"] is True for x in lay.values())
+    assert lay["packed16"]["bytes"] <= lay["lines128"]["bytes"]
 
 
 def test_bench_residual_small():
     line = _run("residual", 1)
     per_q = line["config"]["per_q"]
-    assert all(_positive(per_q[f"q{q}_gsample_s"]) and _positive(per_q[f"q{q}_one_launch_gsample_s"])
-               for q in (8, 16, 32))
+    for q in (8, 16, 32):
+        for form in ("mfma", "valu"):
+            assert _positive(per_q[f"q{q}_{form}_graphs_gsample_s"])
+            assert _positive(per_q[f"q{q}_{form}_one_launch_gsample_s"])
+        assert per_q[f"q{q}_mfma_plan"]["levels_backend"] == "mfma"
+        assert per_q[f"q{q}_valu_plan"]["levels_backend"] == "valu"
+    assert line["value"] == per_q["q16_mfma_graphs_gsample_s"]
     r = line["roofline"]
     assert r["bound"] == "hbm" and _positive(r["achieved"]) and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
-    # the committed counters were taken on 8 frames: none reported for 1
+    assert r["kernel"].startswith("k_mfma_resid") and r["kernel_launches"] == line["steps"]
+    assert line["parity"]["ok"] is True
+    # counters are committed for the full 120-frame stream only
     assert r["traffic"] is None and r["compute"] is None
 
 
 def test_bench_residual_one_step_with_copy_calibration():
     line = _run("residual", 1, q=8, calibrate_copy=True)
     per_q = line["config"]["per_q"]
-    assert _positive(per_q["q8_gsample_s"]) and "q16_gsample_s" not in per_q
-    assert line["value"] == per_q["q8_gsample_s"]
+    assert _positive(per_q["q8_mfma_graphs_gsample_s"]) and "q16_mfma_graphs_gsample_s" not in per_q
+    assert line["value"] == per_q["q8_mfma_graphs_gsample_s"]
     r = line["roofline"]
     assert "q = 8" in r["timing"] and r["calibration_copy_bytes"] > 0
 
@@ -99,7 +111,7 @@ def test_bench_residual_one_step_with_copy_calibration():
 def test_bench_rd_one_point_with_copy_calibration():
     line = _run("rd", 1, qp=32, calibrate_copy=True)
     pts = line["config"]["rd_curve"]
-    assert [p["qp"] for p in pts] == [32] and line["value"] == pts[0]["gsample_s"]
+    assert [p["qp"] for p in pts] == [32] and line["value"] == pts[0]["mfma_gsample_s"]
     r = line["roofline"]
     assert "QP 32" in r["timing"] and r["calibration_copy_bytes"] > 0
 
@@ -108,7 +120,8 @@ def test_bench_rd_small():
     line = _run("rd", 1)
     pts = line["config"]["rd_curve"]
     assert [p["qp"] for p in pts] == [22, 27, 32, 37]
-    assert line["value"] == pts[1]["gsample_s"]
+    assert line["value"] == pts[1]["mfma_gsample_s"]
+    assert all(p["mfma_plan"]["levels_backend"] == "mfma" and _positive(p["valu_gsample_s"]) for p in pts)
     # the committed counters were taken on 8 frames: none reported for 1
     assert line["roofline"]["traffic"] is None and line["roofline"]["compute"] is None
     # coarser steps never cost more bits
