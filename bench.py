@@ -34,10 +34,10 @@ COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_hbm_counters.json")
 SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_luma256_sq_counters.json")
 UHD_COUNTERS = os.path.join(ROOT, "profiles", "fused_uhd64_hbm_counters.json")
 UHD_SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_uhd64_sq_counters.json")
-RES_COUNTERS = os.path.join(ROOT, "profiles", "fused_residual8_hbm_counters.json")
-RES_SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_residual8_sq_counters.json")
-RD_COUNTERS = os.path.join(ROOT, "profiles", "fused_rd8_hbm_counters.json")
-RD_SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_rd8_sq_counters.json")
+RES_COUNTERS = os.path.join(ROOT, "profiles", "fused_resid120_q16_hbm_counters.json")
+RES_SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_resid120_q16_sq_counters.json")
+RD_COUNTERS = os.path.join(ROOT, "profiles", "fused_rd120_qp27_hbm_counters.json")
+RD_SQ_COUNTERS = os.path.join(ROOT, "profiles", "fused_rd120_qp27_sq_counters.json")
 # Issue capacity of the chip's 256 CUs x 4 SIMDs at 2.4 GHz: a wave64 VALU
 # instruction occupies its 16-lane SIMD for 4 cycles, and each SIMD's matrix
 # core has 2.4e9 busy cycles per second.

@@ -196,13 +196,15 @@ struct adct16_plan_s {
   int64_t n_blocks = 0, n_strips = 0;
   ImageDesc* d_images = nullptr;
   Tables* d_tables = nullptr;
-  // Task tables of the matrix-core kernels: [0] 4-strip tasks, [1] 16-strip tasks.
+  // Task tables of the matrix-core kernels: [0] 4-strip, [1] 16-strip and
+  // [2] 1-strip tasks (the last for launches with few strips per wavefront,
+  // where the latency of a wavefront's last task sets the launch time).
   struct TaskTable {
     RowTask* d_rows = nullptr;
     int64_t* d_first = nullptr;  // each image's first task, n_images + 1 entries
     int64_t n_rows = 0;
     int strips = 0;
-  } tasks[2];
+  } tasks[kTaskTables];
   int task_sel = 0;     // table of the calls without level output
   int task_sel_lv = 0;  // table of the calls with level output
   uint32_t* d_task_sse = nullptr;  // per-task SSE partials of the matrix-core fused kernel
@@ -395,7 +397,7 @@ std::string tune_key(const adct16_plan_s* p, const char* arch, bool levels) {
     << "/o" << p->out_kind << "/f"
     << (p->d.flags & (ADCT16_FLAG_EXPLICIT_COEF | ADCT16_FLAG_MFMA_INT8 | ADCT16_FLAG_RESIDUAL_RANGE))
     << "/lv" << (levels ? p->qcoef_kind : -1)
-    << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips) << "/v2";
+    << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips) << "/v3";
   return k.str();
 }
 
@@ -486,7 +488,7 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
   if (p->d.backend != ADCT16_BACKEND_MFMA || !mfma_ok)
     for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_VALU, wg, grid_for(p, wg), 0, 1e30f});
   if (p->d.backend != ADCT16_BACKEND_VALU && mfma_ok)
-    for (int ts = 0; ts < 2; ++ts)
+    for (int ts = 0; ts < kTaskTables; ++ts)
       for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_MFMA, wg, grid_for(p, wg), ts, 1e30f});
   void* const tout = p->out_kind == OUT_F32 ? nullptr : w.dout;
   // Warm-up (code objects, and the engine clock, which ramps up under load):
@@ -733,10 +735,10 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   }
   p->n_ssim_tiles = ssim_tiles.back();
   t.rsep = d->qmode == ADCT16_Q_ZONAL ? d->r : 16;
-  std::vector<RowTask> rows[2];
-  std::vector<int64_t> first[2];
-  for (int ts = 0; ts < 2; ++ts) {
-    const int n = ts == 0 ? kTaskStripsShort : kTaskStripsLong;
+  std::vector<RowTask> rows[kTaskTables];
+  std::vector<int64_t> first[kTaskTables];
+  for (int ts = 0; ts < kTaskTables; ++ts) {
+    const int n = ts == 0 ? kTaskStripsShort : ts == 1 ? kTaskStripsLong : kTaskStripsUnit;
     p->tasks[ts].strips = n;
     for (size_t i = 0; i < images.size(); ++i) {
       first[ts].push_back((int64_t)rows[ts].size());
@@ -755,22 +757,24 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   // more wavefronts at once (at most 2^20 accumulators in all)
   p->sse_slots = images.size() <= 1024 ? 64 : images.size() <= 16384 ? 8 : 1;
   bool ok = hipMalloc(&p->d_images, sizeof(ImageDesc) * images.size()) == hipSuccess &&
-            hipMalloc(&p->d_tables, sizeof(Tables)) == hipSuccess &&
-            hipMalloc(&p->tasks[0].d_rows, sizeof(RowTask) * rows[0].size()) == hipSuccess &&
-            hipMalloc(&p->tasks[1].d_rows, sizeof(RowTask) * rows[1].size()) == hipSuccess &&
-            hipMalloc(&p->tasks[0].d_first, sizeof(int64_t) * first[0].size()) == hipSuccess &&
-            hipMalloc(&p->tasks[1].d_first, sizeof(int64_t) * first[1].size()) == hipSuccess &&
-            hipMalloc(&p->d_task_sse, sizeof(unsigned long long) * rows[0].size()) == hipSuccess &&
+            hipMalloc(&p->d_tables, sizeof(Tables)) == hipSuccess;
+  size_t max_rows = 0;
+  for (int ts = 0; ts < kTaskTables; ++ts) {
+    max_rows = std::max(max_rows, rows[ts].size());
+    ok = ok && hipMalloc(&p->tasks[ts].d_rows, sizeof(RowTask) * rows[ts].size()) == hipSuccess &&
+         hipMalloc(&p->tasks[ts].d_first, sizeof(int64_t) * first[ts].size()) == hipSuccess &&
+         hipMemcpy(p->tasks[ts].d_rows, rows[ts].data(), sizeof(RowTask) * rows[ts].size(), hipMemcpyHostToDevice) ==
+             hipSuccess &&
+         hipMemcpy(p->tasks[ts].d_first, first[ts].data(), sizeof(int64_t) * first[ts].size(), hipMemcpyHostToDevice) ==
+             hipSuccess;
+  }
+  ok = ok && hipMalloc(&p->d_task_sse, sizeof(unsigned long long) * max_rows) == hipSuccess &&
             hipMalloc(&p->d_ssim_tiles, sizeof(int64_t) * ssim_tiles.size()) == hipSuccess &&
             hipMalloc(&p->d_sse_ws, sizeof(unsigned long long) * images.size() * p->sse_slots) == hipSuccess &&
             hipMalloc(&p->d_sse_out, sizeof(unsigned long long) * images.size()) == hipSuccess;
   ok = ok && hipMemset(p->d_sse_ws, 0, sizeof(unsigned long long) * images.size() * p->sse_slots) == hipSuccess;
   ok = ok && hipMemcpy(p->d_images, images.data(), sizeof(ImageDesc) * images.size(), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_tables, &t, sizeof t, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->tasks[0].d_rows, rows[0].data(), sizeof(RowTask) * rows[0].size(), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->tasks[1].d_rows, rows[1].data(), sizeof(RowTask) * rows[1].size(), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->tasks[0].d_first, first[0].data(), sizeof(int64_t) * first[0].size(), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->tasks[1].d_first, first[1].data(), sizeof(int64_t) * first[1].size(), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(p->d_ssim_tiles, ssim_tiles.data(), sizeof(int64_t) * ssim_tiles.size(), hipMemcpyHostToDevice) ==
            hipSuccess;
   if (!ok) {
@@ -786,7 +790,10 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)p->cu_count * wgpc, max_groups));
   // task size of the matrix-core kernels (ADCT16_TASK_STRIPS = 4 or 16 overrides the default 4; the
   // autotuner may replace it)
-  if (const char* env = getenv("ADCT16_TASK_STRIPS")) p->task_sel = atoi(env) >= kTaskStripsLong ? 1 : 0;
+  if (const char* env = getenv("ADCT16_TASK_STRIPS")) {
+    const int n = atoi(env);
+    p->task_sel = n >= kTaskStripsLong ? 1 : n <= kTaskStripsUnit ? 2 : 0;
+  }
   if (d->backend == ADCT16_BACKEND_MFMA && !mfma_supported(p) && !mfma_forward_supported(p)) {
     adct16_plan_destroy(p);
     return fail(ADCT16_E_MODE,

@@ -235,9 +235,9 @@ def test_mfma_ragged(align):
         assert np.array_equal(got, want) and sse[i] == s
 
 
-@pytest.mark.parametrize("strips", [4, 16])
+@pytest.mark.parametrize("strips", [1, 4, 16])
 def test_mfma_task_sizes(monkeypatch, strips):
-    """Both task tables (equal runs of at most 4 or 16 strips of a block
+    """The task tables (equal runs of at most 1, 4 or 16 strips of a block
     row), on images whose block rows hold fewer and more strips than a run
     and split into runs of unequal length (2050 pixels: 17 strips, 8 + 9 or
     3 + 3 + 4 + 3 + 4), through the fused kernel and both forward forms."""
@@ -400,7 +400,7 @@ def _images_i16_full():
     return ims
 
 
-@pytest.mark.parametrize("align,strips", [(16, 4), (128, 4), (128, 16)])
+@pytest.mark.parametrize("align,strips", [(16, 4), (128, 1), (128, 4), (128, 16)])
 def test_mfma_forward_i16_bit_exact(monkeypatch, align, strips):
     """16-bit input through the int8 form with three base-64 digits per value
     (both passes): bit-exact with the oracle and the vector-ALU forward on

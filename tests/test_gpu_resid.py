@@ -107,6 +107,21 @@ def test_resid_mfma_uniform_against_oracle(batch_res, q):
         _check_recon(got, real, im, sse[i], psnr[i], want_rec)
 
 
+@pytest.mark.parametrize("strips", [1, 4, 16])
+def test_resid_mfma_task_sizes(monkeypatch, batch_res, strips):
+    """The three task tables (runs of at most 1, 4 or 16 strips)."""
+    monkeypatch.setenv("ADCT16_TASK_STRIPS", str(strips))
+    recs, lvs, sse, psnr, info = _run(batch_res, A().BACKEND_MFMA, A().Q_UNIFORM, 16, A().FLAG_RESIDUAL_RANGE)
+    assert info["levels_backend"] == "mfma" and info["levels_task_strips"] == strips
+    for i, (got, lvl, im) in enumerate(zip(recs, lvs, batch_res.images)):
+        h, w = im.shape
+        want_lv = codec.quantise_uniform(codec.forward_image(im), 16)
+        assert np.array_equal(lvl.astype(np.int64), want_lv), f"image {i}"
+        real = codec.reconstruct_uniform(want_lv, 16, h, w, rounded=False)
+        want_rec = codec.reconstruct_uniform(want_lv, 16, h, w, out_dtype=np.int16)
+        _check_recon(got, real, im, sse[i], psnr[i], want_rec)
+
+
 @pytest.mark.parametrize("qp,inter", [(22, False), (27, True), (32, True), (37, False), (51, True)])
 def test_resid_mfma_deadzone_against_oracle(batch_res, qp, inter):
     flags = A().FLAG_RESIDUAL_RANGE | (A().FLAG_DEADZONE_INTER if inter else 0)
