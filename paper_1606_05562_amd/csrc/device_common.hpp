@@ -324,6 +324,60 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
+// SSE and PSNR of image blockIdx.x from its task partials (a workgroup of
+// kFinishThreads threads, four loads in flight per thread): 32-bit
+// partials, or 64-bit ones (WIDE) where ~0 marks a task that saw a sample
+// outside the kernel's domain (SSE -1, PSNR NaN).
+constexpr int kFinishThreads = 256;
+
+template <bool WIDE>
+__device__ __forceinline__ void finish_image(const Params& P) {
+  __shared__ unsigned long long part[kFinishThreads / 64];
+  __shared__ int part_bad[kFinishThreads / 64];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int64_t b = P.task_first[i], e = P.task_first[i + 1];
+  unsigned long long v = 0;
+  bool bad = false;
+  auto take = [&](int64_t t) {
+    if constexpr (WIDE) {
+      const unsigned long long s = P.task_sse64[t];
+      bad |= s == ~0ull;
+      v += s;
+    } else {
+      v += P.task_sse[t];
+    }
+  };
+  int64_t t = b + tid;
+  for (; t + 3 * kFinishThreads < e; t += 4 * kFinishThreads) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) take(t + u * kFinishThreads);
+  }
+  for (; t < e; t += kFinishThreads) take(t);
+  v = wave_sum_u64(v);
+  const bool wbad = __builtin_amdgcn_ballot_w64(bad) != 0;
+  if ((tid & 63) == 0) {
+    part[tid >> 6] = v;
+    part_bad[tid >> 6] = wbad;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long sum = 0;
+    bool any_bad = false;
+#pragma unroll
+    for (int w = 0; w < kFinishThreads / 64; ++w) {
+      sum += part[w];
+      any_bad |= part_bad[w] != 0;
+    }
+    P.sse[i] = any_bad ? ~0ull : sum;
+    if (P.psnr) {
+      const ImageDesc& d = P.images[i];
+      P.psnr[i] = any_bad ? __builtin_nan("")
+                          : sum == 0 ? __builtin_huge_val()
+                                     : 10.0 * log10(65025.0 * (double)d.h * (double)d.w / (double)sum);
+    }
+  }
+}
+
 __device__ __forceinline__ unsigned byte_of(const uint4& q, int k) {
   const unsigned w = k < 4 ? q.x : k < 8 ? q.y : k < 12 ? q.z : q.w;
   return (w >> (8 * (k & 3))) & 0xffu;

@@ -199,12 +199,12 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   __shared__ int lds_all[kWavesPerGroup * 512];
   int* lds = lds_all + (threadIdx.x >> 6) * 512;
   const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4, r = lane >> 3, c = lane & 7;
+  const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
+  int64_t t0 = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
+  if (t0 >= P.n_rows) return;  // before any load: launches with few tasks leave many wavefronts idle
   const RoundTrip<ZIGZAG, COLLAPSE, I8> rt(q, g, P.tables);
   const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
   uint8_t* outp = reinterpret_cast<uint8_t*>(P.out);
-  const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
-  int64_t t0 = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
-  if (t0 >= P.n_rows) return;
   TaskRegs tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
   int kk = 0;  // current task: t0 + kk W
   int sy = __builtin_amdgcn_readlane(tr.sy, 0);
@@ -485,11 +485,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_mfma_forward(Params P, const 
   __shared__ int lds_all[kWavesPerGroup * 512];
   int* lds = lds_all + (threadIdx.x >> 6) * 512;
   const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4, r = lane >> 3, c = lane & 7;
-  const FwdConsts f = fwd_consts<FORM>(q, g, P.tables);
-  const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
   const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
   int64_t t0 = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
-  if (t0 >= P.n_rows) return;
+  if (t0 >= P.n_rows) return;  // before any load
+  const FwdConsts f = fwd_consts<FORM>(q, g, P.tables);
+  const uint8_t* in = reinterpret_cast<const uint8_t*>(P.in);
   TaskRegs tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
   int kk = 0;
   int sy = __builtin_amdgcn_readlane(tr.sy, 0);

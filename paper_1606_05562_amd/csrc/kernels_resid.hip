@@ -291,14 +291,14 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_RESID_MIN_WG) void k_mfma_res
   int* lds = lds_all + (threadIdx.x >> 6) * kWaveDw;
   int* lvl = lds + kResWaveLds;  // level staging (interior strips)
   const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4, rr = lane >> 4, cc = lane & 15;
+  const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
+  int64_t t0 = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
+  if (t0 >= P.n_rows) return;  // before any load: launches with few tasks leave many wavefronts idle
   const ResidConsts k = load_resid_consts(lane, P.tables);
   const double cmb[4] = {P.tables->rcomb[0], P.tables->rcomb[1], P.tables->rcomb[2], P.tables->rcomb[3]};
   const float f = P.tables->qoff;
   const int16_t* in = reinterpret_cast<const int16_t*>(P.in);
   int16_t* outp = reinterpret_cast<int16_t*>(P.out);
-  const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
-  int64_t t0 = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
-  if (t0 >= P.n_rows) return;
   TaskRegs tr = gather_tasks(images, rows, t0, W, P.n_rows, lane);
   int kk = 0;
   int sy = __builtin_amdgcn_readlane(tr.sy, 0);
@@ -509,28 +509,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_RESID_MIN_WG) void k_mfma_res
 
 // Per-image SSE and PSNR from 64-bit task partials; a task that saw a
 // sample outside [-256, 255] marks its image (SSE -1, PSNR NaN).
-__global__ __launch_bounds__(64) void k_task_sse_reduce64(Params P) {
-  const int i = blockIdx.x;
-  const int64_t b = P.task_first[i], e = P.task_first[i + 1];
-  unsigned long long v = 0;
-  bool bad = false;
-  for (int64_t t = b + threadIdx.x; t < e; t += 64) {
-    const unsigned long long s = P.task_sse64[t];
-    bad |= s == ~0ull;
-    v += s;
-  }
-  v = wave_sum_u64(v);
-  const bool any_bad = __builtin_amdgcn_ballot_w64(bad) != 0;
-  if (threadIdx.x == 0) {
-    P.sse[i] = any_bad ? ~0ull : v;
-    if (P.psnr) {
-      const ImageDesc& d = P.images[i];
-      P.psnr[i] = any_bad ? __builtin_nan("")
-                          : v == 0 ? __builtin_huge_val()
-                                   : 10.0 * log10(65025.0 * (double)d.h * (double)d.w / (double)v);
-    }
-  }
-}
+__global__ __launch_bounds__(kFinishThreads) void k_task_sse_reduce64(Params P) { finish_image<true>(P); }
 
 #define ADCT16_RLAUNCH(kernel, grid, s, ...)                                            \
   do {                                                                                 \
@@ -567,7 +546,7 @@ hipError_t launch_mfma_resid(int mode, int qout_kind, int out_kind, bool nt, con
 }
 
 hipError_t launch_task_sse_reduce64(const Params& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_task_sse_reduce64, dim3(P.n_images), dim3(64), 0, s, P);
+  hipLaunchKernelGGL(k_task_sse_reduce64, dim3(P.n_images), dim3(kFinishThreads), 0, s, P);
   return hipGetLastError();
 }
 

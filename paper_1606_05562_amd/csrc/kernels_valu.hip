@@ -921,21 +921,8 @@ __global__ __launch_bounds__(64) void k_sse_finalize(Params P, unsigned long lon
 }
 
 // Per-image SSE from the per-task partials of the matrix-core fused kernel
-// (one wavefront per image; an image's tasks are contiguous), and PSNR.
-__global__ __launch_bounds__(64) void k_task_sse_reduce(Params P) {
-  const int i = blockIdx.x;
-  const int64_t b = P.task_first[i], e = P.task_first[i + 1];
-  unsigned long long v = 0;
-  for (int64_t t = b + threadIdx.x; t < e; t += 64) v += P.task_sse[t];
-  v = wave_sum_u64(v);
-  if (threadIdx.x == 0) {
-    P.sse[i] = v;
-    if (P.psnr) {
-      const ImageDesc& d = P.images[i];
-      P.psnr[i] = v == 0 ? __builtin_huge_val() : 10.0 * log10(65025.0 * (double)d.h * (double)d.w / (double)v);
-    }
-  }
-}
+// (one workgroup per image; an image's tasks are contiguous), and PSNR.
+__global__ __launch_bounds__(kFinishThreads) void k_task_sse_reduce(Params P) { finish_image<false>(P); }
 
 // 1-D transforms of int32 vectors of 16.  A wavefront moves 64 vectors
 // (4 KB) per step: each load or store instruction covers 1 KB of
@@ -1017,7 +1004,7 @@ hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
 }
 
 hipError_t launch_task_sse_reduce(const Params& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_task_sse_reduce, dim3(P.n_images), dim3(64), 0, s, P);
+  hipLaunchKernelGGL(k_task_sse_reduce, dim3(P.n_images), dim3(kFinishThreads), 0, s, P);
   return hipGetLastError();
 }
 
