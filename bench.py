@@ -389,7 +389,8 @@ def _luma_variants(args, A, torch, pt, frames):
 
     v = {}
     for name, be, fl in (("valu", A.BACKEND_VALU, 0), ("mfma", A.BACKEND_MFMA, 0),
-                         ("mfma_explicit_coef", A.BACKEND_MFMA, A.FLAG_EXPLICIT_COEF)):
+                         ("mfma_explicit_coef", A.BACKEND_MFMA, A.FLAG_EXPLICIT_COEF),
+                         ("mfma_int8", A.BACKEND_MFMA, A.FLAG_MFMA_INT8)):
         for r in (args.r, 16):
             p2 = make(be, r=r, flags=A.FLAG_AUTOTUNE | fl)
             f = lambda: p2.compress_and_measure(dev, out, None, sse, psnr)

@@ -216,8 +216,9 @@ adct16_status adct16_plan_num_blocks(adct16_plan plan, int64_t *num_blocks);
  *   ADCT16_WG_PER_CU    workgroups per CU of the persistent kernels, 1..64;
  *   ADCT16_TASK_STRIPS  1, 4 or 16, the task table of the matrix-core kernels;
  *   ADCT16_TUNE_CACHE   a file where autotuned choices are kept between
- *                       processes (keyed by device, dtypes, modes and the
- *                       batch's strip count). */
+ *                       processes (keyed by device, dtypes, modes, the
+ *                       batch's strip count and whether its rows are whole
+ *                       128-byte lines). */
 adct16_status adct16_plan_info(adct16_plan plan, char *buf, int32_t buf_len);
 
 /* Measurement of the hot path (the roofline of the persistent kernel):

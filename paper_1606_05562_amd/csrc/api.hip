@@ -397,7 +397,8 @@ std::string tune_key(const adct16_plan_s* p, const char* arch, bool levels) {
     << "/o" << p->out_kind << "/f"
     << (p->d.flags & (ADCT16_FLAG_EXPLICIT_COEF | ADCT16_FLAG_MFMA_INT8 | ADCT16_FLAG_RESIDUAL_RANGE))
     << "/lv" << (levels ? p->qcoef_kind : -1)
-    << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips) << "/v3";
+    << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips) << "/a" << (p->lines_aligned ? 1 : 0)
+    << "/v4";
   return k.str();
 }
 
@@ -479,8 +480,8 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
   if (e != hipSuccess) return hip_fail(e, "autotune set-up");
   // Candidates are timed round-robin, one launch at a time, and each keeps
   // its fastest launch: clocks drift over a few milliseconds of sustained
-  // load, and a sequential sweep would favour whichever ran first (4 to 32
-  // rounds, by the length of a round).
+  // load, and a sequential sweep would favour whichever ran first (8 to 32
+  // rounds, by the length of a round: about 40 ms of timed work).
   // (matrix-core candidates also choose the task size)
   struct Cand { int backend, wgpc, grid, tsel; float best; };
   std::vector<Cand> cands;
@@ -509,7 +510,7 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
     if (e != hipSuccess) return hip_fail(e, "autotune timing");
     warm_ms += pass_ms;
   }
-  const int rounds = std::max(4, std::min(32, (int)(20.0f / std::max(pass_ms, 1e-3f))));
+  const int rounds = std::max(8, std::min(32, (int)(40.0f / std::max(pass_ms, 1e-3f))));
   for (int round = 0; round < rounds; ++round) {
     for (Cand& c : cands) {
       e = hipEventRecord(w.e0, w.s);
