@@ -196,8 +196,14 @@ struct RoundTrip {
 template <bool ZIGZAG, bool COLLAPSE, int OUT, bool NT, bool I8>
 __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fused(
     Params P, const ImageDesc* __restrict__ images, const RowTask* __restrict__ rows) {
-  __shared__ int lds_all[kWavesPerGroup * 512];
-  int* lds = lds_all + (threadIdx.x >> 6) * 512;
+  // rows that are not whole cache lines (NT false) keep two strips' areas:
+  // the line-aligned stores below combine a strip's output with the
+  // previous strip's
+  constexpr bool REALIGN = !NT && OUT == OUT_U8;
+  constexpr int kAreas = REALIGN ? 2 : 1;
+  __shared__ int lds_all[kWavesPerGroup * 512 * kAreas];
+  int* const lds_w = lds_all + (threadIdx.x >> 6) * 512 * kAreas;
+  int* lds = lds_w;
   const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4, r = lane >> 3, c = lane & 7;
   const int64_t W = (int64_t)gridDim.x * kWavesPerGroup;
   int64_t t0 = (int64_t)blockIdx.x * kWavesPerGroup + uniform_int(threadIdx.x >> 6);
@@ -212,6 +218,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   int sxi = task_run_first(run0);
   ImgGeom d = task_geom(tr, 0);
   int sxe = min(sxi + task_run_count(run0), d.sx);  // end of the current task
+  int sxf = sxi;                                     // first strip of the current task
   auto interior = [](const ImgGeom& dd, int ssy, int ssxi) {
     return (ssxi + 1) * (16 * kStripBlocks) <= dd.w && ssy * 16 + 16 <= dd.h;
   };
@@ -240,7 +247,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   for (;;) {
     // the strip after this one
     const bool task_end = sxi + 1 == sxe;
-    int nsy = sy, nsxi = sxi + 1, nsxe = sxe;
+    int nsy = sy, nsxi = sxi + 1, nsxe = sxe, nsxf = sxf;
     ImgGeom nd = d;
     bool more = true;
     if (task_end) {
@@ -254,6 +261,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
         nsy = __builtin_amdgcn_readlane(tr.sy, kk);
         const int nrun = __builtin_amdgcn_readlane(tr.run, kk);
         nsxi = task_run_first(nrun);
+        nsxf = nsxi;
         nd = task_geom(tr, kk);
         nsxe = min(nsxi + task_run_count(nrun), nd.sx);
       }
@@ -267,11 +275,67 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
         nr[1] = ld_row16<NT>(in + lane_off(nd, nsy, nsxi, 1));
       }
     };
+    int* const prev_area = lds;
+    if constexpr (REALIGN) lds = lds_w + 512 * (lds == lds_w ? 1 : 0);  // this strip's area
     if (interior(d, sy, sxi)) {
       prefetch();
       unsigned x[kStripBlocks], out[kStripBlocks];
       rt.run(lds, r, c, g, q, cr, x, out);
-      if constexpr (OUT == OUT_U8) {
+      if constexpr (REALIGN) {
+        // Rows that are not whole cache lines: a strip's 128-byte row piece
+        // straddles two lines, and storing the pieces as they lie leaves
+        // every line written in two parts (by this strip and the next),
+        // which HBM serves far slower.  Instead each lane writes one
+        // 16-byte chunk of a whole aligned line: the line where this
+        // strip's piece begins takes its first s chunks (s = the row's
+        // offset in the line, in chunks) from the previous strip of the run
+        // and the rest from this one; after the run's last interior strip
+        // the line it ends in takes that strip's last s chunks.  Stores are
+        // unconditional buffer stores, chunks that are not this run's get an
+        // offset past the buffer range (the hardware drops them), so that
+        // exactly two or four stores follow the prefetch loads.
+        int4* p = reinterpret_cast<int4*>(lds + g * 128 + q * kStripBlocks);
+        p[0] = make_int4((int)out[0], (int)out[1], (int)out[2], (int)out[3]);
+        p[1] = make_int4((int)out[4], (int)out[5], (int)out[6], (int)out[7]);
+        wave_lds_sync();
+        const bool first_in_run = sxi == sxf;
+        const bool tail = task_end || !interior(d, sy, sxi + 1);
+        // buffer range: the strip row's 16 rows, from one line before its
+        // first row (a line may begin before its row)
+        const int64_t row0 = d.offset + (int64_t)sy * 16 * d.pitch;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(outp + row0 - 128, 0, 16 * d.pitch + 256, 0x00020000);
+        constexpr unsigned kOffNone = 0x80000000u;  // past the range: dropped
+        v4u tl[2];
+        unsigned toff[2];
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int rho = 8 * hh + r;
+          const int64_t rowb = (int64_t)rho * d.pitch;                 // row start, from row0
+          // chunks of the row's first cache line before the row starts
+          const int sh = (int)((((uintptr_t)outp + (uint64_t)(row0 + rowb)) & 127) >> 4);
+          const int64_t line = rowb + 128 * sxi - 16 * sh;              // this strip's first line, from row0
+          const int i0 = rho * kStripBlocks;
+          // chunk c of the line: this strip's chunk c - sh, or the previous strip's chunk c + 8 - sh
+          const bool own = c >= sh;
+          const int* src = own ? lds + i0 + (c - sh) : prev_area + i0 + (c + 8 - sh);
+          const v4u v = {(unsigned)src[0], (unsigned)src[128], (unsigned)src[256], (unsigned)src[384]};
+          const unsigned off = (own || !first_in_run) ? (unsigned)(line + 128 + 16 * c) : kOffNone;
+          __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, 0);
+          // the line this strip ends in: its chunks c < sh are this strip's last
+          const int* t = lds + i0 + ((c + 8 - sh) & 7);
+          tl[hh] = v4u{(unsigned)t[0], (unsigned)t[128], (unsigned)t[256], (unsigned)t[384]};
+          toff[hh] = c < sh ? (unsigned)(line + 256 + 16 * c) : kOffNone;
+        }
+        if (tail) {
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) __builtin_amdgcn_raw_buffer_store_b128(tl[hh], rs, toff[hh], 0, 0);
+        }
+        // the prefetched rows were issued before these stores: vmcnt(2)
+        // completes them (with the tail's two stores it also waits for the
+        // first two, which is correct)
+        __builtin_amdgcn_s_waitcnt(0x0F72);
+      } else if constexpr (OUT == OUT_U8) {
         uint4 orow[2];
         operands_to_rows(lds, r, c, g, q, out, orow);
         st_row16<NT>(outp + lane_off(d, sy, sxi, 0), orow[0]);
@@ -346,6 +410,7 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
     sy = nsy;
     sxi = nsxi;
     sxe = nsxe;
+    sxf = nsxf;
     d = nd;
   }
 }

@@ -421,3 +421,35 @@ def test_mfma_forward_i16_bit_exact(monkeypatch, align, strips):
         want = codec.forward_image(im)
         assert np.array_equal(coefs[mod.BACKEND_MFMA][i].astype(np.int64), want), f"image {i} {im.shape}"
         assert np.array_equal(coefs[mod.BACKEND_MFMA][i], coefs[mod.BACKEND_VALU][i])
+
+
+@pytest.mark.parametrize("strips", [1, 4, 16])
+def test_mfma_unaligned_rows_line_stores(monkeypatch, strips):
+    """Rows at 16-byte pitches and offsets (not whole cache lines): the
+    strip kernel writes whole aligned lines, each from two consecutive strips
+    of a run plus a tail after the run's last interior strip.  Every image
+    byte equals the oracle's, and no byte outside the images (row padding,
+    gaps between images) is written.  Widths give every shift of a row in its
+    line, runs of 1 to 16 strips, and edge strips after interior ones."""
+    monkeypatch.setenv("ADCT16_TASK_STRIPS", str(strips))
+    T = torch()
+    sizes = [(48, 1040), (33, 2050), (16, 2048), (40, 1936), (17, 1000), (64, 3856), (20, 272), (32, 128)]
+    ims = [mixed_image(BASE_SEED + 9, k, h, w) for k, (h, w) in enumerate(sizes)]
+    b = Batch(ims, 16)
+    fill = 0xA5
+    plan = b.plan(coef_dtype=A().I32, qmode=A().Q_ZONAL, r=6, backend=A().BACKEND_MFMA)
+    import json
+    info = json.loads(plan.info())
+    assert info["rows_line_aligned"] is False and info["task_strips"] == strips
+    out = b.empty_like_images(np.uint8, fill)
+    sse = T.zeros(len(ims), dtype=T.int64, device="cuda")
+    plan.compress_and_measure(b.dev, out, None, sse, None)
+    T.cuda.synchronize()
+    flat = out.cpu().numpy()
+    inside = np.zeros(len(flat), dtype=bool)
+    for i, (im, h, w, p, o) in enumerate(zip(ims, b.h, b.w, b.p, b.o)):
+        want, s, _ = codec.compress_kept(im, codec.mask_zonal(6))
+        got = flat[o:o + h * p].reshape(h, p)[:, :w]
+        assert np.array_equal(got, want) and int(sse[i]) == s, f"image {i} {sizes[i]}"
+        inside[o:o + h * p].reshape(h, p)[:, :w] = True
+    assert np.all(flat[~inside] == fill)
