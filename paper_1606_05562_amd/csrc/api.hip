@@ -196,9 +196,10 @@ struct adct16_plan_s {
   int64_t n_blocks = 0, n_strips = 0;
   ImageDesc* d_images = nullptr;
   Tables* d_tables = nullptr;
-  // Task tables of the matrix-core kernels: [0] 4-strip, [1] 16-strip and
-  // [2] 1-strip tasks (the last for launches with few strips per wavefront,
-  // where the latency of a wavefront's last task sets the launch time).
+  // Task tables of the matrix-core kernels: [0] 4-strip, [1] 16-strip, [2]
+  // 1-strip and [3] 2-strip tasks (the short ones for launches with few
+  // strips per wavefront, where the latency of a wavefront's last task sets
+  // the launch time).
   struct TaskTable {
     RowTask* d_rows = nullptr;
     int64_t* d_first = nullptr;  // each image's first task, n_images + 1 entries
@@ -398,7 +399,7 @@ std::string tune_key(const adct16_plan_s* p, const char* arch, bool levels) {
     << (p->d.flags & (ADCT16_FLAG_EXPLICIT_COEF | ADCT16_FLAG_MFMA_INT8 | ADCT16_FLAG_RESIDUAL_RANGE))
     << "/lv" << (levels ? p->qcoef_kind : -1)
     << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips) << "/a" << (p->lines_aligned ? 1 : 0)
-    << "/v4";
+    << "/v5";
   return k.str();
 }
 
@@ -739,7 +740,7 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   std::vector<RowTask> rows[kTaskTables];
   std::vector<int64_t> first[kTaskTables];
   for (int ts = 0; ts < kTaskTables; ++ts) {
-    const int n = ts == 0 ? kTaskStripsShort : ts == 1 ? kTaskStripsLong : kTaskStripsUnit;
+    const int n = ts == 0 ? kTaskStripsShort : ts == 1 ? kTaskStripsLong : ts == 2 ? kTaskStripsUnit : kTaskStripsPair;
     p->tasks[ts].strips = n;
     for (size_t i = 0; i < images.size(); ++i) {
       first[ts].push_back((int64_t)rows[ts].size());
@@ -793,7 +794,7 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   // autotuner may replace it)
   if (const char* env = getenv("ADCT16_TASK_STRIPS")) {
     const int n = atoi(env);
-    p->task_sel = n >= kTaskStripsLong ? 1 : n <= kTaskStripsUnit ? 2 : 0;
+    p->task_sel = n >= kTaskStripsLong ? 1 : n <= kTaskStripsUnit ? 2 : n == kTaskStripsPair ? 3 : 0;
   }
   if (d->backend == ADCT16_BACKEND_MFMA && !mfma_supported(p) && !mfma_forward_supported(p)) {
     adct16_plan_destroy(p);
