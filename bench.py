@@ -62,6 +62,8 @@ def _parse():
                     help="rd workload: one QP instead of all four")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="residual workload: the one-launch calls only (no per-frame graphs)")
     ap.add_argument("--cpu-frames", type=int, default=64)
     ap.add_argument("--no-c2", action="store_true", help="target workload: skip the 1920x1088 batch")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -596,28 +598,29 @@ def bench_residual(args, A, torch):
     reps = max(10, args.steps)
     for q in qs:
         for form in forms:
-            # per-frame graphs
-            keep, graphs = [], []
-            for buf, hs, ws, ps, offs in bufs:
-                dev = torch.from_numpy(buf).cuda()
-                rec = torch.empty_like(dev)
-                plan = _resid_plan(A, hs, ws, ps, offs, q, form)
-                lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
-                sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
-                psnr = torch.zeros(len(hs), dtype=torch.float64, device="cuda")
-                graphs.append(plan.graph(dev, rec, lv, sse, psnr))
-                keep.append((plan, dev, rec, lv, sse, psnr))
-            run = lambda: [g.launch() for g in graphs]
-            for _ in range(max(3, args.warmup)):
-                run()
-            ms = _events_ms(run, reps, stream)
-            out[f"q{q}_{form}_graphs_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
-            out[f"q{q}_{form}_psnr_y0_db"] = round(float(keep[0][5][0]), 4)
-            out[f"q{q}_{form}_plan"] = json.loads(keep[0][0].info())
-            if form == "mfma" and q == rq:
-                b0 = bufs[0]
-                parity = _resid_parity(planes[:per], *b0[1:], keep[0][2], keep[0][3], keep[0][4], keep[0][0], q)
-            del graphs, keep
+            if not args.no_graphs:
+                # per-frame graphs
+                keep, graphs = [], []
+                for buf, hs, ws, ps, offs in bufs:
+                    dev = torch.from_numpy(buf).cuda()
+                    rec = torch.empty_like(dev)
+                    plan = _resid_plan(A, hs, ws, ps, offs, q, form)
+                    lv = torch.empty(plan.num_blocks * 256, dtype=torch.int16, device="cuda")
+                    sse = torch.zeros(len(hs), dtype=torch.int64, device="cuda")
+                    psnr = torch.zeros(len(hs), dtype=torch.float64, device="cuda")
+                    graphs.append(plan.graph(dev, rec, lv, sse, psnr))
+                    keep.append((plan, dev, rec, lv, sse, psnr))
+                run = lambda: [g.launch() for g in graphs]
+                for _ in range(max(3, args.warmup)):
+                    run()
+                ms = _events_ms(run, reps, stream)
+                out[f"q{q}_{form}_graphs_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
+                out[f"q{q}_{form}_psnr_y0_db"] = round(float(keep[0][5][0]), 4)
+                out[f"q{q}_{form}_plan"] = json.loads(keep[0][0].info())
+                if form == "mfma" and q == rq:
+                    b0 = bufs[0]
+                    parity = _resid_parity(planes[:per], *b0[1:], keep[0][2], keep[0][3], keep[0][4], keep[0][0], q)
+                del graphs, keep
             # the whole stream in one launch
             buf, hs, ws, ps, offs = big
             dev = torch.from_numpy(buf).cuda()
@@ -629,6 +632,11 @@ def bench_residual(args, A, torch):
             f = lambda: plan.compress_and_measure(dev, rec, lv, sse, psnr)
             ms, kt = _timed_fused(plan, f, reps, max(3, args.warmup), stream, torch)
             out[f"q{q}_{form}_one_launch_gsample_s"] = round(npx / (ms * 1e-3) / 1e9, 4)
+            if args.no_graphs:
+                out[f"q{q}_{form}_plan"] = json.loads(plan.info())
+                if form == "mfma" and q == rq:  # frame 0's planes lead the packed stream
+                    parity = _resid_parity(planes[:per], hs[:per], ws[:per], ps[:per], offs[:per], rec, lv, sse,
+                                           plan, q)
             # algorithmic bytes: the int16 samples read once, the int16
             # reconstruction and the int16 levels (256 per block, padded blocks
             # included) written once
@@ -673,8 +681,9 @@ def bench_residual(args, A, torch):
             out[f"forward_{name}_gbs"] = round(6 * npx / (ms * 1e-3) / 1e9, 1)
             del coef
         del dev
-    head = out[f"q{rq}_auto_graphs_gsample_s"]
-    return {"metric": "Gsample/s 2D fwd+quant+inv 16x16, 4:2:0 int16 residual stream, graph per frame",
+    form_name = "one launch" if args.no_graphs else "graph per frame"
+    head = out[f"q{rq}_auto_one_launch_gsample_s" if args.no_graphs else f"q{rq}_auto_graphs_gsample_s"]
+    return {"metric": f"Gsample/s 2D fwd+quant+inv 16x16, 4:2:0 int16 residual stream, {form_name}",
             "value": head, "unit": "Gsample/s", "n_gpus": 1, "steps": reps, "warmup": max(3, args.warmup),
             "ms_per_step": round(npx / (head * 1e9) * 1e3, 4), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None,
@@ -682,7 +691,8 @@ def bench_residual(args, A, torch):
             "data": "synthetic",
             "config": {"workload": f"{nf} frames 3840x2160 4:2:0 int16 residuals (AR(1) frames, per-block motion "
                                    f"+-8), uniform q in {{{','.join(map(str, qs))}}} (value at q = {rq}, autotuned "
-                                   "plan, one HIP graph per frame), levels + reconstruction written, per-plane PSNR",
+                                   f"plan, {'the whole stream in one launch' if args.no_graphs else 'one HIP graph per frame'}), "
+                                   "levels + reconstruction written, per-plane PSNR",
                        "frames": nf, "seed": seed, "per_q": out},
             "roofline": roof, "parity": parity}
 

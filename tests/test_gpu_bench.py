@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 def _args(workload, frames, **kw):
     a = dict(gpus=1, steps=2, warmup=1, workload=workload, r=8, backend="auto", frames=frames,
              no_cpu_baseline=True, no_variants=False, cpu_frames=1, calibrate_copy=False, q=None, qp=None,
-             no_c2=True)
+             no_c2=True, no_graphs=False)
     a.update(kw)
     return argparse.Namespace(**a)
 
@@ -100,6 +100,15 @@ def test_bench_residual_small():
     assert line["parity"]["ok"] is True
     # counters are committed for the full 120-frame stream only
     assert r["traffic"] is None and r["compute"] is None
+
+
+def test_bench_residual_one_launch_only():
+    """--no-graphs: the one-launch calls alone, parity from the one launch."""
+    line = _run("residual", 1, q=16, no_graphs=True)
+    per_q = line["config"]["per_q"]
+    assert "q16_mfma_graphs_gsample_s" not in per_q and "one launch" in line["metric"]
+    assert line["value"] == per_q["q16_auto_one_launch_gsample_s"]
+    assert line["parity"]["ok"] is True and line["roofline"]["kernel"].startswith("k_mfma_resid")
 
 
 def test_bench_residual_one_step_with_copy_calibration():
