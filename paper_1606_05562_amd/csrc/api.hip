@@ -399,7 +399,7 @@ std::string tune_key(const adct16_plan_s* p, const char* arch, bool levels) {
     << (p->d.flags & (ADCT16_FLAG_EXPLICIT_COEF | ADCT16_FLAG_MFMA_INT8 | ADCT16_FLAG_RESIDUAL_RANGE))
     << "/lv" << (levels ? p->qcoef_kind : -1)
     << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips) << "/a" << (p->lines_aligned ? 1 : 0)
-    << "/v5";
+    << "/v6";
   return k.str();
 }
 
@@ -479,19 +479,22 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
   if (e == hipSuccess) e = hipEventCreate(&w.e0);
   if (e == hipSuccess) e = hipEventCreate(&w.e1);
   if (e != hipSuccess) return hip_fail(e, "autotune set-up");
-  // Candidates are timed round-robin, one launch at a time, and each keeps
-  // its fastest launch: clocks drift over a few milliseconds of sustained
-  // load, and a sequential sweep would favour whichever ran first (8 to 32
-  // rounds, by the length of a round: about 40 ms of timed work).
+  // Candidates are timed round-robin, one launch at a time: clocks drift
+  // over a few milliseconds of sustained load, and a sequential sweep would
+  // favour whichever ran first (8 to 32 rounds, by the length of a round:
+  // about 40 ms of timed work).  Each is ranked by the median of its
+  // launches, which tracks sustained throughput; the fastest single launch
+  // picked configurations that won short bursts at a high clock and lost
+  // under sustained load.
   // (matrix-core candidates also choose the task size)
-  struct Cand { int backend, wgpc, grid, tsel; float best; };
+  struct Cand { int backend, wgpc, grid, tsel; std::vector<float> ms; };
   std::vector<Cand> cands;
   const bool mfma_ok = mfma_supported(p) && (!levels || resid_supported(p));
   if (p->d.backend != ADCT16_BACKEND_MFMA || !mfma_ok)
-    for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_VALU, wg, grid_for(p, wg), 0, 1e30f});
+    for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_VALU, wg, grid_for(p, wg), 0, {}});
   if (p->d.backend != ADCT16_BACKEND_VALU && mfma_ok)
     for (int ts = 0; ts < kTaskTables; ++ts)
-      for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_MFMA, wg, grid_for(p, wg), ts, 1e30f});
+      for (int wg : {1, 2, 3, 4, 6, 8, 12}) cands.push_back({ADCT16_BACKEND_MFMA, wg, grid_for(p, wg), ts, {}});
   void* const tout = p->out_kind == OUT_F32 ? nullptr : w.dout;
   // Warm-up (code objects, and the engine clock, which ramps up under load):
   // passes over all candidates until about 20 ms of work has run.  Short
@@ -523,12 +526,16 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
       float ms = 0;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, w.e0, w.e1);
       if (e != hipSuccess) return hip_fail(e, "autotune timing");
-      c.best = std::min(c.best, ms);
+      c.ms.push_back(ms);
     }
   }
   float best = 1e30f;
-  for (const Cand& c : cands)
-    if (c.best < best) { best = c.best; best_b = c.backend; best_w = c.wgpc; best_t = c.tsel; }
+  for (Cand& c : cands) {
+    std::sort(c.ms.begin(), c.ms.end());
+    const size_t n = c.ms.size();
+    const float med = n % 2 ? c.ms[n / 2] : 0.5f * (c.ms[n / 2 - 1] + c.ms[n / 2]);
+    if (med < best) { best = med; best_b = c.backend; best_w = c.wgpc; best_t = c.tsel; }
+  }
   std::ostringstream t;
   t << "timed:" << best_w << "wg/cu";
   how = t.str();
