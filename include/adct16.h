@@ -208,13 +208,13 @@ adct16_status adct16_plan_num_blocks(adct16_plan plan, int64_t *num_blocks);
 /* NUL-terminated JSON describing the chosen kernels: backend of the fused
  * and forward calls, persistent grid (workgroups of 256 threads), the task
  * table of the matrix-core kernels ("task_strips": block rows split into
- * equal runs of at most 1, 2, 4 or 16 strips of 16 x 128 pixels), and how each
+ * equal runs of at most 1, 2, 3, 4 or 16 strips of 16 x 128 pixels), and how each
  * choice was made.  ADCT16_E_SHAPE when buf_len is too small.
  *
  * Launch shapes without ADCT16_FLAG_AUTOTUNE come from defaults, which
  * these environment variables override at plan creation:
  *   ADCT16_WG_PER_CU    workgroups per CU of the persistent kernels, 1..64;
- *   ADCT16_TASK_STRIPS  1, 2, 4 or 16, the task table of the matrix-core kernels;
+ *   ADCT16_TASK_STRIPS  1, 2, 3, 4 or 16, the task table of the matrix-core kernels;
  *   ADCT16_TUNE_CACHE   a file where autotuned choices are kept between
  *                       processes (keyed by device, dtypes, modes, the
  *                       batch's strip count and whether its rows are whole

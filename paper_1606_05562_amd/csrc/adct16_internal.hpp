@@ -46,8 +46,9 @@ static_assert(sizeof(ImageDesc) == 56, "ImageDesc layout");
 // - 1.  Plans hold the tables for N = 4 and N = 16 (whole rows of images up
 // to 2048 pixels wide, two runs of 15 strips for 3840); the autotuner picks.
 // Equal runs keep the wavefronts that share a row in step.
-constexpr int kTaskStripsUnit = 1, kTaskStripsPair = 2, kTaskStripsShort = 4, kTaskStripsLong = 16;
-constexpr int kTaskTables = 4;  // tasks of at most 4, 16, 1 and 2 strips
+constexpr int kTaskStripsUnit = 1, kTaskStripsPair = 2, kTaskStripsTriple = 3, kTaskStripsShort = 4,
+              kTaskStripsLong = 16;
+constexpr int kTaskTables = 5;  // tasks of at most 4, 16, 1, 2 and 3 strips
 struct RowTask {
   int32_t img;
   int16_t sy;
@@ -116,7 +117,7 @@ struct Params {
   uint32_t* task_sse;   // per-task SSE partials (matrix-core fused kernel)
   unsigned long long* task_sse64;  // the same buffer as 64-bit partials (matrix-core residual kernel)
   const int64_t* task_first;  // index of each image's first task (n_images + 1 entries)
-  int32_t task_strips;  // longest run of the task table (4, 16, 1 or 2)
+  int32_t task_strips;  // longest run of the task table (4, 16, 1, 2 or 3)
   int32_t pad1;
 };
 

@@ -197,9 +197,10 @@ struct adct16_plan_s {
   ImageDesc* d_images = nullptr;
   Tables* d_tables = nullptr;
   // Task tables of the matrix-core kernels: [0] 4-strip, [1] 16-strip, [2]
-  // 1-strip and [3] 2-strip tasks (the short ones for launches with few
-  // strips per wavefront, where the latency of a wavefront's last task sets
-  // the launch time).
+  // 1-strip, [3] 2-strip and [4] 3-strip tasks.  The 4 wavefronts of a
+  // workgroup start on 4 consecutive tasks, so short runs put a workgroup on
+  // adjacent stretches of one block row at the same time (which HBM serves
+  // faster), and launches with few strips per wavefront finish sooner.
   struct TaskTable {
     RowTask* d_rows = nullptr;
     int64_t* d_first = nullptr;  // each image's first task, n_images + 1 entries
@@ -399,7 +400,7 @@ std::string tune_key(const adct16_plan_s* p, const char* arch, bool levels) {
     << (p->d.flags & (ADCT16_FLAG_EXPLICIT_COEF | ADCT16_FLAG_MFMA_INT8 | ADCT16_FLAG_RESIDUAL_RANGE))
     << "/lv" << (levels ? p->qcoef_kind : -1)
     << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips) << "/a" << (p->lines_aligned ? 1 : 0)
-    << "/v6";
+    << "/v7";
   return k.str();
 }
 
@@ -747,7 +748,11 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   std::vector<RowTask> rows[kTaskTables];
   std::vector<int64_t> first[kTaskTables];
   for (int ts = 0; ts < kTaskTables; ++ts) {
-    const int n = ts == 0 ? kTaskStripsShort : ts == 1 ? kTaskStripsLong : ts == 2 ? kTaskStripsUnit : kTaskStripsPair;
+    const int n = ts == 0   ? kTaskStripsShort
+                  : ts == 1 ? kTaskStripsLong
+                  : ts == 2 ? kTaskStripsUnit
+                  : ts == 3 ? kTaskStripsPair
+                            : kTaskStripsTriple;
     p->tasks[ts].strips = n;
     for (size_t i = 0; i < images.size(); ++i) {
       first[ts].push_back((int64_t)rows[ts].size());
@@ -801,7 +806,7 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   // autotuner may replace it)
   if (const char* env = getenv("ADCT16_TASK_STRIPS")) {
     const int n = atoi(env);
-    p->task_sel = n >= kTaskStripsLong ? 1 : n <= kTaskStripsUnit ? 2 : n == kTaskStripsPair ? 3 : 0;
+    p->task_sel = n >= kTaskStripsLong ? 1 : n <= kTaskStripsUnit ? 2 : n == kTaskStripsPair ? 3 : n == kTaskStripsTriple ? 4 : 0;
   }
   if (d->backend == ADCT16_BACKEND_MFMA && !mfma_supported(p) && !mfma_forward_supported(p)) {
     adct16_plan_destroy(p);

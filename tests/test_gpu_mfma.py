@@ -235,9 +235,9 @@ def test_mfma_ragged(align):
         assert np.array_equal(got, want) and sse[i] == s
 
 
-@pytest.mark.parametrize("strips", [1, 2, 4, 16])
+@pytest.mark.parametrize("strips", [1, 2, 3, 4, 16])
 def test_mfma_task_sizes(monkeypatch, strips):
-    """The task tables (equal runs of at most 1, 2, 4 or 16 strips of a block
+    """The task tables (equal runs of at most 1, 2, 3, 4 or 16 strips of a block
     row), on images whose block rows hold fewer and more strips than a run
     and split into runs of unequal length (2050 pixels: 17 strips, 8 + 9 or
     3 + 3 + 4 + 3 + 4), through the fused kernel and both forward forms."""
@@ -423,7 +423,7 @@ def test_mfma_forward_i16_bit_exact(monkeypatch, align, strips):
         assert np.array_equal(coefs[mod.BACKEND_MFMA][i], coefs[mod.BACKEND_VALU][i])
 
 
-@pytest.mark.parametrize("strips", [1, 2, 4, 16])
+@pytest.mark.parametrize("strips", [1, 2, 3, 4, 16])
 def test_mfma_unaligned_rows_line_stores(monkeypatch, strips):
     """Rows at 16-byte pitches and offsets (not whole cache lines): the
     strip kernel writes whole aligned lines, each from two consecutive strips

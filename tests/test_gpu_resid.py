@@ -107,9 +107,9 @@ def test_resid_mfma_uniform_against_oracle(batch_res, q):
         _check_recon(got, real, im, sse[i], psnr[i], want_rec)
 
 
-@pytest.mark.parametrize("strips", [1, 2, 4, 16])
+@pytest.mark.parametrize("strips", [1, 2, 3, 4, 16])
 def test_resid_mfma_task_sizes(monkeypatch, batch_res, strips):
-    """The task tables (runs of at most 1, 2, 4 or 16 strips)."""
+    """The task tables (runs of at most 1, 2, 3, 4 or 16 strips)."""
     monkeypatch.setenv("ADCT16_TASK_STRIPS", str(strips))
     recs, lvs, sse, psnr, info = _run(batch_res, A().BACKEND_MFMA, A().Q_UNIFORM, 16, A().FLAG_RESIDUAL_RANGE)
     assert info["levels_backend"] == "mfma" and info["levels_task_strips"] == strips
