@@ -122,7 +122,8 @@ enum {
                                     difference of two 8-bit samples, Section 5.3's residual
                                     planes).  With the MFMA backend (or AUTO with
                                     ADCT16_FLAG_AUTOTUNE), a uniform step q >= 8 or a
-                                    deadzone QP >= 22, and I16 out_dtype, the fused call
+                                    deadzone QP >= 22, I16 out_dtype, and every image below
+                                    2^31 bytes with rows below 2^24 bytes, the fused call
                                     (with or without levels) runs on the matrix cores:
                                     exact FP16 products with FP32 accumulation for the
                                     forward and four integer partial inverses, combined per

@@ -213,6 +213,7 @@ struct adct16_plan_s {
   int64_t* d_ssim_tiles = nullptr;  // SSIM: first tile of each image (n_images + 1 entries)
   int64_t n_ssim_tiles = 0;
   bool lines_aligned = false;       // every pitch and image offset a multiple of 128 bytes
+  bool small_images = false;        // every image below 2^31 bytes, every row below 2^24 bytes
   int mat = MAT_APPROX;             // integer matrix of the transform (T or Walsh-Hadamard)
   // n_images x sse_slots accumulators of the vector kernels, zero between
   // calls (cleared at creation, and by the finishing kernel of every call)
@@ -369,12 +370,13 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, c
 
 // The matrix-core fused kernels cover 8-bit input with retention masks, and
 // 16-bit residuals in [-256, 255] (declared by ADCT16_FLAG_RESIDUAL_RANGE)
-// with a quantiser step of at least 8 (levels output included); the
+// with a quantiser step of at least 8 (levels output included) in images
+// below 2 GiB with rows below 16 MiB (32-bit sample offsets); the
 // matrix-core forward covers 8-bit input to int32 or centred int16
 // coefficients, and 16-bit input to int32.
 bool resid_supported(const adct16_plan_s* p) {
   return p->in_kind == IN_I16 && p->mat == MAT_APPROX && (p->d.flags & ADCT16_FLAG_RESIDUAL_RANGE) &&
-         p->out_kind == OUT_I16 &&
+         p->out_kind == OUT_I16 && p->small_images &&
          ((p->mode == MODE_UNIFORM && p->d.q >= 8) || (p->mode == MODE_DEADZONE && p->d.q >= 22));
 }
 
@@ -671,8 +673,12 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   p->n_blocks = blocks;
   p->n_strips = strips;
   p->lines_aligned = true;
-  for (const ImageDesc& g : images)
+  p->small_images = true;
+  for (const ImageDesc& g : images) {
     if (((int64_t)g.pitch * es) % 128 || (g.offset * es) % 128) p->lines_aligned = false;
+    if ((int64_t)g.pitch * es >= ((int64_t)1 << 24) || (int64_t)g.h * g.pitch * es >= ((int64_t)1 << 31))
+      p->small_images = false;
+  }
 
   // the integer matrix, its squared row norms n_u and the weights 48 / n_u
   p->mat = d->matrix == ADCT16_MATRIX_WHT ? MAT_WHT : MAT_APPROX;
@@ -802,8 +808,8 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   int wgpc = 4;
   if (const char* env = getenv("ADCT16_WG_PER_CU")) wgpc = std::max(1, std::min(64, atoi(env)));
   p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)p->cu_count * wgpc, max_groups));
-  // task size of the matrix-core kernels (ADCT16_TASK_STRIPS = 4 or 16 overrides the default 4; the
-  // autotuner may replace it)
+  // task size of the matrix-core kernels (ADCT16_TASK_STRIPS = 1, 2, 3, 4 or 16 overrides the
+  // default 4; the autotuner may replace it)
   if (const char* env = getenv("ADCT16_TASK_STRIPS")) {
     const int n = atoi(env);
     p->task_sel = n >= kTaskStripsLong ? 1 : n <= kTaskStripsUnit ? 2 : n == kTaskStripsPair ? 3 : n == kTaskStripsTriple ? 4 : 0;
@@ -812,7 +818,8 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
     adct16_plan_destroy(p);
     return fail(ADCT16_E_MODE,
                 "MFMA backend supports U8 input with retention modes and U8 output, or I16 residuals with "
-                "ADCT16_FLAG_RESIDUAL_RANGE, a step of at least 8 and I16 output (fused call), or U8 input to "
+                "ADCT16_FLAG_RESIDUAL_RANGE, a step of at least 8, I16 output and images below 2 GiB with rows "
+                "below 16 MiB (fused call), or U8 input to "
                 "I32/I16 coefficients and I16 input to I32 coefficients (forward)");
   }
   p->grid_lv = p->grid;

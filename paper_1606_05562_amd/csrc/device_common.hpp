@@ -318,10 +318,16 @@ __device__ __forceinline__ unsigned wave_sum_u32(unsigned v) {
   return __builtin_amdgcn_readlane(v, 63);
 }
 
+// Sum of a 64-bit value over the 64 lanes, modulo 2^64 like the plain sum:
+// its 24-, 24- and 16-bit digits are summed separately (64 digits of 24 bits
+// stay below 2^30, so no digit sum carries out of 32 bits) and recombined
+// in scalars.  Three DPP reductions instead of six rounds of lane exchange
+// through LDS.
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
+  const unsigned long long d0 = wave_sum_u32((unsigned)v & 0xFFFFFFu);
+  const unsigned long long d1 = wave_sum_u32((unsigned)(v >> 24) & 0xFFFFFFu);
+  const unsigned long long d2 = wave_sum_u32((unsigned)(v >> 48));
+  return d0 + (d1 << 24) + (d2 << 48);
 }
 
 // SSE and PSNR of image blockIdx.x from its task partials (a workgroup of

@@ -313,16 +313,20 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_RESID_MIN_WG) void k_mfma_res
   // 16 ssy + 4i + rr, samples 8 cc .. 8 cc + 7, clamped into the image: rows
   // past the height read the last row, and a block past the last reads the
   // same half of block 0 (computed on, neither stored nor counted).  Every
-  // address lies inside the image, so the loads are unconditional.
-  auto lane_src = [&](const ImgGeom& dd, int ssy, int ssxi, int i) {
+  // address lies inside the image, so the loads are unconditional.  The
+  // offset is in bytes from the image's first sample: the plan admits this
+  // kernel only for images below 2^31 bytes with rows below 2^24 bytes, so
+  // one 24-bit multiply-add forms it, against a uniform 64-bit base.
+  auto lane_off = [&](const ImgGeom& dd, int ssy, int ssxi, int i) -> unsigned {
     const int y = min(ssy * 16 + 4 * i + rr, dd.h - 1);
     const int blk = ssxi * kStripBlocks + (cc >> 1);
     const int col = (blk < dd.bx ? 16 * blk : 0) + 8 * (cc & 1);
-    return dd.offset + (int64_t)y * dd.pitch + col;
+    return __umul24((unsigned)y, 2u * (unsigned)dd.pitch) + 2u * (unsigned)col;
   };
   auto load4 = [&](const ImgGeom& dd, int ssy, int ssxi, uint4 (&v)[4]) {
+    const uint8_t* base = reinterpret_cast<const uint8_t*>(in + dd.offset);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = ld_row16<NT>(reinterpret_cast<const uint8_t*>(in + lane_src(dd, ssy, ssxi, i)));
+    for (int i = 0; i < 4; ++i) v[i] = ld_row16<NT>(base + lane_off(dd, ssy, ssxi, i));
   };
   // LDS rows of a strip: lane (rr, cc) writes its 16 bytes of rows 4i + rr.
   // Called right after an explicit vmcnt(0): the empty asm statements mark
@@ -445,10 +449,12 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_RESID_MIN_WG) void k_mfma_res
     }
     rows_to_lds(nr);
     if (inner) {
-      if constexpr (OUT == OUT_I16) {
-        const int64_t o = d.offset + (int64_t)(sy * 16 + rr) * d.pitch + sxi * (16 * kStripBlocks) + 8 * cc;
+      if constexpr (OUT == OUT_I16) {  // byte offsets from the image's first sample, as for the loads
+        uint8_t* base = reinterpret_cast<uint8_t*>(outp + d.offset);
+        const unsigned pb = 2u * (unsigned)d.pitch;
+        const unsigned o = __umul24((unsigned)(sy * 16 + rr), pb) + 2u * (unsigned)(sxi * (16 * kStripBlocks) + 8 * cc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) st_row16<NT>(reinterpret_cast<uint8_t*>(outp + o + 4 * i * (int64_t)d.pitch), orow[i]);
+        for (int i = 0; i < 4; ++i) st_row16<NT>(base + o + 4u * i * pb, orow[i]);
       }
       if constexpr (QOUT != CF_NONE) {
 #pragma unroll
