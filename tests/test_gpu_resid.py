@@ -212,6 +212,23 @@ def test_resid_requires_flag_and_step():
         assert info["fused_backend"] == "valu" and info["levels_backend"] == "valu"
 
 
+def test_resid_mfma_needs_32bit_offsets():
+    """The matrix-core kernel addresses samples by 32-bit byte offsets from
+    the image start: plans whose images reach 2^31 bytes, or whose rows
+    reach 2^24 bytes, keep the vector kernel for the fused call (geometry
+    only; nothing is launched)."""
+    mod = A()
+    def levels_backend(h, pitch):
+        plan = mod.Plan([h], [64], [pitch], [0], in_dtype=mod.I16, coef_dtype=mod.I32, qmode=mod.Q_UNIFORM, q=16,
+                        qcoef_dtype=mod.I16, out_dtype=mod.I16, backend=mod.BACKEND_MFMA,
+                        flags=mod.FLAG_RESIDUAL_RANGE)
+        return json.loads(plan.info())["levels_backend"]
+    assert levels_backend(16, (1 << 23) - 64) == "mfma"    # rows just below 16 MiB
+    assert levels_backend(16, 1 << 23) == "valu"           # 16 MiB rows
+    assert levels_backend(1023, 1 << 20) == "mfma"         # just below 2 GiB
+    assert levels_backend(1024, 1 << 20) == "valu"         # 2 GiB
+
+
 def test_resid_graph_replays_match_eager():
     T = torch()
     mod = A()
