@@ -94,8 +94,9 @@ typedef enum adct16_backend {
   ADCT16_BACKEND_VALU = 1,  /* 60-addition butterflies of Eq. (1) on the vector ALUs */
   ADCT16_BACKEND_MFMA = 2   /* T as a dense {0,+1,-1} operand of FP16 matrix-core products,
                                every product and sum exact; used by adct16_forward and by
-                               the fused call for U8 input, mask modes, U8 (or no) output
-                               and no d_qcoef; other cases run the VALU kernels */
+                               the fused call for U8 input, mask modes, U8 (or no) output,
+                               no d_qcoef and every image below 2^31 bytes with rows below
+                               2^24 bytes; other cases run the VALU kernels */
 } adct16_backend;
 
 enum {

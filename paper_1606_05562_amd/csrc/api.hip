@@ -370,8 +370,9 @@ adct16_status compress_impl(adct16_plan_s* p, int backend, int grid, int tsel, c
 
 // The matrix-core fused kernels cover 8-bit input with retention masks, and
 // 16-bit residuals in [-256, 255] (declared by ADCT16_FLAG_RESIDUAL_RANGE)
-// with a quantiser step of at least 8 (levels output included) in images
-// below 2 GiB with rows below 16 MiB (32-bit sample offsets); the
+// with a quantiser step of at least 8 (levels output included), in images
+// below 2 GiB with rows below 16 MiB (32-bit offsets within an image or a
+// strip row); the
 // matrix-core forward covers 8-bit input to int32 or centred int16
 // coefficients, and 16-bit input to int32.
 bool resid_supported(const adct16_plan_s* p) {
@@ -381,7 +382,8 @@ bool resid_supported(const adct16_plan_s* p) {
 }
 
 bool mfma_supported(const adct16_plan_s* p) {
-  return (p->in_kind == IN_U8 && p->mode == MODE_MASK && p->out_kind == OUT_U8) || resid_supported(p);
+  return (p->in_kind == IN_U8 && p->mode == MODE_MASK && p->out_kind == OUT_U8 && p->small_images) ||
+         resid_supported(p);
 }
 
 bool mfma_forward_supported(const adct16_plan_s* p) {
@@ -402,7 +404,7 @@ std::string tune_key(const adct16_plan_s* p, const char* arch, bool levels) {
     << (p->d.flags & (ADCT16_FLAG_EXPLICIT_COEF | ADCT16_FLAG_MFMA_INT8 | ADCT16_FLAG_RESIDUAL_RANGE))
     << "/lv" << (levels ? p->qcoef_kind : -1)
     << "/strips" << (p->n_strips >= (1 << 16) ? 1 << 16 : p->n_strips) << "/a" << (p->lines_aligned ? 1 : 0)
-    << "/v7";
+    << "/v8";
   return k.str();
 }
 
@@ -817,10 +819,10 @@ adct16_status adct16_plan_create(const adct16_desc* d, adct16_plan* out) {
   if (d->backend == ADCT16_BACKEND_MFMA && !mfma_supported(p) && !mfma_forward_supported(p)) {
     adct16_plan_destroy(p);
     return fail(ADCT16_E_MODE,
-                "MFMA backend supports U8 input with retention modes and U8 output, or I16 residuals with "
-                "ADCT16_FLAG_RESIDUAL_RANGE, a step of at least 8, I16 output and images below 2 GiB with rows "
-                "below 16 MiB (fused call), or U8 input to "
-                "I32/I16 coefficients and I16 input to I32 coefficients (forward)");
+                "MFMA backend supports, for images below 2 GiB with rows below 16 MiB, U8 input with retention "
+                "modes and U8 output, or I16 residuals with ADCT16_FLAG_RESIDUAL_RANGE, a step of at least 8 "
+                "and I16 output (fused call); or U8 input to I32/I16 coefficients and I16 input to I32 "
+                "coefficients (forward)");
   }
   p->grid_lv = p->grid;
   p->task_sel_lv = p->task_sel;

@@ -423,6 +423,23 @@ def test_mfma_forward_i16_bit_exact(monkeypatch, align, strips):
         assert np.array_equal(coefs[mod.BACKEND_MFMA][i], coefs[mod.BACKEND_VALU][i])
 
 
+def test_mfma_fused_needs_32bit_offsets():
+    """The line stores of the strip kernel address a strip row through a
+    32-bit buffer range: plans whose images reach 2^31 bytes, or whose rows
+    reach 2^24 bytes, keep the vector kernel for the fused call (geometry
+    only; nothing is launched)."""
+    import json
+    mod = A()
+    def fused_backend(h, pitch):
+        plan = mod.Plan([h], [64], [pitch], [0], in_dtype=mod.U8, coef_dtype=mod.I32, qmode=mod.Q_ZONAL, r=8,
+                        backend=mod.BACKEND_MFMA)
+        return json.loads(plan.info())["fused_backend"]
+    assert fused_backend(16, (1 << 24) - 128) == "mfma"    # rows just below 16 MiB
+    assert fused_backend(16, 1 << 24) == "valu"            # 16 MiB rows
+    assert fused_backend(16383, 1 << 17) == "mfma"         # just below 2 GiB
+    assert fused_backend(16384, 1 << 17) == "valu"         # 2 GiB
+
+
 @pytest.mark.parametrize("strips", [1, 2, 3, 4, 16])
 def test_mfma_unaligned_rows_line_stores(monkeypatch, strips):
     """Rows at 16-byte pitches and offsets (not whole cache lines): the
