@@ -486,8 +486,8 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
   if (e != hipSuccess) return hip_fail(e, "autotune set-up");
   // Candidates are timed round-robin, one launch at a time: clocks drift
   // over a few milliseconds of sustained load, and a sequential sweep would
-  // favour whichever ran first (8 to 32 rounds, by the length of a round:
-  // about 40 ms of timed work).  Each is ranked by the median of its
+  // favour whichever ran first (12 to 64 rounds, by the length of a round:
+  // about 80 ms of timed work).  Each is ranked by the median of its
   // launches, which tracks sustained throughput; the fastest single launch
   // picked configurations that won short bursts at a high clock and lost
   // under sustained load.
@@ -503,8 +503,8 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
   void* const tout = p->out_kind == OUT_F32 ? nullptr : w.dout;
   // Warm-up (code objects, and the engine clock, which ramps up under load):
   // passes over all candidates until about 20 ms of work has run.  Short
-  // launches then also get more timed rounds, so that every candidate is
-  // sampled over about 20 ms of sustained load.
+  // launches then get more timed rounds, so that the timed rounds cover
+  // about 80 ms of sustained load.
   float warm_ms = 0, pass_ms = 0;
   for (int pass = 0; pass < 64 && warm_ms < 20.0f; ++pass) {
     e = hipEventRecord(w.e0, w.s);
@@ -519,7 +519,7 @@ adct16_status tune_shape(adct16_plan_s* p, const char* arch, bool levels, int& b
     if (e != hipSuccess) return hip_fail(e, "autotune timing");
     warm_ms += pass_ms;
   }
-  const int rounds = std::max(8, std::min(32, (int)(40.0f / std::max(pass_ms, 1e-3f))));
+  const int rounds = std::max(12, std::min(64, (int)(80.0f / std::max(pass_ms, 1e-3f))));
   for (int round = 0; round < rounds; ++round) {
     for (Cand& c : cands) {
       e = hipEventRecord(w.e0, w.s);
