@@ -87,12 +87,13 @@ def test_bench_residual_small():
     for q in (8, 16, 32):
         for form in ("auto", "mfma", "valu"):
             assert _positive(per_q[f"q{q}_{form}_graphs_gsample_s"])
+            assert _positive(per_q[f"q{q}_{form}_calls_gsample_s"])
             assert _positive(per_q[f"q{q}_{form}_one_launch_gsample_s"])
         assert per_q[f"q{q}_mfma_plan"]["levels_backend"] == "mfma"
         assert per_q[f"q{q}_valu_plan"]["levels_backend"] == "valu"
         assert per_q[f"q{q}_auto_plan"]["levels_backend"] in ("mfma", "valu")
     # the headline is the autotuned plan's, and names the arithmetic it ran
-    assert line["value"] == per_q["q16_auto_graphs_gsample_s"]
+    assert line["value"] == per_q["q16_auto_calls_gsample_s"] and "one call per frame" in line["metric"]
     assert ("MFMA" in line["dtype"]) == (per_q["q16_auto_plan"]["levels_backend"] == "mfma")
     r = line["roofline"]
     assert r["bound"] == "hbm" and _positive(r["achieved"]) and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
@@ -115,7 +116,7 @@ def test_bench_residual_one_step_with_copy_calibration():
     line = _run("residual", 1, q=8, calibrate_copy=True)
     per_q = line["config"]["per_q"]
     assert _positive(per_q["q8_mfma_graphs_gsample_s"]) and "q16_mfma_graphs_gsample_s" not in per_q
-    assert line["value"] == per_q["q8_auto_graphs_gsample_s"]
+    assert line["value"] == per_q["q8_auto_calls_gsample_s"]
     r = line["roofline"]
     assert "q = 8" in r["timing"] and r["calibration_copy_bytes"] > 0
 
