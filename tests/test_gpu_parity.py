@@ -390,6 +390,42 @@ def test_graph_replays_match_eager(batch_u8):
     g.close()
 
 
+@pytest.mark.parametrize("n_images", [1, 3, 16, 17])
+def test_valu_repeated_calls_and_replays(n_images):
+    """The vector fused kernel accumulates SSE in per-image slots that the
+    finishing kernel sums and clears: repeated calls and graph replays give
+    the oracle's reconstruction, SSE and PSNR every time."""
+    T = torch()
+    ims = [mixed_image(BASE_SEED + 11, k, 40 + 8 * (k % 3), 72 + 16 * (k % 4)) for k in range(n_images)]
+    b = Batch(ims, 16)
+    plan = b.plan(coef_dtype=A().I32, qmode=A().Q_ZONAL, r=5, backend=A().BACKEND_VALU)
+    want = [codec.compress_kept(im, codec.mask_zonal(5)) for im in ims]
+    out = b.empty_like_images(np.uint8)
+    sse = T.zeros(n_images, dtype=T.int64, device="cuda")
+    psnr = T.zeros(n_images, dtype=T.float64, device="cuda")
+
+    def check(tag):
+        T.cuda.synchronize()
+        recs, s, p = b.unpack(out), sse.cpu().numpy(), psnr.cpu().numpy()
+        for i, (got, (wr, ws, wp)) in enumerate(zip(recs, want)):
+            assert np.array_equal(got, wr) and s[i] == ws, f"{tag}, image {i}"
+            assert (math.isinf(wp) and math.isinf(p[i])) or abs(p[i] - wp) <= 1e-3, f"{tag}, image {i}"
+
+    for rep in range(3):
+        sse.fill_(7)
+        psnr.fill_(0)
+        plan.compress_and_measure(b.dev, out, None, sse, psnr)
+        check(f"call {rep}")
+    g = plan.graph(b.dev, out, None, sse, psnr)
+    for rep in range(3):
+        sse.fill_(7)
+        psnr.fill_(0)
+        g.launch()
+        check(f"replay {rep}")
+        _ = (out.float().sum() + 1).item()  # eager work between replays
+    g.close()
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 10000])
 def test_one_d_api(n):
     """Whole 64-vector groups go through the LDS-regrouped path, the rest
