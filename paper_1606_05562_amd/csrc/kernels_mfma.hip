@@ -226,14 +226,17 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
   // block 8 ssxi + c.  Edge strips read inside the image: rows past the
   // height read the last row (its edge extension), and a block past the last
   // reads the row's first block (its result is neither stored nor counted).
-  auto lane_off = [&](const ImgGeom& dd, int ssy, int ssxi, int hh) {
+  // The offset is from the image's first pixel: the plan admits this kernel
+  // for images below 2^31 bytes with rows below 2^24 bytes, so one 24-bit
+  // multiply-add forms it, against a uniform 64-bit base.
+  auto lane_off = [&](const ImgGeom& dd, int ssy, int ssxi, int hh) -> unsigned {
     const int y = min(ssy * 16 + 8 * hh + r, dd.h - 1);
     const int blk = ssxi * kStripBlocks + c;
-    return dd.offset + (int64_t)y * dd.pitch + (blk < dd.bx ? 16 * blk : 0);
+    return __umul24((unsigned)y, (unsigned)dd.pitch) + (blk < dd.bx ? 16u * (unsigned)blk : 0u);
   };
   uint4 nr[2];
-  nr[0] = ld_row16<NT>(in + lane_off(d, sy, sxi, 0));
-  nr[1] = ld_row16<NT>(in + lane_off(d, sy, sxi, 1));
+  nr[0] = ld_row16<NT>(in + d.offset + lane_off(d, sy, sxi, 0));
+  nr[1] = ld_row16<NT>(in + d.offset + lane_off(d, sy, sxi, 1));
   // complete these loads here rather than at the loop head, where the wait
   // would also cover the previous strip's stores
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters unchanged
@@ -271,8 +274,8 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
     // the branches join
     auto prefetch = [&]() {
       if (more) {
-        nr[0] = ld_row16<NT>(in + lane_off(nd, nsy, nsxi, 0));
-        nr[1] = ld_row16<NT>(in + lane_off(nd, nsy, nsxi, 1));
+        nr[0] = ld_row16<NT>(in + nd.offset + lane_off(nd, nsy, nsxi, 0));
+        nr[1] = ld_row16<NT>(in + nd.offset + lane_off(nd, nsy, nsxi, 1));
       }
     };
     int* const prev_area = lds;
@@ -338,8 +341,8 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
       } else if constexpr (OUT == OUT_U8) {
         uint4 orow[2];
         operands_to_rows(lds, r, c, g, q, out, orow);
-        st_row16<NT>(outp + lane_off(d, sy, sxi, 0), orow[0]);
-        st_row16<NT>(outp + lane_off(d, sy, sxi, 1), orow[1]);
+        st_row16<NT>(outp + d.offset + lane_off(d, sy, sxi, 0), orow[0]);
+        st_row16<NT>(outp + d.offset + lane_off(d, sy, sxi, 1), orow[1]);
         // the prefetched rows were issued before these two stores: wait for
         // everything but the stores (vmcnt(2))
         __builtin_amdgcn_s_waitcnt(0x0F72);
