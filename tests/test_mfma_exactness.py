@@ -87,3 +87,22 @@ def test_int8_digits_reassemble():
     s1 = (v + 128) >> 8                # byte 1 of v + 128
     assert np.array_equal(256 * s1 + s0, v)
     assert s0.min() >= -128 and s0.max() <= 127 and s1.min() >= -128 and s1.max() <= 127
+
+
+def test_wave_sum_digits_recombine():
+    """The 64-bit wavefront sum adds the 24-, 24- and 16-bit digits of the 64
+    lane values separately (each digit sum below 2^30, so 32-bit adds do not
+    overflow) and recombines them: the result equals the plain sum modulo
+    2^64, for random values and for the extremes."""
+    rng = np.random.default_rng(64)
+    cases = [rng.integers(0, 2**63, size=64, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, size=64, dtype=np.uint64)
+             for _ in range(200)]
+    cases += [np.full(64, 2**64 - 1, dtype=np.uint64), np.zeros(64, dtype=np.uint64),
+              np.full(64, 2**24 - 1, dtype=np.uint64), np.full(64, 2**48 - 1, dtype=np.uint64)]
+    for v in cases:
+        vals = [int(x) for x in v]
+        d0 = sum(x & 0xFFFFFF for x in vals)
+        d1 = sum((x >> 24) & 0xFFFFFF for x in vals)
+        d2 = sum(x >> 48 for x in vals)
+        assert max(d0, d1, d2) < 2**32
+        assert (d0 + (d1 << 24) + (d2 << 48)) % 2**64 == sum(vals) % 2**64
