@@ -86,8 +86,10 @@ __device__ __forceinline__ unsigned sse4(unsigned a, unsigned r) {
 // dword g of row q of block b, 512 dwords per wave) turns this into the
 // operand layout (lane 16g + q: dword g of row q of every block) and back;
 // the b32 accesses touch 64 consecutive dwords, the b128 ones 2-way at most.
-__device__ __forceinline__ void rows_to_operands(int* lds, int r, int c, int g, int q, const uint4 (&rows)[2],
-                                                 unsigned (&x)[kStripBlocks]) {
+// The row half of the transpose: the strip's rows into LDS.  The kernel
+// calls it before issuing the next strip's loads, so that those loads can
+// take the registers the rows were in (no register copies per strip).
+__device__ __forceinline__ void rows_to_lds(int* lds, int r, int c, const uint4 (&rows)[2]) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int o = (8 * h + r) * kStripBlocks + c;
@@ -96,12 +98,22 @@ __device__ __forceinline__ void rows_to_operands(int* lds, int r, int c, int g, 
     lds[256 + o] = (int)rows[h].z;
     lds[384 + o] = (int)rows[h].w;
   }
+}
+
+// ... and the operand half, after rows_to_lds
+__device__ __forceinline__ void lds_to_operands(int* lds, int g, int q, unsigned (&x)[kStripBlocks]) {
   wave_lds_sync();
   const int4* p = reinterpret_cast<const int4*>(lds + g * 128 + q * kStripBlocks);
   const int4 a = p[0], b = p[1];
   x[0] = (unsigned)a.x; x[1] = (unsigned)a.y; x[2] = (unsigned)a.z; x[3] = (unsigned)a.w;
   x[4] = (unsigned)b.x; x[5] = (unsigned)b.y; x[6] = (unsigned)b.z; x[7] = (unsigned)b.w;
   wave_lds_sync();
+}
+
+__device__ __forceinline__ void rows_to_operands(int* lds, int r, int c, int g, int q, const uint4 (&rows)[2],
+                                                 unsigned (&x)[kStripBlocks]) {
+  rows_to_lds(lds, r, c, rows);
+  lds_to_operands(lds, g, q, x);
 }
 
 __device__ __forceinline__ void operands_to_rows(int* lds, int r, int c, int g, int q, const unsigned (&o)[kStripBlocks],
@@ -122,16 +134,8 @@ __device__ __forceinline__ void operands_to_rows(int* lds, int r, int c, int g, 
 // dword g of row q of block b (the layout of the rounded output, for the
 // error), and for lane groups g < 2 xi[b] = dwords 2g, 2g + 1 of row q (the
 // stage-1 operand; zero for g >= 2).
-__device__ __forceinline__ void rows_to_operands_i8x(int* lds, int r, int c, int g, int q, const uint4 (&rows)[2],
-                                                     unsigned (&x)[kStripBlocks], uint2 (&xi)[kStripBlocks]) {
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int o = (8 * h + r) * kStripBlocks + c;
-    lds[o] = (int)rows[h].x;
-    lds[128 + o] = (int)rows[h].y;
-    lds[256 + o] = (int)rows[h].z;
-    lds[384 + o] = (int)rows[h].w;
-  }
+__device__ __forceinline__ void lds_to_operands_i8x(int* lds, int g, int q, unsigned (&x)[kStripBlocks],
+                                                    uint2 (&xi)[kStripBlocks]) {
   wave_lds_sync();
   const int4* p = reinterpret_cast<const int4*>(lds + g * 128 + q * kStripBlocks);
   const int4 a = p[0], b = p[1];
@@ -165,19 +169,18 @@ struct RoundTrip {
 #pragma unroll
     for (int v = 0; v < 4; ++v) keepz[v] = tb->wkeep[(4 * g + v) * 16 + q] != 0;
   }
-  // rows (the strip's 8 rows x 128 bytes per half, see rows_to_operands) ->
-  // x (input pixels) and out (rounded reconstruction), dword g of row q of
-  // each block
-  __device__ __forceinline__ void run(int* lds, int r, int c, int g, int q, const uint4 (&rows)[2],
-                                      unsigned (&x)[kStripBlocks], unsigned (&out)[kStripBlocks]) const {
+  // the strip's rows (written to LDS by rows_to_lds) -> x (input pixels)
+  // and out (rounded reconstruction), dword g of row q of each block
+  __device__ __forceinline__ void run(int* lds, int g, int q, unsigned (&x)[kStripBlocks],
+                                      unsigned (&out)[kStripBlocks]) const {
     if constexpr (I8) {
       uint2 xi[kStripBlocks];
-      rows_to_operands_i8x(lds, r, c, g, q, rows, x, xi);
+      lds_to_operands_i8x(lds, g, q, x, xi);
       constexpr int NB = ADCT16_MFMA_BATCH;
 #pragma unroll
       for (int b0 = 0; b0 < kStripBlocks; b0 += NB) collapsed_blocks_i8<NB>(&xi[b0], &out[b0], k);
     } else {
-      rows_to_operands(lds, r, c, g, q, rows, x);
+      lds_to_operands(lds, g, q, x);
       roundtrip8<ZIGZAG, COLLAPSE>(x, out, k, keepz);
     }
   }
@@ -281,9 +284,10 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
     int* const prev_area = lds;
     if constexpr (REALIGN) lds = lds_w + 512 * (lds == lds_w ? 1 : 0);  // this strip's area
     if (interior(d, sy, sxi)) {
+      rows_to_lds(lds, r, c, cr);
       prefetch();
       unsigned x[kStripBlocks], out[kStripBlocks];
-      rt.run(lds, r, c, g, q, cr, x, out);
+      rt.run(lds, g, q, x, out);
       if constexpr (REALIGN) {
         // Rows that are not whole cache lines: a strip's 128-byte row piece
         // straddles two lines, and storing the pieces as they lie leaves
@@ -362,7 +366,6 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
       // past the height.  The rows were loaded as for interior strips; the
       // partial block's row is extended by its last pixel, and only pixels
       // inside the image are stored and counted.
-      prefetch();
       const int blk = sxi * kStripBlocks + c;
       const int nvalid = d.w - 16 * blk;  // pixels of this lane's block row inside the image
       uint4 er[2] = {cr[0], cr[1]};
@@ -370,8 +373,10 @@ __global__ __launch_bounds__(kGroupThreads, ADCT16_MFMA_MIN_WG) void k_mfma_fuse
         er[0] = extend_bytes(er[0], nvalid);
         er[1] = extend_bytes(er[1], nvalid);
       }
+      rows_to_lds(lds, r, c, er);
+      prefetch();
       unsigned x[kStripBlocks], out[kStripBlocks];
-      rt.run(lds, r, c, g, q, er, x, out);
+      rt.run(lds, g, q, x, out);
       if constexpr (OUT == OUT_U8) {
         uint4 orow[2];
         operands_to_rows(lds, r, c, g, q, out, orow);
